@@ -1,0 +1,232 @@
+"""Benchmark of the TVS proton-CT hot path on one MI355X.
+
+A step is one TVS cycle of NTVS (arXiv 1803.01112, Appendix C): N
+perturbation steps followed by one DROP feasibility sweep over every
+history, whose rows (MLP + voxel walk) are formed on the fly inside the
+sweep.  The metric is histories processed per second per cycle.
+
+Default workload: 200x200x16 voxels of 1x1x2.5 mm, a 150 mm cylinder
+phantom with six inserts, 20M synthetic histories at 180 angles, DROP
+blocks of 3200 histories, lambda = 1e-4, N = 5, alpha = 0.75, TV check off.
+Inputs are generated (seeded), copied to HBM, and loaded before the timed
+region starts.
+
+Prints one JSON line.  Only one GPU is supported: --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# float64 operations of one MLP vertex and its segment walk, counted on the
+# algorithm as implemented (moments, 2x2 conditioning, position, Siddon walk)
+FP64_FLOPS_PER_VERTEX = 320.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def row_stream_bytes(n_hist, nnz, chord_bytes):
+    """Algorithmic HBM bytes of one DROP pass over n_hist rows holding nnz entries:
+    per row an int64 offset, float32 ||a||^2 and float32 WEPL (16 B); per entry an
+    int32 voxel index and a chord of chord_bytes."""
+    return 16.0 * n_hist + (4.0 + chord_bytes) * nnz
+
+
+def mlp_vertices(h, step):
+    u = np.stack([h["ux"], h["uy"]]).astype(np.float64)
+    u /= np.hypot(u[0], u[1])
+    L = (h["qx"] - h["ex"]) * u[0] + (h["qy"] - h["ey"]) * u[1]
+    J = np.maximum(np.ceil(L / step), 1.0)
+    return float(np.sum(np.where(L > 0, J - 1, 0)))
+
+
+def run_form(tvs, torch, w, dev_hist, x0, args, path_mode, K, W):
+    ctx = tvs.Context(w.grid, block_size=args.block, path_mode=path_mode)
+    t0 = time.perf_counter()
+    ctx.load_histories(dev_hist)
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t0
+    ctx.set_image(x0)
+    kw = dict(lam=args.lam, N=args.N, alpha=args.alpha, tv_check=args.check, seed=args.seed)
+    if W > 0:
+        ctx.iterate(W, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.iterate(K, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ctx.stats()
+    return ctx, st, dt, load_s
+
+
+def cpu_baseline(w, args, cores):
+    """The oracle (plain float64 CPU code) on a bounded prefix of the same scan:
+    rows formed (MLP + walk, OpenMP over histories) and one cycle per repeat."""
+    import oracle
+    n = args.cpu_sample
+    h = w.histories(count=n)
+    x0 = w.initial_image()
+    t0 = time.perf_counter()
+    reps = 0
+    S = None
+    while True:
+        rows = oracle.build_rows(w.grid, h, min(w.grid.vx, w.grid.vy))
+        if S is None:
+            S = oracle.Superiorizer(w.grid, rows, x0, args.block)
+        else:
+            S.rows = rows
+        S.iterate(1, args.lam, args.N, args.alpha, tv_check=args.check, seed=args.seed)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > args.cpu_seconds or reps >= 20:
+            break
+    return dict(value=n * reps / el, unit="histories/s", cores=cores, kind="oracle",
+                sample=f"first {n} histories of the {w.name} scan ({w.n_hist}), {reps} cycle(s) "
+                       f"each re-forming rows (MLP+walk, OpenMP {cores} threads) then "
+                       f"N={args.N} TV steps and one DROP sweep (single thread); {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="vol200")
+    ap.add_argument("--n-hist", type=int, default=None)
+    ap.add_argument("--block", type=int, default=3200)
+    ap.add_argument("--lam", type=float, default=1e-4)
+    ap.add_argument("--N", type=int, default=5)
+    ap.add_argument("--alpha", type=float, default=0.75)
+    ap.add_argument("--check", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=1803011121)
+    ap.add_argument("--path-mode", default="otf")
+    ap.add_argument("--forms", default="f32,f16", help="extra path-store forms to time")
+    ap.add_argument("--latency-cycles", type=int, default=6)
+    ap.add_argument("--cpu-sample", type=int, default=400_000)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1803_01112_amd import synth, tvs
+
+    tvs.load_library()
+    w = synth.workload(args.workload, n_hist=args.n_hist)
+    log(f"generating {w.n_hist} histories of {w.name}")
+    t0 = time.perf_counter()
+    h = w.histories()
+    log(f"generated in {time.perf_counter() - t0:.1f} s; copying to HBM")
+    dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in h.items()}
+    x0 = torch.from_numpy(w.initial_image()).to("cuda:0")
+    torch.cuda.synchronize()
+    step_mm = min(w.grid.vx, w.grid.vy)
+    vertices = mlp_vertices(h, step_mm)
+    del h
+
+    log(f"timing {args.path_mode}: warmup {args.warmup}, steps {args.steps}")
+    ctx, st, dt, load_s = run_form(tvs, torch, w, dev, x0, args, args.path_mode, args.steps,
+                                   args.warmup)
+    H = w.n_hist
+    value = H * args.steps / dt
+    ms_per_step = 1e3 * dt / args.steps
+    log(f"{args.path_mode}: {value:.4g} histories/s, {ms_per_step:.2f} ms/cycle; stats {st}")
+
+    # per-cycle latency (each cycle synchronised on its own)
+    lat = []
+    for _ in range(args.latency_cycles):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.iterate(1, args.lam, args.N, args.alpha, tv_check=args.check, seed=args.seed)
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - t0))
+    ctx.close()
+
+    # dominant kernel of the timed region
+    drop_ms = st["drop_ms_total"] / max(st["drop_launches"], 1)
+    rows_ms = st["rows_ms_total"] / max(st["rows_launches"], 1)
+    nnz = st["nnz"]
+    if st["rows_ms_total"] > st["drop_ms_total"]:
+        flops_sweep = FP64_FLOPS_PER_VERTEX * vertices
+        per_launch = flops_sweep / max(st["rows_launches"] / max(st["cycles_timed"], 1), 1)
+        achieved = per_launch / (rows_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", kernel="k_rows_fill (float64 MLP + walk)", achieved=achieved,
+                    peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS,
+                    traffic=None, avg_launch_ms=rows_ms)
+    else:
+        chord_b = {"otf": 4, "f32": 4, "f16": 2}[args.path_mode]
+        launches_per_sweep = max(st["drop_launches"] / max(st["cycles_timed"], 1), 1)
+        per_launch = row_stream_bytes(H, nnz, chord_b) / launches_per_sweep
+        achieved = per_launch / (drop_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", kernel="k_drop_persistent", achieved=achieved,
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
+                    avg_launch_ms=drop_ms)
+
+    forms = {}
+    for form in [f for f in args.forms.split(",") if f]:
+        log(f"timing form {form}")
+        c2, s2, d2, l2 = run_form(tvs, torch, w, dev, x0, args, form, args.steps, 1)
+        dms = s2["drop_ms_total"] / max(s2["drop_launches"], 1)
+        cb = 2 if form == "f16" else 4
+        gbs = row_stream_bytes(H, s2["nnz"], cb) / (dms * 1e-3) / 1e9
+        forms[form] = dict(value=H * args.steps / d2, ms_per_step=1e3 * d2 / args.steps,
+                           drop_ms=dms, drop_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+                           store_build_s=l2)
+        c2.close()
+        log(f"{form}: {forms[form]}")
+
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cpu = None if args.no_cpu else cpu_baseline(w, args, cores)
+
+    out = {
+        "metric": "proton histories/s per TVS iteration (MLP+DROP+TV)",
+        "value": value,
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.grid.nx}x{w.grid.ny}x{w.grid.nz} voxels of "
+                               f"{w.grid.vx}x{w.grid.vy}x{w.grid.vz} mm, {w.diameter:.0f} mm "
+                               f"cylinder with 6 inserts, {H} histories at {w.n_angles} angles",
+                   "block_size": args.block, "lambda": args.lam, "N": args.N,
+                   "alpha": args.alpha, "tv_check": bool(args.check),
+                   "path_mode": args.path_mode, "nnz": nnz, "parallelism": "1 GPU"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "cycles": len(lat)},
+        "phases_ms_per_cycle": {"tv": st["tv_ms_total"] / max(st["cycles_timed"], 1),
+                                "sweep": st["sweep_ms_total"] / max(st["cycles_timed"], 1),
+                                "rows": st["rows_ms_total"] / max(st["cycles_timed"], 1),
+                                "drop": st["drop_ms_total"] / max(st["cycles_timed"], 1)},
+        "load_s": load_s,
+        "roofline": roof,
+        "forms": forms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * tvs.h -- C ABI of the MI355X (gfx950) hot path of total-variation-
+ * superiorized (TVS) proton-CT reconstruction, after Schultze, Censor,
+ * Karbasi, Schubert and Schulte, "An Improved Method of Total Variation
+ * Superiorization Applied to Reconstruction in Proton Computed Tomography"
+ * (arXiv 1803.01112).
+ *
+ * The problem (Section I): every proton history gives one linear equation
+ * whose left side is the sum, over the voxels its most likely path (MLP)
+ * crosses, of the chord length in the voxel times the voxel's unknown
+ * relative stopping power (RSP), and whose right side is its measured
+ * water-equivalent path length (WEPL).  Each cycle k of NTVS (Appendix C)
+ * applies N perturbation steps x += beta * v, v = -grad TV / ||grad TV||,
+ * beta = alpha^ell, optionally checking that TV does not increase, and then
+ * one feasibility-seeking sweep P_T: block-iterative DROP with relaxation
+ * lambda over blocks of B histories (Section III-D).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns a status (TVS_OK or a negative TVS_E* code); no
+ *     exception or signal crosses the ABI.  tvs_last_error(ctx) gives a
+ *     human-readable reason for the last failure on that context.
+ *   - Pointers marked "host or device" are read as device pointers when the
+ *     accompanying on_device flag is 1 (e.g. torch.Tensor.data_ptr() of a
+ *     CUDA tensor), else as host pointers.  Input arrays are borrowed for the
+ *     duration of the call only: the library copies what it keeps.
+ *   - `stream` is a hipStream_t (NULL: the context's own stream).  Work is
+ *     enqueued on it; a call that returns data in host memory waits for it.
+ *   - Lengths are in mm; images are float32 RSP, nx*ny*nz values, x fastest
+ *     (index ix + nx*(iy + ny*iz)).
+ *   - One context must not be used by two threads at once; distinct
+ *     contexts are independent (each owns all of its device memory).
+ */
+#ifndef TVS_H
+#define TVS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tvs_ctx tvs_ctx;
+
+enum tvs_status {
+    TVS_OK = 0,
+    TVS_EINVAL = -1,   /* invalid argument (NaN/inf input, bad grid or parameter) */
+    TVS_ENOMEM = -2,   /* footprint exceeds the HBM budget or free device memory */
+    TVS_EDEVICE = -3,  /* HIP runtime error */
+    TVS_ESTATE = -4,   /* call out of order (e.g. iterate before load) */
+    TVS_ERANGE = -5    /* an index or size outside what the context holds */
+};
+
+/* Voxel grid: nx*ny*nz voxels of vx*vy*vz mm; (ox,oy,oz) is the corner of
+ * voxel (0,0,0) (Section III-D uses 200x200 voxels of 1.0x1.0x2.5 mm per
+ * 20 slices). */
+typedef struct {
+    int32_t nx, ny, nz;
+    double vx, vy, vz;
+    double ox, oy, oz;
+} tvs_grid;
+
+/* How the rows of the system are formed during a sweep. */
+enum tvs_path_mode {
+    TVS_PATH_ON_THE_FLY = 0, /* MLP walked for every history on every sweep */
+    TVS_PATH_STORE_F32 = 1,  /* rows formed once: int32 voxel index + float32 chord */
+    TVS_PATH_STORE_F16 = 2   /* rows formed once: int32 voxel index + float16 chord */
+};
+
+typedef struct {
+    int32_t block_size;      /* B, histories per DROP block (Section III-D: 3200); >= 1 */
+    int32_t path_mode;       /* enum tvs_path_mode */
+    double mlp_step_mm;      /* depth spacing of MLP vertices; <= 0: min(vx, vy) */
+    int32_t mlp_log_term;    /* 1: Highland logarithmic correction in the MLP moments */
+    int32_t mlp_const_power; /* 1: constant scattering power (test mode) */
+    int64_t chunk_histories; /* on-the-fly: histories whose rows are formed together; 0: auto */
+    uint64_t hbm_budget_bytes; /* 0: 80 % of the device memory free at tvs_create */
+    int32_t device;          /* HIP device ordinal */
+    int32_t max_tries;       /* bound on the retries of one checked TV step; 0: 100000 */
+    int32_t sweep_kernel;    /* 0: auto; 1: one launch per block phase; 2: persistent */
+    int32_t wave_rows;       /* lanes per row in the DROP row kernels (8..64); 0: auto */
+} tvs_config;
+
+/* Fills *cfg with the defaults above (B = 3200, on-the-fly rows, log term on). */
+void tvs_config_default(tvs_config *cfg);
+
+/* Proton histories as structure-of-arrays float32 streams of equal length
+ * (Section I: entry/exit positions and directions, and WEPL):
+ *   ex,ey,ez / qx,qy,qz : entry / exit position on the object hull, mm;
+ *   eth,eps / qth,qps   : entry / exit slopes dt/du and dv/du, where u is
+ *                         the beam (depth) axis, t = (-uy, ux, 0) the
+ *                         in-plane lateral axis and v = z;
+ *   ux,uy               : beam axis in the x-y plane (normalised internally);
+ *   wepl                : measured WEPL, mm. */
+typedef struct {
+    const float *ex, *ey, *ez, *qx, *qy, *qz;
+    const float *eth, *eps, *qth, *qps;
+    const float *ux, *uy;
+    const float *wepl;
+} tvs_histories;
+
+enum tvs_variant {
+    TVS_NTVS = 0,      /* Appendix C: ell_k = rand(k, ell_{k-1}); N steps of beta = alpha^ell */
+    TVS_OTVS = 1,      /* Appendix B: one checked step per cycle, beta = (1/2)^ell */
+    TVS_DECOUPLED = 2  /* Section VI proposal: beta_{k,n} = alpha^n gamma^k, n = 1..N */
+};
+
+/* Reconstruction parameters (Section III-E). */
+typedef struct {
+    double lambda;     /* DROP relaxation, > 0 */
+    int32_t N;         /* TV perturbation steps per cycle, >= 0 */
+    double alpha;      /* perturbation kernel, 0 < alpha < 1 */
+    int32_t tv_check;  /* NTVS: 1 = keep the TV-reduction check, 0 = exclude it */
+    int32_t variant;   /* enum tvs_variant */
+    double tv_eps;     /* TV smoothing: m = sqrt(dx^2 + dy^2 + eps^2), phi = sum (m - eps); >= 0 */
+    uint64_t seed;     /* seed of the SplitMix64 stream that draws ell_k */
+    double gamma;      /* TVS_DECOUPLED only, 0 < gamma < 1 */
+} tvs_params;
+
+typedef struct {
+    int64_t k;           /* cycles completed since the image was set */
+    int64_t ell;         /* current exponent ell */
+    int64_t n_hist;      /* histories loaded */
+    int64_t n_skipped;   /* histories forming no row (exit not beyond entry, or empty row) */
+    int64_t nnz;         /* row entries over all histories (0 until rows were formed) */
+    int64_t steps;       /* perturbation steps taken (records in the step log) */
+    int64_t tries;       /* TV-check tries in total */
+    int64_t max_row_nnz; /* longest row */
+    /* Device times from HIP events recorded on the launch stream during the
+     * last tvs_iterate call (reading them waits for that work). */
+    double last_sweep_ms;  /* last cycle's sweep P_T */
+    double last_tv_ms;     /* last cycle's perturbation steps */
+    double last_rows_ms;   /* row formation inside the last sweep (on-the-fly rows) */
+    uint64_t device_bytes; /* device memory held by the context */
+    double tv_ms_total;    /* all perturbation steps of the call */
+    double sweep_ms_total; /* all sweeps of the call */
+    double rows_ms_total;  /* all row-formation launches of the call */
+    double drop_ms_total;  /* all DROP launches of the call */
+    int64_t cycles_timed;  /* cycles of the call */
+    int64_t rows_launches; /* row-formation launches of the call */
+    int64_t drop_launches; /* DROP launches (persistent) or per-block launch pairs' spans */
+} tvs_stats;
+
+/* One record per perturbation step (Appendix C; checked steps record TV). */
+typedef struct {
+    int32_t k, n;
+    int32_t tries;       /* tries until accepted (1 for unchecked steps) */
+    int32_t accepted;    /* 0: the step gave up after max_tries, image unchanged */
+    int64_t ell_start;   /* ell at the first try */
+    double phi_x;        /* TV before the step (checked steps) */
+    double phi_z;        /* TV of the accepted image (checked steps) */
+    double gnorm;        /* ||grad TV|| */
+} tvs_step_log;
+
+/* Creates a context on cfg->device for the given grid.  Validates the grid
+ * (positive sizes and spacings, finite origin, nx*ny*nz < 2^31) and the
+ * configuration.  *out receives the context (NULL on failure). */
+int tvs_create(const tvs_grid *grid, const tvs_config *cfg, tvs_ctx **out);
+
+/* Frees every device buffer of ctx; NULL is accepted. */
+void tvs_destroy(tvs_ctx *ctx);
+
+/* Loads n proton histories (host or device arrays, see tvs_histories),
+ * replacing any loaded before.  Rejects NaN/inf values and zero beam axes
+ * with TVS_EINVAL, a footprint beyond the HBM budget with TVS_ENOMEM; on
+ * failure nothing stays loaded.  A history whose exit is not deeper than
+ * its entry along the beam axis, or whose path misses the grid, forms no
+ * row: it is counted in n_skipped, not rejected.  With a path store the
+ * rows (MLP + voxel walk, Section I) are formed here, once.  Resets the
+ * image to zero and the cycle state to k = 0, ell = 0. */
+int tvs_load_histories(tvs_ctx *ctx, int64_t n, const tvs_histories *h, int on_device,
+                       void *stream);
+
+/* Sets the initial iterate x-bar (Appendix A) from nx*ny*nz floats (host or
+ * device) and resets the cycle state (k = 0, ell = 0, RNG unseeded). */
+int tvs_set_image(tvs_ctx *ctx, const float *x0, int on_device, void *stream);
+
+/* Runs K more cycles (Appendix C / B, or the Section VI schedule) from the
+ * current state.  The first cycle after tvs_set_image / tvs_load_histories
+ * seeds the RNG from p->seed; later calls continue the same stream, so K
+ * cycles in one call equal the same K cycles split over several calls.
+ * TVS_EINVAL for lambda <= 0, alpha outside (0,1), N < 0, tv_eps < 0;
+ * TVS_ESTATE before tvs_load_histories. */
+int tvs_iterate(tvs_ctx *ctx, const tvs_params *p, int32_t K, void *stream);
+
+/* Copies the current image (nx*ny*nz floats) to out (host or device). */
+int tvs_get_image(tvs_ctx *ctx, float *out, int on_device, void *stream);
+
+/* Counters and timings of the context. */
+int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out);
+
+/* Copies up to cap step records (oldest first) to out; *n receives the number
+ * of records held.  The log is cleared by tvs_set_image / tvs_load_histories. */
+int tvs_get_step_log(tvs_ctx *ctx, tvs_step_log *out, int64_t cap, int64_t *n);
+
+/* Exports the rows of histories [first, first+count) for inspection: row
+ * lengths (row_nnz[count]), voxel indices and chords concatenated in history
+ * order (at most cap entries), and ||a||^2 (norm2[count]); all host arrays.
+ * Rows are formed by the same kernels the sweep uses.  TVS_ERANGE when
+ * [first, first+count) is outside the loaded histories or cap is too small
+ * (row_nnz is still filled then). */
+int tvs_debug_rows(tvs_ctx *ctx, int64_t first, int64_t count, int64_t *row_nnz, int32_t *idx,
+                   float *chord, float *norm2, int64_t cap);
+
+/* Static description of a status code. */
+const char *tvs_strerror(int status);
+
+/* Message of the last failure on ctx ("" if none); valid until the next call. */
+const char *tvs_last_error(tvs_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TVS_H */

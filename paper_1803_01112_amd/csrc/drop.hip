@@ -1,0 +1,285 @@
+// drop.hip -- the feasibility-seeking sweep P_T on gfx950: block-iterative
+// DROP (diagonally relaxed orthogonal projections) over blocks of B
+// consecutive histories (arXiv 1803.01112, Section III-D; P_T in Appendix A).
+//
+// For block t, from one image x:
+//   r_i = (b_i - a_i . x) / ||a_i||^2          every row i of the block
+//   c_j = sum_i r_i a_ij,  s_j = #entries at j  (scatter)
+//   x_j += lambda c_j / s_j                     where s_j > 0 (apply)
+// Blocks are applied one after another.
+//
+// Rows are read from a CSR row set (int32 voxel index + float32 or float16
+// chord).  A group of LPR lanes (a wavefront for LPR = 64) reads one row
+// coalesced, gathers x (float64), reduces the dot product in float64 with
+// cross-lane shuffles,
+// and scatters r a_ij / 1 with hardware float / integer atomics.  The first
+// hit of a voxel in a block appends it to a touched list (one atomic per
+// wavefront), so the apply phase visits only touched voxels and clears them.
+//
+// Two forms: one launch per phase (rows, apply), or one persistent launch
+// per sweep with a device-wide barrier between phases.  The barrier spins a
+// bounded number of times; on timeout it raises an error flag that makes
+// every workgroup leave, and the host reports a device error.
+#include "tvs_internal.hpp"
+
+namespace tvs {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+template <typename CH>
+__device__ inline float chord_at(const CH *p, int64_t e)
+{
+    if constexpr (sizeof(CH) == 4) return p[e];
+    else return __half2float(p[e]);
+}
+
+template <int LPR>
+__device__ inline double group_sum(double v)
+{
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Appends j to the touched list when `first` (wavefront-aggregated).
+__device__ inline void append_touched(bool first, int32_t j, int32_t *touched, uint32_t *cnt)
+{
+    unsigned long long m = __ballot(first);
+    if (m == 0) return;
+    int lane = threadIdx.x & 63;
+    int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    if (first) {
+        unsigned long long below = m & ((1ull << lane) - 1ull);
+        touched[base + (uint32_t)__popcll(below)] = j;
+    }
+}
+
+// One row: dot, residual, scatter.  All LPR lanes of the group call it.
+template <int LPR, typename CH>
+__device__ inline void drop_row(const RowSet &rs, const CH *chord, const float *wepl, int64_t row,
+                                const double *x, float *c, uint32_t *s, int32_t *touched,
+                                uint32_t *cnt)
+{
+    const int lane = threadIdx.x & (LPR - 1);
+    const int64_t lr = row - rs.first;
+    const float n2 = rs.norm2[lr];
+    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
+    double acc = 0.0;
+    if (n2 > 0.0f)
+        for (int64_t e = off + lane; e < end; e += LPR)
+            acc += (double)chord_at(chord, e) * x[rs.idx[e]];
+    acc = group_sum<LPR>(acc);
+    const float r = (n2 > 0.0f) ? (float)(((double)wepl[row] - acc) / (double)n2) : 0.0f;
+    const int64_t trips = (n2 > 0.0f) ? (end - off + LPR - 1) / LPR : 0;
+    // Uniform trip count inside the group so the wavefront-wide ballot sees
+    // every lane of the group.
+    for (int64_t q = 0; q < trips; q++) {
+        int64_t e = off + q * LPR + lane;
+        bool first = false;
+        int32_t j = 0;
+        if (e < end) {
+            j = rs.idx[e];
+            unsafeAtomicAdd(c + j, r * chord_at(chord, e));
+            first = (atomicAdd(s + j, 1u) == 0u);
+        }
+        append_touched(first, j, touched, cnt);
+    }
+}
+
+template <int LPR, typename CH>
+__global__ void __launch_bounds__(kThreads)
+k_drop_rows(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1, const double *x,
+            float *c, uint32_t *s, int32_t *touched, uint32_t *cnt)
+{
+    const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
+    if (row >= r1) return;   // groups never straddle a wavefront boundary
+    drop_row<LPR, CH>(rs, chord, wepl, row, x, c, s, touched, cnt);
+}
+
+__device__ inline void apply_voxel(int32_t j, double lambda, double *x, float *c, uint32_t *s)
+{
+    float cj = c[j];
+    uint32_t sj = s[j];
+    x[j] += lambda * (double)cj / (double)sj;
+    c[j] = 0.0f;
+    s[j] = 0u;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_drop_apply(double lambda, double *x, float *c, uint32_t *s, const int32_t *touched,
+             const uint32_t *cnt, uint32_t *cnt_next)
+{
+    const uint32_t n = *cnt;
+    for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
+        apply_voxel(touched[i], lambda, x, c, s);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_next = 0u;
+}
+
+__global__ void k_zero_counters(uint32_t *cnt)
+{
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0u;
+}
+
+// Sense-free grid barrier: bar[0] = arrivals, bar[1] = generation,
+// bar[2] = error flag.  The last arriving workgroup resets the count and
+// bumps the generation; the others wait for the generation to change.
+__device__ inline bool grid_barrier(uint32_t *bar)
+{
+    __shared__ uint32_t ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t good = 1;
+        __threadfence();
+        uint32_t gen = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (arrived == gridDim.x) {
+            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    good = 0;
+                    break;
+                }
+                if (++spins > kSpinLimit) {
+                    __hip_atomic_store(bar + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    good = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __threadfence();
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0u;
+}
+
+template <int LPR, typename CH>
+__global__ void __launch_bounds__(kThreads)
+k_drop_persistent(RowSet rs, const CH *chord, const float *wepl, int64_t block_size, double lambda,
+                  double *x, float *c, uint32_t *s, int32_t *touched, uint32_t *cnt, uint32_t *bar)
+{
+    const int64_t groups = (int64_t)gridDim.x * (kThreads / LPR);
+    const int64_t gid = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
+    const int64_t gthreads = (int64_t)gridDim.x * kThreads;
+    const int64_t gtid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t nblocks = (rs.n + block_size - 1) / block_size;
+    for (int64_t t = 0; t < nblocks; t++) {
+        const int64_t r0 = rs.first + t * block_size;
+        const int64_t r1 = (r0 + block_size < rs.first + rs.n) ? r0 + block_size : rs.first + rs.n;
+        uint32_t *cur = cnt + (t & 1);
+        for (int64_t row = r0 + gid; row < r1; row += groups)
+            drop_row<LPR, CH>(rs, chord, wepl, row, x, c, s, touched, cur);
+        if (!grid_barrier(bar)) return;
+        const uint32_t n = *cur;
+        for (int64_t i = gtid; i < (int64_t)n; i += gthreads) apply_voxel(touched[i], lambda, x, c, s);
+        if (gtid == 0) cnt[(t + 1) & 1] = 0u;
+        if (!grid_barrier(bar)) return;
+    }
+    if (gtid == 0) {
+        cnt[0] = 0u;
+        cnt[1] = 0u;
+    }
+}
+
+template <int LPR>
+hipError_t block_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1, double lambda,
+                        const DropBuffers &b, int parity, hipStream_t stream)
+{
+    const int64_t rows = r1 - r0;
+    if (rows <= 0) return hipSuccess;
+    dim3 grid((unsigned)((rows * LPR + kThreads - 1) / kThreads));
+    uint32_t *cur = b.ntouched + (parity & 1), *nxt = b.ntouched + ((parity + 1) & 1);
+    if (rs.chord16)
+        hipLaunchKernelGGL((k_drop_rows<LPR, __half>), grid, dim3(kThreads), 0, stream, rs,
+                           rs.chord16, wepl, r0, r1, b.x, b.c, b.s, b.touched, cur);
+    else
+        hipLaunchKernelGGL((k_drop_rows<LPR, float>), grid, dim3(kThreads), 0, stream, rs,
+                           rs.chord32, wepl, r0, r1, b.x, b.c, b.s, b.touched, cur);
+    hipLaunchKernelGGL(k_drop_apply, dim3(1024), dim3(kThreads), 0, stream, lambda, b.x,
+                       b.c, b.s, b.touched, cur, nxt);
+    return hipGetLastError();
+}
+
+template <int LPR>
+hipError_t persistent_launch(const RowSet &rs, const float *wepl, int64_t block_size,
+                             double lambda, const DropBuffers &b, int grid_wgs, hipStream_t stream)
+{
+    if (rs.n <= 0) return hipSuccess;
+    if (rs.chord16)
+        hipLaunchKernelGGL((k_drop_persistent<LPR, __half>), dim3(grid_wgs), dim3(kThreads), 0,
+                           stream, rs, rs.chord16, wepl, block_size, lambda, b.x, b.c, b.s,
+                           b.touched, b.ntouched, b.barrier);
+    else
+        hipLaunchKernelGGL((k_drop_persistent<LPR, float>), dim3(grid_wgs), dim3(kThreads), 0,
+                           stream, rs, rs.chord32, wepl, block_size, lambda, b.x, b.c, b.s,
+                           b.touched, b.ntouched, b.barrier);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_drop_block(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
+                             double lambda, const DropBuffers &b, int parity, int lanes_per_row,
+                             hipStream_t stream)
+{
+    switch (lanes_per_row) {
+    case 16: return block_launch<16>(rs, wepl, r0, r1, lambda, b, parity, stream);
+    case 32: return block_launch<32>(rs, wepl, r0, r1, lambda, b, parity, stream);
+    default: return block_launch<64>(rs, wepl, r0, r1, lambda, b, parity, stream);
+    }
+}
+
+hipError_t launch_zero_counters(uint32_t *cnt, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_drop_persistent(const RowSet &rs, const float *wepl, int64_t block_size,
+                                  double lambda, const DropBuffers &b, int lanes_per_row,
+                                  int grid_wgs, hipStream_t stream)
+{
+    switch (lanes_per_row) {
+    case 16: return persistent_launch<16>(rs, wepl, block_size, lambda, b, grid_wgs, stream);
+    case 32: return persistent_launch<32>(rs, wepl, block_size, lambda, b, grid_wgs, stream);
+    default: return persistent_launch<64>(rs, wepl, block_size, lambda, b, grid_wgs, stream);
+    }
+}
+
+int persistent_grid_size(int device, int lanes_per_row)
+{
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    hipError_t e;
+    switch (lanes_per_row) {
+    case 16:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(k_drop_persistent<16, float>), kThreads, 0);
+        break;
+    case 32:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(k_drop_persistent<32, float>), kThreads, 0);
+        break;
+    default:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(k_drop_persistent<64, float>), kThreads, 0);
+        break;
+    }
+    if (e != hipSuccess || per_cu <= 0) return 0;
+    // Stay well inside co-residency: at most 2 workgroups per CU.
+    if (per_cu > 2) per_cu = 2;
+    return cus * per_cu;
+}
+
+}  // namespace tvs

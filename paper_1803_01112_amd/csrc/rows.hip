@@ -1,0 +1,458 @@
+// rows.hip -- formation of the rows of the pCT linear system on gfx950.
+//
+// Each proton history gives one equation: the chord lengths of its most
+// likely path (MLP) through the voxels, times the voxel RSPs, sum to its
+// WEPL (arXiv 1803.01112, Section I).  One lane forms one row:
+//   1. the MLP vertices at depths j*step along the beam axis, from the
+//      Fermi-Eyges / Highland scattering moments of the entry->vertex and
+//      vertex->exit slabs and the 2x2 Gaussian conditioning of the lateral
+//      (t, dt/du) and vertical (v, dv/du) states on the entry and exit
+//      measurements, all in float64;
+//   2. a Siddon parametric walk of every polyline segment (crossings of the
+//      integer grid planes merged in order, voxel of a piece taken at its
+//      midpoint), merging consecutive pieces in the same voxel.
+// Decisions that pick voxel indices are taken in float64; chords are
+// rounded to float32 (or float16) only when written.  This file must be
+// compiled with -ffp-contract=off so that no multiply-add is fused.
+#include "tvs_internal.hpp"
+
+namespace tvs {
+namespace {
+
+constexpr double kE0 = 13.6;     // MeV, Highland constant
+constexpr double kX0 = 360.8;    // mm, radiation length of water
+constexpr int kThreads = 256;
+
+__device__ inline double ipow(double base, int e)
+{
+    double r = 1.0;
+    for (int i = 0; i < e; i++) r *= base;
+    return r;
+}
+
+__device__ constexpr double fact(int n) { return n <= 1 ? 1.0 : (double)n * fact(n - 1); }
+
+__device__ inline double highland(double depth, int log_term)
+{
+    double f = 1.0;
+    if (log_term) f = 1.0 + 0.038 * log(depth / kX0);
+    return kE0 * kE0 * f * f / kX0;
+}
+
+// 1/(beta^2 p^2) of a 200 MeV proton in water, per mm^k.
+__device__ inline void power_coefs(int const_power, double b[6])
+{
+    b[0] = 7.457e-6;
+    b[1] = 4.548e-8;
+    b[2] = -5.777e-10;
+    b[3] = 1.301e-11;
+    b[4] = -9.228e-14;
+    b[5] = 2.687e-16;
+    if (const_power) b[1] = b[2] = b[3] = b[4] = b[5] = 0.0;
+}
+
+struct M2 { double a, b, c, d; };   // [[a, b], [c, d]]
+
+__device__ inline M2 mul(const M2 &A, const M2 &B)
+{
+    return {A.a * B.a + A.b * B.c, A.a * B.b + A.b * B.d,
+            A.c * B.a + A.d * B.c, A.c * B.b + A.d * B.d};
+}
+__device__ inline M2 inv(const M2 &A)
+{
+    double det = A.a * A.d - A.b * A.c;
+    return {A.d / det, -A.b / det, -A.c / det, A.a / det};
+}
+__device__ inline void mvec(const M2 &A, double x0, double x1, double &y0, double &y1)
+{
+    double r0 = A.a * x0 + A.b * x1;
+    double r1 = A.c * x0 + A.d * x1;
+    y0 = r0;
+    y1 = r1;
+}
+
+// Row emission state: consecutive pieces in one voxel merge into one entry.
+template <bool FILL, typename CH>
+struct Emit {
+    int32_t cur = -1;
+    double cur_len = 0.0;
+    double norm2 = 0.0;
+    int64_t n = 0;
+    int32_t *idx = nullptr;
+    CH *chord = nullptr;
+
+    __device__ inline void flush()
+    {
+        if (cur < 0) return;
+        if (FILL) {
+            idx[n] = cur;
+            if constexpr (sizeof(CH) == 4) chord[n] = (float)cur_len;
+            else chord[n] = __float2half((float)cur_len);
+        }
+        norm2 += cur_len * cur_len;
+        n++;
+        cur = -1;
+        cur_len = 0.0;
+    }
+};
+
+template <bool FILL, typename CH>
+__device__ void walk_segment(const GridDev &g, const double q0[3], const double q1[3],
+                             Emit<FILL, CH> &e)
+{
+    const int32_t n[3] = {g.nx, g.ny, g.nz};
+    const double vs[3] = {g.vx, g.vy, g.vz};
+    const double o[3] = {g.ox, g.oy, g.oz};
+    double g0[3], g1[3], dg[3];
+    for (int a = 0; a < 3; a++) {
+        g0[a] = (q0[a] - o[a]) / vs[a];
+        g1[a] = (q1[a] - o[a]) / vs[a];
+        dg[a] = g1[a] - g0[a];
+    }
+    double dx = q1[0] - q0[0], dy = q1[1] - q0[1], dz = q1[2] - q0[2];
+    double len = sqrt(dx * dx + dy * dy + dz * dz);
+    if (!(len > 0.0)) return;
+
+    // Per axis: next integer plane in the direction of travel, the last one
+    // inside [0, n], and its crossing parameter tau = (m - g0) / dg.
+    double mnext[3], mend[3], step[3], tnext[3];
+    bool act[3];
+    for (int a = 0; a < 3; a++) {
+        act[a] = false;
+        tnext[a] = 2.0;
+        if (dg[a] == 0.0) continue;
+        double lo = (g0[a] < g1[a]) ? g0[a] : g1[a];
+        double hi = (g0[a] < g1[a]) ? g1[a] : g0[a];
+        double mlo = floor(lo) + 1.0;
+        double mhi = ceil(hi) - 1.0;
+        if (mlo < 0.0) mlo = 0.0;
+        if (mhi > (double)n[a]) mhi = (double)n[a];
+        if (mlo > mhi) continue;
+        act[a] = true;
+        if (dg[a] > 0.0) { mnext[a] = mlo; mend[a] = mhi; step[a] = 1.0; }
+        else { mnext[a] = mhi; mend[a] = mlo; step[a] = -1.0; }
+        tnext[a] = (mnext[a] - g0[a]) / dg[a];
+    }
+
+    double prev = 0.0;
+    for (;;) {
+        double tb = 1.0;
+        for (int a = 0; a < 3; a++)
+            if (act[a] && tnext[a] < tb) tb = tnext[a];
+        if (tb > prev) {
+            double ta = prev;
+            prev = tb;
+            double tm = (ta + tb) * 0.5;
+            bool inside = true;
+            int64_t vi[3];
+            for (int a = 0; a < 3; a++) {
+                double c = floor(g0[a] + tm * dg[a]);
+                if (c < 0.0 || c >= (double)n[a]) { inside = false; break; }
+                vi[a] = (int64_t)c;
+            }
+            if (inside) {
+                int32_t lin = (int32_t)(vi[0] + (int64_t)n[0] * (vi[1] + (int64_t)n[1] * vi[2]));
+                double clen = (tb - ta) * len;
+                if (lin == e.cur) {
+                    e.cur_len += clen;
+                } else {
+                    e.flush();
+                    e.cur = lin;
+                    e.cur_len = clen;
+                }
+            }
+        }
+        if (tb >= 1.0) break;
+        for (int a = 0; a < 3; a++) {
+            if (act[a] && tnext[a] == tb) {
+                if (mnext[a] == mend[a]) { act[a] = false; tnext[a] = 2.0; }
+                else { mnext[a] += step[a]; tnext[a] = (mnext[a] - g0[a]) / dg[a]; }
+            }
+        }
+    }
+}
+
+// MLP of history i and the Siddon walk of its polyline.
+template <bool FILL, typename CH>
+__device__ void form_row(const GridDev &g, const HistDev &H, const MlpCfg &m, int64_t i,
+                         Emit<FILL, CH> &e)
+{
+    double ex = H.ex[i], ey = H.ey[i], ez = H.ez[i];
+    double qx = H.qx[i], qy = H.qy[i], qz = H.qz[i];
+    double eth = H.eth[i], eps = H.eps[i], qth = H.qth[i], qps = H.qps[i];
+    double ux = H.ux[i], uy = H.uy[i];
+    double nrm = sqrt(ux * ux + uy * uy);
+    ux = ux / nrm;
+    uy = uy / nrm;
+
+    double u0 = ex * ux + ey * uy, t0 = -ex * uy + ey * ux, v0 = ez;
+    double u2 = qx * ux + qy * uy, t2 = -qx * uy + qy * ux, v2 = qz;
+    double L = u2 - u0;
+    if (!(L > 0.0)) return;
+    double Jd = ceil(L / m.step);
+    int64_t J = (Jd < 1.0) ? 1 : (int64_t)Jd;
+
+    double b[6];
+    power_coefs(m.const_power, b);
+    // Exit-side expansion P(L - s) = sum_k c_k s^k.
+    double c[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = k; q < 6; q++) {
+            const double binom = fact(q) / (fact(k) * fact(q - k));
+            acc += b[q] * binom * ipow(L, q - k);
+        }
+        c[k] = (k % 2) ? -acc : acc;
+    }
+
+    double prevp[3] = {ex, ey, ez};
+    for (int64_t j = 1; j < J; j++) {
+        double d1 = (double)j * m.step;
+        double d2 = L - d1;
+        double i1[3] = {0.0, 0.0, 0.0}, j2[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mm = 0; mm < 3; mm++) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const double beta = fact(mm) * fact(k) / fact(mm + k + 1);
+                i1[mm] += b[k] * ipow(d1, mm + k + 1) * beta;
+            }
+        }
+#pragma unroll
+        for (int mm = 0; mm < 3; mm++)
+#pragma unroll
+            for (int k = 0; k < 6; k++)
+                j2[mm] += c[k] * ipow(d2, mm + k + 1) / (double)(mm + k + 1);
+        double A1 = highland(d1, m.log_term);
+        double A2 = highland(d2, m.log_term);
+        M2 S1 = {A1 * i1[2], A1 * i1[1], A1 * i1[1], A1 * i1[0]};
+        M2 S2 = {A2 * j2[2], A2 * j2[1], A2 * j2[1], A2 * j2[0]};
+        M2 R0 = {1.0, d1, 0.0, 1.0};
+        M2 R1 = {1.0, d2, 0.0, 1.0};
+        M2 S1i = inv(S1);
+        M2 S2i = inv(S2);
+        M2 R1t = {R1.a, R1.c, R1.b, R1.d};
+        M2 T = mul(R1t, S2i);
+        M2 T2 = mul(T, R1);
+        M2 M = {S1i.a + T2.a, S1i.b + T2.b, S1i.c + T2.c, S1i.d + T2.d};
+        M2 Mi = inv(M);
+        double y1t, y1v;
+        {
+            double a0, a1, p0, p1, q0, q1, r0, r1, y0_, y1_;
+            mvec(R0, t0, eth, a0, a1);
+            mvec(S1i, a0, a1, p0, p1);
+            mvec(T, t2, qth, q0, q1);
+            r0 = p0 + q0;
+            r1 = p1 + q1;
+            mvec(Mi, r0, r1, y0_, y1_);
+            y1t = y0_;
+        }
+        {
+            double a0, a1, p0, p1, q0, q1, r0, r1, y0_, y1_;
+            mvec(R0, v0, eps, a0, a1);
+            mvec(S1i, a0, a1, p0, p1);
+            mvec(T, v2, qps, q0, q1);
+            r0 = p0 + q0;
+            r1 = p1 + q1;
+            mvec(Mi, r0, r1, y0_, y1_);
+            y1v = y0_;
+        }
+        double u = u0 + d1;
+        double p[3] = {u * ux - y1t * uy, u * uy + y1t * ux, y1v};
+        walk_segment<FILL, CH>(g, prevp, p, e);
+        prevp[0] = p[0];
+        prevp[1] = p[1];
+        prevp[2] = p[2];
+    }
+    double last[3] = {qx, qy, qz};
+    walk_segment<FILL, CH>(g, prevp, last, e);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_rows_count(GridDev g, HistDev H, MlpCfg m, int64_t first, int64_t n, int32_t *nnz)
+{
+    int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= n) return;
+    Emit<false, float> e;
+    form_row<false, float>(g, H, m, first + q, e);
+    e.flush();
+    nnz[q] = (int32_t)e.n;
+}
+
+template <typename CH>
+__global__ void __launch_bounds__(kThreads)
+k_rows_fill(GridDev g, HistDev H, MlpCfg m, int64_t first, int64_t n, const int64_t *row_off,
+            int64_t base, int32_t *idx, CH *chord, float *norm2)
+{
+    int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= n) return;
+    Emit<true, CH> e;
+    int64_t off = row_off[q] - base;
+    e.idx = idx + off;
+    e.chord = chord + off;
+    form_row<true, CH>(g, H, m, first + q, e);
+    e.flush();
+    norm2[q] = (float)e.norm2;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_validate(HistDev H, int64_t n, double step, uint32_t *bad)
+{
+    int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const float *f[13] = {H.ex, H.ey, H.ez, H.qx, H.qy, H.qz, H.eth, H.eps, H.qth, H.qps,
+                          H.ux, H.uy, H.wepl};
+    bool ok = true;
+    for (int q = 0; q < 13; q++) {
+        float v = f[q][i];
+        if (!isfinite(v) || fabsf(v) > 1.0e6f) ok = false;
+    }
+    if (ok) {
+        double ux = H.ux[i], uy = H.uy[i];
+        double nn = ux * ux + uy * uy;
+        if (!(nn >= 1.0e-12)) {
+            ok = false;
+        } else {
+            double nrm = sqrt(nn);
+            double L = ((double)H.qx[i] - (double)H.ex[i]) * (ux / nrm) +
+                       ((double)H.qy[i] - (double)H.ey[i]) * (uy / nrm);
+            if (L / step > 1048576.0) ok = false;
+        }
+    }
+    if (!ok) atomicAdd(bad, 1u);
+}
+
+// ---------------------------------------------------------------- scan
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kThreads * kScanItems;
+
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t *total)
+{
+    __shared__ int64_t warp_sums[kThreads / 64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) warp_sums[w] = inc;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+    for (int q = 0; q < kThreads / 64; q++) {
+        if (q < w) before += warp_sums[q];
+        all += warp_sums[q];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_tiles(const int32_t *cnt, int64_t n, int64_t *tile_sum)
+{
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0;
+    for (int q = 0; q < kScanItems; q++) {
+        int64_t i = base + (int64_t)threadIdx.x * kScanItems + q;
+        if (i < n) s += cnt[i];
+    }
+    int64_t total;
+    block_exclusive_scan(s, &total);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_partials(int64_t *tile_sum, int64_t ntiles)
+{
+    // Single workgroup: exclusive scan of the tile sums in place, in chunks.
+    int64_t carry = 0;
+    for (int64_t base = 0; base < ntiles; base += kThreads) {
+        int64_t i = base + threadIdx.x;
+        int64_t v = (i < ntiles) ? tile_sum[i] : 0;
+        int64_t total;
+        int64_t ex = block_exclusive_scan(v, &total);
+        if (i < ntiles) tile_sum[i] = carry + ex;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_sum[ntiles] = carry;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_scan_write(const int32_t *cnt, int64_t n, const int64_t *tile_off, int64_t ntiles, int64_t *off)
+{
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+    for (int q = 0; q < kScanItems; q++) {
+        int64_t i = base + (int64_t)threadIdx.x * kScanItems + q;
+        v[q] = (i < n) ? (int64_t)cnt[i] : 0;
+        s += v[q];
+    }
+    int64_t total;
+    int64_t ex = block_exclusive_scan(s, &total) + tile_off[blockIdx.x];
+    for (int q = 0; q < kScanItems; q++) {
+        int64_t i = base + (int64_t)threadIdx.x * kScanItems + q;
+        if (i < n) off[i] = ex;
+        ex += v[q];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) off[n] = tile_off[ntiles];
+}
+
+}  // namespace
+
+hipError_t launch_rows_count(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t first,
+                             int64_t n, int32_t *nnz, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(k_rows_count, grid, dim3(kThreads), 0, stream, g, h, m, first, n, nnz);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_fill(const GridDev &g, const HistDev &h, const MlpCfg &m, const RowSet &rs,
+                            hipStream_t stream)
+{
+    if (rs.n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((rs.n + kThreads - 1) / kThreads));
+    if (rs.chord16)
+        hipLaunchKernelGGL(k_rows_fill<__half>, grid, dim3(kThreads), 0, stream, g, h, m, rs.first,
+                           rs.n, rs.row_off, rs.base, rs.idx, rs.chord16, rs.norm2);
+    else
+        hipLaunchKernelGGL(k_rows_fill<float>, grid, dim3(kThreads), 0, stream, g, h, m, rs.first,
+                           rs.n, rs.row_off, rs.base, rs.idx, rs.chord32, rs.norm2);
+    return hipGetLastError();
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *bad,
+                           hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
+                       0, stream, h, n, step, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const int32_t *cnt, int64_t n, int64_t *off, int64_t *tmp,
+                       hipStream_t stream)
+{
+    int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ntiles == 0) {
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, stream, tmp, (int64_t)0);
+        hipLaunchKernelGGL(k_scan_write, dim3(1), dim3(kThreads), 0, stream, cnt, (int64_t)0, tmp,
+                           (int64_t)0, off);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kThreads), 0, stream, cnt, n, tmp);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, stream, tmp, ntiles);
+    hipLaunchKernelGGL(k_scan_write, dim3((unsigned)ntiles), dim3(kThreads), 0, stream, cnt, n, tmp,
+                       ntiles, off);
+    return hipGetLastError();
+}
+
+}  // namespace tvs

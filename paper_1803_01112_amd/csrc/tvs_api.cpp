@@ -1,0 +1,837 @@
+// tvs_api.cpp -- the C ABI (include/tvs.h) and the host runtime around the
+// gfx950 kernels: argument validation, device memory ownership and HBM
+// budget, history ingest, row formation (once for a path store, per chunk
+// for on-the-fly rows), the cycle driver (schedule of ell and beta, TV
+// steps with or without the TV-reduction check, the DROP sweep) and the
+// step log.
+//
+// Cycle structure (arXiv 1803.01112, Appendix C): ell_k = rand(k, ell_{k-1})
+// once per cycle; N perturbation steps with beta = alpha^ell, ell += 1 after
+// each; then x = P_T(x).  With the check, each step retries z = x + beta v
+// with ell += 1 (and beta = alpha^ell recomputed) until TV(z) <= TV(x).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tvs_internal.hpp"
+
+using tvs::GridDev;
+using tvs::HistDev;
+using tvs::RowSet;
+
+namespace {
+
+constexpr int kNumStreams = 13;
+
+// SplitMix64 (Steele, Lea, Flood 2014): golden-gamma Weyl state, variant-13
+// output mixer.
+uint64_t splitmix64(uint64_t &state)
+{
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// rand(k, ell): uniform integer in [k, ell], both ends included (k when
+// ell < k); exactly one draw per call.
+int64_t draw_ell(int64_t k, int64_t ell, uint64_t &state)
+{
+    uint64_t u = splitmix64(state);
+    if (ell < k) return k;
+    uint64_t span = (uint64_t)(ell - k) + 1u;
+    unsigned __int128 p = (unsigned __int128)u * span;
+    return k + (int64_t)(uint64_t)(p >> 64);
+}
+
+}  // namespace
+
+struct tvs_ctx {
+    tvs_grid grid{};
+    tvs_config cfg{};
+    GridDev gd{};
+    tvs::MlpCfg mlp{};
+    hipStream_t stream = nullptr;
+    int64_t nvox = 0;
+    uint64_t budget = 0;
+    uint64_t bytes = 0;
+    std::string err;
+
+    // image-side buffers (image and subgradient float64; corrections float32)
+    double *x = nullptr, *g = nullptr;
+    float *c = nullptr;
+    float *xio = nullptr;           // float32 staging of the image at the ABI
+    uint32_t *s = nullptr;
+    int32_t *touched = nullptr;
+    uint32_t *ntouched = nullptr;   // [2] touched counters, [2..4] barrier, [5] scratch flag
+    double *part = nullptr, *scal = nullptr;
+    uint32_t *ticket = nullptr;
+    int64_t nparts = 0;
+
+    // histories
+    bool loaded = false;
+    int64_t nh = 0;
+    float *hist = nullptr;          // 13 * nh floats
+    int64_t *row_off = nullptr;     // nh + 1
+    float *norm2 = nullptr;         // nh
+    int32_t *idx = nullptr;         // store or chunk buffer
+    float *chord32 = nullptr;
+    __half *chord16 = nullptr;
+    int64_t nnz = 0, max_row = 0, skipped = 0;
+    int64_t chunk = 0;              // histories per chunk (on-the-fly)
+    std::vector<int64_t> chunk_base; // row_off at each chunk start (and the end)
+
+    // cycle state
+    int64_t k = 0, ell = 0;
+    uint64_t rng = 0;
+    bool seeded = false;
+    std::vector<tvs_step_log> log;
+    int64_t tries = 0;
+
+    // timing: HIP events recorded on the launch stream around every phase of
+    // the last tvs_iterate call, resolved lazily by tvs_get_stats
+    std::vector<hipEvent_t> tev;
+    size_t tev_used = 0;
+    struct Span { int kind; size_t a, b; };   // kind: 0 TV steps, 1 sweep, 2 rows, 3 DROP
+    std::vector<Span> spans;
+    bool timed = false;
+    double last_sweep_ms = 0, last_tv_ms = 0, last_rows_ms = 0;
+    double tot_ms[4] = {0, 0, 0, 0};
+    int64_t tot_n[4] = {0, 0, 0, 0};
+    int lpr = 64;
+    int pgrid = 0;
+};
+
+namespace {
+
+int fail(tvs_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ctx, TVS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+int dalloc(tvs_ctx *ctx, T **p, size_t count)
+{
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = sizeof(T);
+    if (ctx->bytes + bytes > ctx->budget)
+        return fail(ctx, TVS_ENOMEM,
+                    "footprint " + std::to_string(ctx->bytes + bytes) + " B exceeds budget " +
+                        std::to_string(ctx->budget) + " B");
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, TVS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    *p = static_cast<T *>(q);
+    ctx->bytes += bytes;
+    return TVS_OK;
+}
+
+template <typename T>
+void dfree(tvs_ctx *ctx, T **p, size_t count)
+{
+    if (*p) {
+        (void)hipFree(*p);
+        size_t bytes = count * sizeof(T);
+        if (bytes == 0) bytes = sizeof(T);
+        ctx->bytes -= std::min<uint64_t>(ctx->bytes, bytes);
+        *p = nullptr;
+    }
+}
+
+int64_t nnz_cap_of(tvs_ctx *ctx)
+{
+    // entries held by the idx/chord buffers: the whole store, or the largest chunk
+    if (ctx->cfg.path_mode != TVS_PATH_ON_THE_FLY) return ctx->nnz;
+    int64_t m = 0;
+    for (size_t q = 0; q + 1 < ctx->chunk_base.size(); q++)
+        m = std::max(m, ctx->chunk_base[q + 1] - ctx->chunk_base[q]);
+    return m;
+}
+
+void free_histories(tvs_ctx *ctx)
+{
+    int64_t cap = nnz_cap_of(ctx);
+    dfree(ctx, &ctx->hist, (size_t)(kNumStreams * ctx->nh));
+    dfree(ctx, &ctx->row_off, (size_t)(ctx->nh + 1));
+    dfree(ctx, &ctx->norm2, (size_t)ctx->nh);
+    dfree(ctx, &ctx->idx, (size_t)cap);
+    dfree(ctx, &ctx->chord32, (size_t)cap);
+    dfree(ctx, &ctx->chord16, (size_t)cap);
+    ctx->loaded = false;
+    ctx->nh = 0;
+    ctx->nnz = ctx->max_row = ctx->skipped = 0;
+    ctx->chunk_base.clear();
+}
+
+HistDev hist_dev(const tvs_ctx *ctx)
+{
+    const float *b = ctx->hist;
+    const int64_t n = ctx->nh;
+    return HistDev{b + 0 * n, b + 1 * n, b + 2 * n,  b + 3 * n,  b + 4 * n,  b + 5 * n, b + 6 * n,
+                   b + 7 * n, b + 8 * n, b + 9 * n, b + 10 * n, b + 11 * n, b + 12 * n};
+}
+
+tvs::DropBuffers drop_bufs(tvs_ctx *ctx)
+{
+    return tvs::DropBuffers{ctx->x, ctx->c, ctx->s, ctx->touched, ctx->ntouched,
+                            ctx->ntouched + 2, ctx->nvox};
+}
+
+tvs::TvBuffers tv_bufs(tvs_ctx *ctx)
+{
+    return tvs::TvBuffers{ctx->g, ctx->part, ctx->ticket, ctx->scal, ctx->nparts};
+}
+
+hipStream_t pick(tvs_ctx *ctx, void *stream)
+{
+    return stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+}
+
+void reset_state(tvs_ctx *ctx)
+{
+    ctx->k = 0;
+    ctx->ell = 0;
+    ctx->rng = 0;
+    ctx->seeded = false;
+    ctx->log.clear();
+    ctx->tries = 0;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Records a timing event on st; returns its index in the pool (or -1).
+long mark(tvs_ctx *ctx, hipStream_t st)
+{
+    if (ctx->tev_used == ctx->tev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        ctx->tev.push_back(e);
+    }
+    if (hipEventRecord(ctx->tev[ctx->tev_used], st) != hipSuccess) return -1;
+    return (long)ctx->tev_used++;
+}
+
+void span(tvs_ctx *ctx, int kind, long a, long b)
+{
+    if (a >= 0 && b >= 0) ctx->spans.push_back({kind, (size_t)a, (size_t)b});
+}
+
+// Row set covering histories [first, first + n) of the loaded data, with
+// the idx/chord buffers (store: global entries; chunk: entries from base).
+RowSet rowset(tvs_ctx *ctx, int64_t first, int64_t n, int64_t base)
+{
+    RowSet rs;
+    rs.first = first;
+    rs.n = n;
+    rs.base = base;
+    rs.row_off = ctx->row_off + first;
+    rs.norm2 = ctx->norm2 + first;
+    rs.idx = ctx->idx;
+    rs.chord32 = ctx->chord32;
+    rs.chord16 = ctx->chord16;
+    return rs;
+}
+
+// One P_T sweep over all loaded histories.
+int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st)
+{
+    const int64_t B = ctx->cfg.block_size;
+    const float *wepl = ctx->hist + 12 * ctx->nh;
+    tvs::DropBuffers db = drop_bufs(ctx);
+    const bool persistent = ctx->pgrid > 0;
+    const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
+    const int64_t step = otf ? ctx->chunk : ctx->nh;
+    for (int64_t first = 0, q = 0; first < ctx->nh; first += step, q++) {
+        const int64_t n = std::min(step, ctx->nh - first);
+        RowSet rs = rowset(ctx, first, n, otf ? ctx->chunk_base[q] : 0);
+        long e0 = mark(ctx, st);
+        if (otf) {
+            HIPCHK(tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rs, st));
+            long e1 = mark(ctx, st);
+            span(ctx, 2, e0, e1);
+            e0 = e1;
+        }
+        if (persistent) {
+            HIPCHK(tvs::launch_drop_persistent(rs, wepl, B, lambda, db, ctx->lpr, ctx->pgrid, st));
+        } else {
+            int parity = 0;
+            for (int64_t r0 = first; r0 < first + n; r0 += B, parity ^= 1) {
+                int64_t r1 = std::min(r0 + B, first + n);
+                HIPCHK(tvs::launch_drop_block(rs, wepl, r0, r1, lambda, db, parity, ctx->lpr, st));
+            }
+            HIPCHK(tvs::launch_zero_counters(ctx->ntouched, st));
+        }
+        span(ctx, 3, e0, mark(ctx, st));
+    }
+    return TVS_OK;
+}
+
+int validate_params(tvs_ctx *ctx, const tvs_params *p)
+{
+    if (!p) return fail(ctx, TVS_EINVAL, "params is NULL");
+    if (!finite_pos(p->lambda)) return fail(ctx, TVS_EINVAL, "lambda must be finite and > 0");
+    if (p->variant < 0 || p->variant > 2) return fail(ctx, TVS_EINVAL, "unknown variant");
+    if (p->variant != TVS_OTVS && !(p->alpha > 0.0 && p->alpha < 1.0))
+        return fail(ctx, TVS_EINVAL, "alpha must lie in (0, 1)");
+    if (p->N < 0) return fail(ctx, TVS_EINVAL, "N must be >= 0");
+    if (!(p->tv_eps >= 0.0) || !std::isfinite(p->tv_eps))
+        return fail(ctx, TVS_EINVAL, "tv_eps must be finite and >= 0");
+    if (p->variant == TVS_DECOUPLED && !(p->gamma > 0.0 && p->gamma < 1.0))
+        return fail(ctx, TVS_EINVAL, "gamma must lie in (0, 1)");
+    return TVS_OK;
+}
+
+int read_scalars(tvs_ctx *ctx, hipStream_t st, double out[2])
+{
+    HIPCHK(hipMemcpyAsync(out, ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return TVS_OK;
+}
+
+// Forms rows [first, first+n) with temporary buffers (used by load and debug).
+int count_rows(tvs_ctx *ctx, int64_t first, int64_t n, int64_t *row_off_dev, hipStream_t st)
+{
+    int32_t *cnt = nullptr;
+    int64_t *tmp = nullptr;
+    int rc = dalloc(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
+    if (rc) return rc;
+    rc = dalloc(ctx, &tmp, (size_t)tvs::scan_tmp_elems(n) + 1);
+    if (rc) {
+        dfree(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
+        return rc;
+    }
+    hipError_t e = tvs::launch_rows_count(ctx->gd, hist_dev(ctx), ctx->mlp, first, n, cnt, st);
+    if (e == hipSuccess) e = tvs::launch_scan(cnt, n, row_off_dev, tmp, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
+    dfree(ctx, &tmp, (size_t)tvs::scan_tmp_elems(n) + 1);
+    if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("row count: ") + hipGetErrorString(e));
+    return TVS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tvs_config_default(tvs_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->block_size = 3200;
+    cfg->path_mode = TVS_PATH_ON_THE_FLY;
+    cfg->mlp_step_mm = 0.0;
+    cfg->mlp_log_term = 1;
+    cfg->mlp_const_power = 0;
+    cfg->chunk_histories = 0;
+    cfg->hbm_budget_bytes = 0;
+    cfg->device = 0;
+    cfg->max_tries = 0;
+    cfg->sweep_kernel = 0;
+    cfg->wave_rows = 0;
+}
+
+const char *tvs_strerror(int status)
+{
+    switch (status) {
+    case TVS_OK: return "ok";
+    case TVS_EINVAL: return "invalid argument";
+    case TVS_ENOMEM: return "out of device memory or HBM budget";
+    case TVS_EDEVICE: return "HIP device error";
+    case TVS_ESTATE: return "call out of order";
+    case TVS_ERANGE: return "index or size out of range";
+    default: return "unknown status";
+    }
+}
+
+const char *tvs_last_error(tvs_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+void tvs_destroy(tvs_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->cfg.device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_histories(ctx);
+    dfree(ctx, &ctx->x, (size_t)ctx->nvox);
+    dfree(ctx, &ctx->xio, (size_t)ctx->nvox);
+    dfree(ctx, &ctx->c, (size_t)ctx->nvox);
+    dfree(ctx, &ctx->g, (size_t)ctx->nvox);
+    dfree(ctx, &ctx->s, (size_t)ctx->nvox);
+    dfree(ctx, &ctx->touched, (size_t)ctx->nvox);
+    dfree(ctx, &ctx->ntouched, (size_t)8);
+    dfree(ctx, &ctx->part, (size_t)ctx->nparts);
+    dfree(ctx, &ctx->scal, (size_t)4);
+    dfree(ctx, &ctx->ticket, (size_t)4);
+    for (auto &e : ctx->tev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
+{
+    tvs_ctx *ctx = nullptr;
+    if (!out) return TVS_EINVAL;
+    *out = nullptr;
+    if (!grid) return TVS_EINVAL;
+    tvs_config cfg;
+    if (cfg_in) cfg = *cfg_in;
+    else tvs_config_default(&cfg);
+    if (grid->nx <= 0 || grid->ny <= 0 || grid->nz <= 0) return TVS_EINVAL;
+    if (!finite_pos(grid->vx) || !finite_pos(grid->vy) || !finite_pos(grid->vz)) return TVS_EINVAL;
+    if (!std::isfinite(grid->ox) || !std::isfinite(grid->oy) || !std::isfinite(grid->oz))
+        return TVS_EINVAL;
+    int64_t nvox = (int64_t)grid->nx * grid->ny * grid->nz;
+    if (nvox >= ((int64_t)1 << 31)) return TVS_EINVAL;
+    if (cfg.block_size < 1) return TVS_EINVAL;
+    if (cfg.path_mode < 0 || cfg.path_mode > 2) return TVS_EINVAL;
+    if (!std::isfinite(cfg.mlp_step_mm)) return TVS_EINVAL;
+    if (cfg.chunk_histories < 0 || cfg.max_tries < 0) return TVS_EINVAL;
+    if (cfg.sweep_kernel < 0 || cfg.sweep_kernel > 2) return TVS_EINVAL;
+    if (cfg.wave_rows != 0 && cfg.wave_rows != 16 && cfg.wave_rows != 32 && cfg.wave_rows != 64)
+        return TVS_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg.device < 0 || cfg.device >= ndev)
+        return TVS_EDEVICE;
+    if (hipSetDevice(cfg.device) != hipSuccess) return TVS_EDEVICE;
+
+    ctx = new tvs_ctx();
+    ctx->grid = *grid;
+    ctx->cfg = cfg;
+    ctx->gd = GridDev{grid->nx, grid->ny, grid->nz, grid->vx, grid->vy, grid->vz,
+                      grid->ox, grid->oy, grid->oz};
+    double step = cfg.mlp_step_mm > 0.0 ? cfg.mlp_step_mm : std::min(grid->vx, grid->vy);
+    ctx->mlp = tvs::MlpCfg{step, cfg.mlp_log_term ? 1 : 0, cfg.mlp_const_power ? 1 : 0};
+    if (ctx->cfg.max_tries == 0) ctx->cfg.max_tries = 100000;
+    ctx->nvox = nvox;
+    ctx->lpr = cfg.wave_rows ? cfg.wave_rows : 64;
+
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
+        delete ctx;
+        return TVS_EDEVICE;
+    }
+    ctx->budget = cfg.hbm_budget_bytes ? cfg.hbm_budget_bytes : (uint64_t)(0.8 * (double)freeb);
+
+    int rc = TVS_OK;
+    ctx->nparts = tvs::tv_num_parts(ctx->gd);
+    if (!rc) rc = dalloc(ctx, &ctx->x, (size_t)nvox);
+    if (!rc) rc = dalloc(ctx, &ctx->xio, (size_t)nvox);
+    if (!rc) rc = dalloc(ctx, &ctx->c, (size_t)nvox);
+    if (!rc) rc = dalloc(ctx, &ctx->g, (size_t)nvox);
+    if (!rc) rc = dalloc(ctx, &ctx->s, (size_t)nvox);
+    if (!rc) rc = dalloc(ctx, &ctx->touched, (size_t)nvox);
+    if (!rc) rc = dalloc(ctx, &ctx->ntouched, (size_t)8);
+    if (!rc) rc = dalloc(ctx, &ctx->part, (size_t)ctx->nparts);
+    if (!rc) rc = dalloc(ctx, &ctx->scal, (size_t)4);
+    if (!rc) rc = dalloc(ctx, &ctx->ticket, (size_t)4);
+    if (rc) {
+        tvs_destroy(ctx);
+        return rc;
+    }
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+        tvs_destroy(ctx);
+        return TVS_EDEVICE;
+    }
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->x, 0, sizeof(double) * nvox, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->c, 0, sizeof(float) * nvox, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->s, 0, sizeof(uint32_t) * nvox, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->ntouched, 0, sizeof(uint32_t) * 8, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->ticket, 0, sizeof(uint32_t) * 4, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->scal, 0, sizeof(double) * 4, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        tvs_destroy(ctx);
+        return TVS_EDEVICE;
+    }
+    int sk = cfg.sweep_kernel ? cfg.sweep_kernel : 2;
+    ctx->pgrid = (sk == 2) ? tvs::persistent_grid_size(cfg.device, ctx->lpr) : 0;
+    *out = ctx;
+    return TVS_OK;
+}
+
+int tvs_load_histories(tvs_ctx *ctx, int64_t n, const tvs_histories *h, int on_device, void *stream)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    if (n < 0) return fail(ctx, TVS_EINVAL, "n must be >= 0");
+    if (n >= ((int64_t)1 << 31)) return fail(ctx, TVS_EINVAL, "at most 2^31 - 1 histories");
+    if (n > 0 && !h) return fail(ctx, TVS_EINVAL, "histories is NULL");
+    const float *src[kNumStreams] = {};
+    if (n > 0) {
+        const float *tmp[kNumStreams] = {h->ex,  h->ey,  h->ez, h->qx, h->qy, h->qz, h->eth,
+                                         h->eps, h->qth, h->qps, h->ux, h->uy, h->wepl};
+        for (int q = 0; q < kNumStreams; q++) {
+            if (!tmp[q]) return fail(ctx, TVS_EINVAL, "a history stream is NULL");
+            src[q] = tmp[q];
+        }
+    }
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    HIPCHK(hipStreamSynchronize(st));
+    free_histories(ctx);
+    reset_state(ctx);
+    HIPCHK(hipMemsetAsync(ctx->x, 0, sizeof(double) * ctx->nvox, st));
+    ctx->nh = n;
+
+    int rc = dalloc(ctx, &ctx->hist, (size_t)(kNumStreams * n));
+    if (!rc) rc = dalloc(ctx, &ctx->row_off, (size_t)(n + 1));
+    if (!rc) rc = dalloc(ctx, &ctx->norm2, (size_t)n);
+    if (rc) {
+        free_histories(ctx);
+        return rc;
+    }
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int q = 0; q < kNumStreams && n > 0; q++) {
+        hipError_t e = hipMemcpyAsync(ctx->hist + q * n, src[q], sizeof(float) * n, kind, st);
+        if (e != hipSuccess) {
+            free_histories(ctx);
+            return fail(ctx, TVS_EDEVICE, std::string("history copy: ") + hipGetErrorString(e));
+        }
+    }
+    // validation on the device (the inputs may live there already)
+    uint32_t bad = 0;
+    {
+        hipError_t e = hipMemsetAsync(ctx->ntouched + 5, 0, sizeof(uint32_t), st);
+        if (e == hipSuccess) e = tvs::launch_validate(hist_dev(ctx), n, ctx->mlp.step, ctx->ntouched + 5, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&bad, ctx->ntouched + 5, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            free_histories(ctx);
+            return fail(ctx, TVS_EDEVICE, std::string("validation: ") + hipGetErrorString(e));
+        }
+    }
+    if (bad) {
+        free_histories(ctx);
+        return fail(ctx, TVS_EINVAL,
+                    std::to_string(bad) + " histories hold NaN/inf, |value| > 1e6, a zero beam "
+                                          "axis or more than 2^20 MLP vertices");
+    }
+    // row lengths of every history (one MLP pass); rows themselves are
+    // formed now for a path store, per chunk and sweep otherwise
+    rc = count_rows(ctx, 0, n, ctx->row_off, st);
+    if (rc) {
+        free_histories(ctx);
+        return rc;
+    }
+    std::vector<int64_t> off_h;
+    int64_t total = 0;
+    {
+        std::vector<int64_t> all((size_t)n + 1);
+        hipError_t e = hipMemcpy(all.data(), ctx->row_off, sizeof(int64_t) * (n + 1),
+                                 hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            free_histories(ctx);
+            return fail(ctx, TVS_EDEVICE, std::string("row offsets: ") + hipGetErrorString(e));
+        }
+        total = all[(size_t)n];
+        int64_t mx = 0, sk = 0;
+        for (int64_t i = 0; i < n; i++) {
+            int64_t len = all[(size_t)i + 1] - all[(size_t)i];
+            mx = std::max(mx, len);
+            sk += (len == 0);
+        }
+        ctx->max_row = mx;
+        ctx->skipped = sk;
+        const int64_t B = ctx->cfg.block_size;
+        int64_t chunk = ctx->cfg.chunk_histories;
+        if (chunk <= 0) chunk = std::max<int64_t>(B, ((int64_t)1 << 20) / B * B);
+        else chunk = (chunk + B - 1) / B * B;
+        ctx->chunk = std::max<int64_t>(chunk, 1);
+        for (int64_t f = 0; f < n; f += ctx->chunk) ctx->chunk_base.push_back(all[(size_t)f]);
+        ctx->chunk_base.push_back(total);
+    }
+    ctx->nnz = total;
+    int64_t cap = nnz_cap_of(ctx);
+    rc = dalloc(ctx, &ctx->idx, (size_t)cap);
+    if (!rc) {
+        if (ctx->cfg.path_mode == TVS_PATH_STORE_F16) rc = dalloc(ctx, &ctx->chord16, (size_t)cap);
+        else rc = dalloc(ctx, &ctx->chord32, (size_t)cap);
+    }
+    if (rc) {
+        free_histories(ctx);
+        return rc;
+    }
+    if (ctx->cfg.path_mode != TVS_PATH_ON_THE_FLY && n > 0) {
+        RowSet rs = rowset(ctx, 0, n, 0);
+        hipError_t e = tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rs, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            free_histories(ctx);
+            return fail(ctx, TVS_EDEVICE, std::string("row fill: ") + hipGetErrorString(e));
+        }
+    }
+    ctx->loaded = true;
+    ctx->timed = false;
+    ctx->spans.clear();
+    return TVS_OK;
+}
+
+int tvs_set_image(tvs_ctx *ctx, const float *x0, int on_device, void *stream)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    if (!x0) return fail(ctx, TVS_EINVAL, "image is NULL");
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    if (!on_device) {
+        for (int64_t j = 0; j < ctx->nvox; j++)
+            if (!std::isfinite(x0[j])) return fail(ctx, TVS_EINVAL, "image holds NaN/inf");
+    }
+    HIPCHK(hipMemcpyAsync(ctx->xio, x0, sizeof(float) * ctx->nvox,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    HIPCHK(tvs::launch_widen(ctx->xio, ctx->x, ctx->nvox, st));
+    if (!on_device) HIPCHK(hipStreamSynchronize(st));
+    reset_state(ctx);
+    return TVS_OK;
+}
+
+int tvs_iterate(tvs_ctx *ctx, const tvs_params *p, int32_t K, void *stream)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    int rc = validate_params(ctx, p);
+    if (rc) return rc;
+    if (K < 0) return fail(ctx, TVS_EINVAL, "K must be >= 0");
+    if (!ctx->loaded) return fail(ctx, TVS_ESTATE, "tvs_iterate before tvs_load_histories");
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    tvs::TvBuffers tb = tv_bufs(ctx);
+    if (!ctx->seeded) {
+        ctx->rng = p->seed;
+        ctx->seeded = true;
+    }
+    const bool checked = (p->variant == TVS_OTVS) || (p->variant == TVS_NTVS && p->tv_check);
+    const int32_t nsteps = (p->variant == TVS_OTVS) ? 1 : p->N;
+    if (K > 0) {
+        ctx->tev_used = 0;
+        ctx->spans.clear();
+        ctx->timed = true;
+    }
+    for (int32_t kk = 0; kk < K; kk++) {
+        const int64_t k = ctx->k;
+        if (p->variant == TVS_NTVS) ctx->ell = draw_ell(k, ctx->ell, ctx->rng);
+        const long c0 = mark(ctx, st);
+        for (int32_t n = 0; n < nsteps; n++) {
+            tvs_step_log rec;
+            std::memset(&rec, 0, sizeof(rec));
+            rec.k = (int32_t)k;
+            rec.n = n;
+            rec.ell_start = ctx->ell;
+            rec.gnorm = -1.0;
+            HIPCHK(tvs::launch_tv_grad(ctx->gd, ctx->x, p->tv_eps, tb, st));
+            if (!checked) {
+                double beta = (p->variant == TVS_DECOUPLED)
+                                  ? std::pow(p->alpha, (double)(n + 1)) * std::pow(p->gamma, (double)k)
+                                  : std::pow(p->alpha, (double)ctx->ell);
+                HIPCHK(tvs::launch_tv_step(ctx->gd, ctx->x, beta, tb, st));
+                ctx->ell += 1;
+                rec.tries = 1;
+                rec.accepted = 1;
+                ctx->tries += 1;
+            } else {
+                double sc[2];
+                HIPCHK(tvs::launch_tv_phi(ctx->gd, ctx->x, 0.0, p->tv_eps, tb, st));
+                rc = read_scalars(ctx, st, sc);
+                if (rc) return rc;
+                const double phx = sc[1];
+                rec.phi_x = phx;
+                rec.gnorm = std::sqrt(sc[0]);
+                int32_t tries = 0;
+                while (tries < ctx->cfg.max_tries) {
+                    double beta = (p->variant == TVS_OTVS) ? std::pow(0.5, (double)ctx->ell)
+                                                           : std::pow(p->alpha, (double)ctx->ell);
+                    HIPCHK(tvs::launch_tv_phi(ctx->gd, ctx->x, beta, p->tv_eps, tb, st));
+                    rc = read_scalars(ctx, st, sc);
+                    if (rc) return rc;
+                    tries++;
+                    ctx->ell += 1;
+                    if (sc[1] <= phx) {
+                        HIPCHK(tvs::launch_tv_step(ctx->gd, ctx->x, beta, tb, st));
+                        rec.phi_z = sc[1];
+                        rec.accepted = 1;
+                        break;
+                    }
+                }
+                rec.tries = tries;
+                ctx->tries += tries;
+            }
+            ctx->log.push_back(rec);
+        }
+        const long c1 = mark(ctx, st);
+        span(ctx, 0, c0, c1);
+        rc = run_sweep(ctx, p->lambda, st);
+        if (rc) return rc;
+        span(ctx, 1, c1, mark(ctx, st));
+        ctx->k += 1;
+    }
+    if (K > 0 && ctx->pgrid > 0) {
+        uint32_t flag = 0;
+        HIPCHK(hipMemcpyAsync(&flag, ctx->ntouched + 4, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (flag) {
+            HIPCHK(hipMemsetAsync(ctx->ntouched, 0, sizeof(uint32_t) * 5, st));
+            HIPCHK(hipStreamSynchronize(st));
+            return fail(ctx, TVS_EDEVICE, "sweep grid barrier timed out");
+        }
+    }
+    return TVS_OK;
+}
+
+int tvs_get_image(tvs_ctx *ctx, float *out, int on_device, void *stream)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    if (!out) return fail(ctx, TVS_EINVAL, "output is NULL");
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    HIPCHK(tvs::launch_narrow(ctx->x, ctx->xio, ctx->nvox, st));
+    HIPCHK(hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nvox,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    if (!on_device) HIPCHK(hipStreamSynchronize(st));
+    return TVS_OK;
+}
+
+int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out)
+{
+    if (!ctx || !out) return TVS_EINVAL;
+    ctx->err.clear();
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    if (ctx->timed && !ctx->spans.empty()) {
+        HIPCHK(hipEventSynchronize(ctx->tev[ctx->spans.back().b]));
+        for (int q = 0; q < 4; q++) {
+            ctx->tot_ms[q] = 0.0;
+            ctx->tot_n[q] = 0;
+        }
+        double last[4] = {0, 0, 0, 0};
+        size_t last_cycle_start = 0;
+        for (const auto &sp : ctx->spans) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->tev[sp.a], ctx->tev[sp.b]));
+            ctx->tot_ms[sp.kind] += ms;
+            ctx->tot_n[sp.kind] += 1;
+            if (sp.kind == 0) {
+                last_cycle_start = sp.a;
+                last[0] = ms;
+                last[2] = 0;
+            } else if (sp.kind == 1) {
+                last[1] = ms;
+            } else if (sp.kind == 2 && sp.a >= last_cycle_start) {
+                last[2] += ms;
+            }
+        }
+        ctx->last_tv_ms = last[0];
+        ctx->last_sweep_ms = last[1];
+        ctx->last_rows_ms = last[2];
+        ctx->timed = false;
+    }
+    out->k = ctx->k;
+    out->ell = ctx->ell;
+    out->n_hist = ctx->nh;
+    out->n_skipped = ctx->skipped;
+    out->nnz = ctx->nnz;
+    out->steps = (int64_t)ctx->log.size();
+    out->tries = ctx->tries;
+    out->max_row_nnz = ctx->max_row;
+    out->last_sweep_ms = ctx->last_sweep_ms;
+    out->last_tv_ms = ctx->last_tv_ms;
+    out->last_rows_ms = ctx->last_rows_ms;
+    out->device_bytes = ctx->bytes;
+    out->tv_ms_total = ctx->tot_ms[0];
+    out->sweep_ms_total = ctx->tot_ms[1];
+    out->rows_ms_total = ctx->tot_ms[2];
+    out->drop_ms_total = ctx->tot_ms[3];
+    out->cycles_timed = ctx->tot_n[1];
+    out->rows_launches = ctx->tot_n[2];
+    out->drop_launches = ctx->tot_n[3];
+    return TVS_OK;
+}
+
+int tvs_get_step_log(tvs_ctx *ctx, tvs_step_log *out, int64_t cap, int64_t *n)
+{
+    if (!ctx || !n || cap < 0 || (cap > 0 && !out)) return TVS_EINVAL;
+    *n = (int64_t)ctx->log.size();
+    int64_t m = std::min<int64_t>(cap, *n);
+    if (m > 0) std::memcpy(out, ctx->log.data(), sizeof(tvs_step_log) * (size_t)m);
+    return TVS_OK;
+}
+
+int tvs_debug_rows(tvs_ctx *ctx, int64_t first, int64_t count, int64_t *row_nnz, int32_t *idx,
+                   float *chord, float *norm2, int64_t cap)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    if (!ctx->loaded) return fail(ctx, TVS_ESTATE, "no histories loaded");
+    if (first < 0 || count < 0 || first + count > ctx->nh)
+        return fail(ctx, TVS_ERANGE, "history range outside the loaded histories");
+    if (count > 0 && (!row_nnz || !norm2)) return fail(ctx, TVS_EINVAL, "output is NULL");
+    if (count == 0) return TVS_OK;
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = ctx->stream;
+    int64_t *off = nullptr;
+    int rc = dalloc(ctx, &off, (size_t)(count + 1));
+    if (rc) return rc;
+    rc = count_rows(ctx, first, count, off, st);
+    std::vector<int64_t> offh((size_t)count + 1);
+    if (!rc && hipMemcpy(offh.data(), off, sizeof(int64_t) * (count + 1), hipMemcpyDeviceToHost) !=
+                   hipSuccess)
+        rc = fail(ctx, TVS_EDEVICE, "row offsets copy");
+    if (rc) {
+        dfree(ctx, &off, (size_t)(count + 1));
+        return rc;
+    }
+    const int64_t tot = offh[(size_t)count];
+    for (int64_t q = 0; q < count; q++) row_nnz[q] = offh[(size_t)q + 1] - offh[(size_t)q];
+    if (tot > cap || (tot > 0 && (!idx || !chord))) {
+        dfree(ctx, &off, (size_t)(count + 1));
+        return fail(ctx, TVS_ERANGE, "cap smaller than the entries of the requested rows");
+    }
+    int32_t *di = nullptr;
+    float *dc = nullptr, *dn = nullptr;
+    rc = dalloc(ctx, &di, (size_t)std::max<int64_t>(tot, 1));
+    if (!rc) rc = dalloc(ctx, &dc, (size_t)std::max<int64_t>(tot, 1));
+    if (!rc) rc = dalloc(ctx, &dn, (size_t)count);
+    if (!rc) {
+        RowSet rs;
+        rs.first = first;
+        rs.n = count;
+        rs.base = 0;
+        rs.row_off = off;
+        rs.idx = di;
+        rs.chord32 = dc;
+        rs.norm2 = dn;
+        hipError_t e = tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rs, st);
+        if (e == hipSuccess && tot > 0)
+            e = hipMemcpyAsync(idx, di, sizeof(int32_t) * tot, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && tot > 0)
+            e = hipMemcpyAsync(chord, dc, sizeof(float) * tot, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(norm2, dn, sizeof(float) * count, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(ctx, TVS_EDEVICE, std::string("debug rows: ") + hipGetErrorString(e));
+    }
+    dfree(ctx, &di, (size_t)std::max<int64_t>(tot, 1));
+    dfree(ctx, &dc, (size_t)std::max<int64_t>(tot, 1));
+    dfree(ctx, &dn, (size_t)count);
+    dfree(ctx, &off, (size_t)(count + 1));
+    return rc;
+}
+
+}  // extern "C"

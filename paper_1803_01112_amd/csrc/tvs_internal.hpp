@@ -1,0 +1,117 @@
+// tvs_internal.hpp -- internal declarations of the MI355X TVS library: the
+// context, device-side parameter blocks and the kernel launchers.  Nothing
+// here is part of the public ABI (include/tvs.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tvs.h"
+
+namespace tvs {
+
+// Voxel grid as the kernels see it.
+struct GridDev {
+    int32_t nx, ny, nz;
+    double vx, vy, vz;
+    double ox, oy, oz;
+};
+
+// SoA history streams on the device (13 float32 arrays of length n_hist).
+struct HistDev {
+    const float *ex, *ey, *ez, *qx, *qy, *qz, *eth, *eps, *qth, *qps, *ux, *uy, *wepl;
+};
+
+struct MlpCfg {
+    double step;
+    int32_t log_term;
+    int32_t const_power;
+};
+
+// Rows of a contiguous range of histories [first, first + n): CSR with
+// offsets relative to the start of this row set.
+struct RowSet {
+    int64_t first = 0;        // global index of the first history
+    int64_t n = 0;            // histories in the set
+    int64_t nnz = 0;          // entries
+    int64_t base = 0;         // entries of row q start at row_off[q] - base
+    int64_t *row_off = nullptr;   // n + 1 offsets
+    int32_t *idx = nullptr;       // voxel indices
+    float *chord32 = nullptr;     // chords (float32) or
+    __half *chord16 = nullptr;    // chords (float16)
+    float *norm2 = nullptr;       // ||a_i||^2 per history (0: the history forms no row)
+};
+
+// ----------------------------------------------------------------- rows.hip
+// Forms the rows of histories [first, first + n) in two passes.  Pass 1
+// writes nnz[i] (int32); after an exclusive scan into row_off, pass 2 fills
+// idx / chord / norm2.  All launches are asynchronous on `stream`.
+hipError_t launch_rows_count(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t first,
+                             int64_t n, int32_t *nnz, hipStream_t stream);
+hipError_t launch_rows_fill(const GridDev &g, const HistDev &h, const MlpCfg &m, const RowSet &rs,
+                            hipStream_t stream);
+// Exclusive scan of n int32 counts into n+1 int64 offsets (off[n] = total).
+// `tmp` needs scan_tmp_elems(n) int64 elements.
+int64_t scan_tmp_elems(int64_t n);
+// Counts histories with non-finite values, a degenerate beam axis,
+// coordinates beyond 1e6 mm or more than 2^20 MLP vertices into *bad.
+hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *bad,
+                           hipStream_t stream);
+hipError_t launch_scan(const int32_t *cnt, int64_t n, int64_t *off, int64_t *tmp,
+                       hipStream_t stream);
+
+// ----------------------------------------------------------------- drop.hip
+struct DropBuffers {
+    double *x;           // image (float64: keeps the small DROP increments exact
+                         // enough for the scale-free TV subgradient)
+    float *c;            // correction sums
+    uint32_t *s;         // hit counts
+    int32_t *touched;    // voxels touched by the current block (capacity nvox)
+    uint32_t *ntouched;  // two counters used alternately by consecutive blocks
+    uint32_t *barrier;   // persistent sweep: grid barrier counter + error flag
+    int64_t nvox;
+};
+
+// One DROP block [r0, r1) (global history indices inside rs) with the
+// one-launch-per-phase kernels; `parity` selects the touched counter.
+hipError_t launch_drop_block(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
+                             double lambda, const DropBuffers &b, int parity, int lanes_per_row,
+                             hipStream_t stream);
+// All blocks of rs in one persistent launch with grid barriers.
+hipError_t launch_drop_persistent(const RowSet &rs, const float *wepl, int64_t block_size,
+                                  double lambda, const DropBuffers &b, int lanes_per_row,
+                                  int grid_wgs, hipStream_t stream);
+int persistent_grid_size(int device, int lanes_per_row);
+// Clears both touched-list counters.
+hipError_t launch_zero_counters(uint32_t *cnt, hipStream_t stream);
+
+// ----------------------------------------------------------------- tv.hip
+struct TvBuffers {
+    double *g;           // subgradient
+    double *part;        // per-workgroup partial sums
+    uint32_t *ticket;    // last-workgroup counter
+    double *scal;        // [0] = ||g||^2, [1] = phi value
+    int64_t nparts;
+};
+int64_t tv_num_parts(const GridDev &g);
+// g = grad TV(x); scal[0] = ||g||^2 (fixed-order reduction).
+hipError_t launch_tv_grad(const GridDev &g, const double *x, double eps, const TvBuffers &t,
+                          hipStream_t stream);
+// x = x + s * g with s = -beta / sqrt(scal[0]) (0 when the norm is 0).
+hipError_t launch_tv_step(const GridDev &g, double *x, double beta, const TvBuffers &t,
+                          hipStream_t stream);
+// scal[1] = TV(x + s g) with s = -beta / sqrt(scal[0]) rounded as in
+// launch_tv_step, so an accepted trial image equals the stepped image
+// (beta = 0: TV(x)).
+hipError_t launch_tv_phi(const GridDev &g, const double *x, double beta, double eps,
+                         const TvBuffers &t, hipStream_t stream);
+// Image conversions between the float32 ABI and the float64 device image.
+hipError_t launch_widen(const float *src, double *dst, int64_t n, hipStream_t stream);
+hipError_t launch_narrow(const double *src, float *dst, int64_t n, hipStream_t stream);
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream);
+
+}  // namespace tvs

@@ -1,0 +1,273 @@
+"""Python binding of libtvs (include/tvs.h): argument marshalling only.
+
+Every step of the reconstruction runs in the gfx950 kernels behind the C
+ABI; this module converts arguments (numpy arrays for host memory, torch
+CUDA tensors for device memory, torch streams or raw hipStream_t handles)
+and raises TvsError on a failing status.  There is no fallback: if the
+shared library is missing the import of the library fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from ._build import LIB
+
+HIST_FIELDS = ("ex", "ey", "ez", "qx", "qy", "qz", "eth", "eps", "qth", "qps", "ux", "uy", "wepl")
+
+TVS_OK, TVS_EINVAL, TVS_ENOMEM, TVS_EDEVICE, TVS_ESTATE, TVS_ERANGE = 0, -1, -2, -3, -4, -5
+PATH_MODES = {"otf": 0, "f32": 1, "f16": 2}
+VARIANTS = {"ntvs": 0, "otvs": 1, "decoupled": 2}
+
+EXPORTED = ("tvs_config_default", "tvs_create", "tvs_destroy", "tvs_load_histories",
+            "tvs_set_image", "tvs_iterate", "tvs_get_image", "tvs_get_stats", "tvs_get_step_log",
+            "tvs_debug_rows", "tvs_strerror", "tvs_last_error")
+
+
+class TvsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("vx", C.c_double), ("vy", C.c_double), ("vz", C.c_double),
+                ("ox", C.c_double), ("oy", C.c_double), ("oz", C.c_double)]
+
+
+class Config(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("path_mode", C.c_int32), ("mlp_step_mm", C.c_double),
+                ("mlp_log_term", C.c_int32), ("mlp_const_power", C.c_int32),
+                ("chunk_histories", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
+                ("device", C.c_int32), ("max_tries", C.c_int32), ("sweep_kernel", C.c_int32),
+                ("wave_rows", C.c_int32)]
+
+
+_FP = C.POINTER(C.c_float)
+
+
+class Histories(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in HIST_FIELDS]
+
+
+class Params(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("N", C.c_int32), ("alpha", C.c_double),
+                ("tv_check", C.c_int32), ("variant", C.c_int32), ("tv_eps", C.c_double),
+                ("seed", C.c_uint64), ("gamma", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("k", C.c_int64), ("ell", C.c_int64), ("n_hist", C.c_int64),
+                ("n_skipped", C.c_int64), ("nnz", C.c_int64), ("steps", C.c_int64),
+                ("tries", C.c_int64), ("max_row_nnz", C.c_int64), ("last_sweep_ms", C.c_double),
+                ("last_tv_ms", C.c_double), ("last_rows_ms", C.c_double),
+                ("device_bytes", C.c_uint64), ("tv_ms_total", C.c_double),
+                ("sweep_ms_total", C.c_double), ("rows_ms_total", C.c_double),
+                ("drop_ms_total", C.c_double), ("cycles_timed", C.c_int64),
+                ("rows_launches", C.c_int64), ("drop_launches", C.c_int64)]
+
+
+class StepLog(C.Structure):
+    _fields_ = [("k", C.c_int32), ("n", C.c_int32), ("tries", C.c_int32), ("accepted", C.c_int32),
+                ("ell_start", C.c_int64), ("phi_x", C.c_double), ("phi_z", C.c_double),
+                ("gnorm", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB):
+    """Loads libtvs.so (built by __graft_entry__.build); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libtvs.so not built at {path}: run __graft_entry__.build() first")
+    L = C.CDLL(path)
+    P = C.POINTER
+    L.tvs_config_default.argtypes = [P(Config)]
+    L.tvs_config_default.restype = None
+    L.tvs_create.argtypes = [P(Grid), P(Config), P(C.c_void_p)]
+    L.tvs_destroy.argtypes = [C.c_void_p]
+    L.tvs_destroy.restype = None
+    L.tvs_load_histories.argtypes = [C.c_void_p, C.c_int64, P(Histories), C.c_int, C.c_void_p]
+    L.tvs_set_image.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    L.tvs_iterate.argtypes = [C.c_void_p, P(Params), C.c_int32, C.c_void_p]
+    L.tvs_get_image.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    L.tvs_get_stats.argtypes = [C.c_void_p, P(Stats)]
+    L.tvs_get_step_log.argtypes = [C.c_void_p, P(StepLog), C.c_int64, P(C.c_int64)]
+    L.tvs_debug_rows.argtypes = [C.c_void_p, C.c_int64, C.c_int64, P(C.c_int64), P(C.c_int32),
+                                 _FP, _FP, C.c_int64]
+    L.tvs_strerror.argtypes = [C.c_int]
+    L.tvs_strerror.restype = C.c_char_p
+    L.tvs_last_error.argtypes = [C.c_void_p]
+    L.tvs_last_error.restype = C.c_char_p
+    for name in ("tvs_create", "tvs_load_histories", "tvs_set_image", "tvs_iterate",
+                 "tvs_get_image", "tvs_get_stats", "tvs_get_step_log", "tvs_debug_rows"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+def _is_device(a) -> bool:
+    return hasattr(a, "is_cuda") and bool(a.is_cuda)
+
+
+def _ptr(a):
+    """(pointer, on_device, keep-alive) of a float32 array or tensor."""
+    if _is_device(a):
+        import torch
+        if a.dtype != torch.float32 or not a.is_contiguous():
+            raise TypeError("device arrays must be contiguous float32 tensors")
+        return C.c_void_p(a.data_ptr()), 1, a
+    arr = np.ascontiguousarray(np.asarray(a), dtype=np.float32)
+    return C.c_void_p(arr.ctypes.data), 0, arr
+
+
+def grid_struct(g) -> Grid:
+    return Grid(int(g.nx), int(g.ny), int(g.nz), float(g.vx), float(g.vy), float(g.vz),
+                float(g.ox), float(g.oy), float(g.oz))
+
+
+def default_config() -> Config:
+    cfg = Config()
+    load_library().tvs_config_default(C.byref(cfg))
+    return cfg
+
+
+class Context:
+    """One reconstruction context (tvs_ctx): grid, histories, image and cycle state."""
+
+    def __init__(self, grid, *, block_size=3200, path_mode="otf", mlp_step_mm=0.0,
+                 mlp_log_term=True, mlp_const_power=False, chunk_histories=0,
+                 hbm_budget_bytes=0, device=0, max_tries=0, sweep_kernel=0, wave_rows=0):
+        self._L = load_library()
+        self.grid = grid
+        self.nvox = int(grid.nx) * int(grid.ny) * int(grid.nz)
+        cfg = default_config()
+        cfg.block_size = int(block_size)
+        cfg.path_mode = PATH_MODES[path_mode] if isinstance(path_mode, str) else int(path_mode)
+        cfg.mlp_step_mm = float(mlp_step_mm)
+        cfg.mlp_log_term = int(bool(mlp_log_term))
+        cfg.mlp_const_power = int(bool(mlp_const_power))
+        cfg.chunk_histories = int(chunk_histories)
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.device = int(device)
+        cfg.max_tries = int(max_tries)
+        cfg.sweep_kernel = int(sweep_kernel)
+        cfg.wave_rows = int(wave_rows)
+        self.cfg = cfg
+        h = C.c_void_p()
+        g = grid_struct(grid)
+        rc = self._L.tvs_create(C.byref(g), C.byref(cfg), C.byref(h))
+        if rc != TVS_OK:
+            raise TvsError(rc, "tvs_create: " + self._L.tvs_strerror(rc).decode())
+        self._h = h
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, rc, what):
+        if rc != TVS_OK:
+            msg = self._L.tvs_last_error(self._h).decode() or self._L.tvs_strerror(rc).decode()
+            raise TvsError(rc, f"{what}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.tvs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------ calls
+    def load_histories(self, hist: dict, stream=None):
+        n = len(hist["ex"])
+        ptrs, keep, dev = {}, [], None
+        for k in HIST_FIELDS:
+            p, d, ka = _ptr(hist[k])
+            if len(ka) != n:
+                raise ValueError("history streams differ in length")
+            if dev is None:
+                dev = d
+            elif dev != d:
+                raise ValueError("mix of host and device history streams")
+            ptrs[k] = p
+            keep.append(ka)
+        hs = Histories(*[ptrs[k] for k in HIST_FIELDS])
+        rc = self._L.tvs_load_histories(self._h, n, C.byref(hs), int(dev or 0),
+                                        _stream_handle(stream))
+        self._check(rc, "tvs_load_histories")
+
+    def set_image(self, x, stream=None):
+        p, d, keep = _ptr(x)
+        if len(keep.reshape(-1)) != self.nvox:
+            raise ValueError("image size does not match the grid")
+        self._check(self._L.tvs_set_image(self._h, p, d, _stream_handle(stream)), "tvs_set_image")
+
+    def iterate(self, K, lam, N, alpha, tv_check=False, variant="ntvs", tv_eps=0.0, seed=0,
+                gamma=0.5, stream=None):
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        p = Params(float(lam), int(N), float(alpha), int(bool(tv_check)), v, float(tv_eps),
+                   int(seed) & (2**64 - 1), float(gamma))
+        self._check(self._L.tvs_iterate(self._h, C.byref(p), int(K), _stream_handle(stream)),
+                    "tvs_iterate")
+
+    def get_image(self, out=None, stream=None):
+        if out is None:
+            out = np.zeros(self.nvox, np.float32)
+        if _is_device(out):
+            self._check(self._L.tvs_get_image(self._h, C.c_void_p(out.data_ptr()), 1,
+                                              _stream_handle(stream)), "tvs_get_image")
+            return out
+        self._check(self._L.tvs_get_image(self._h, C.c_void_p(out.ctypes.data), 0,
+                                          _stream_handle(stream)), "tvs_get_image")
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self._L.tvs_get_stats(self._h, C.byref(s)), "tvs_get_stats")
+        return {n: getattr(s, n) for n, _ in Stats._fields_}
+
+    def step_log(self) -> list:
+        n = C.c_int64(0)
+        self._check(self._L.tvs_get_step_log(self._h, None, 0, C.byref(n)), "tvs_get_step_log")
+        buf = (StepLog * max(n.value, 1))()
+        self._check(self._L.tvs_get_step_log(self._h, buf, n.value, C.byref(n)),
+                    "tvs_get_step_log")
+        return [{f: getattr(r, f) for f, _ in StepLog._fields_} for r in buf[:n.value]]
+
+    def debug_rows(self, first, count, cap=None):
+        """(row_nnz int64[count], idx int32[], chord float32[], norm2 float32[count])."""
+        rn = np.zeros(max(count, 1), np.int64)
+        n2 = np.zeros(max(count, 1), np.float32)
+        if cap is None:
+            self._L.tvs_debug_rows(self._h, first, count, rn.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   None, None, n2.ctypes.data_as(_FP), 0)
+            cap = int(rn[:count].sum())
+        idx = np.zeros(max(cap, 1), np.int32)
+        ch = np.zeros(max(cap, 1), np.float32)
+        rc = self._L.tvs_debug_rows(self._h, first, count, rn.ctypes.data_as(C.POINTER(C.c_int64)),
+                                    idx.ctypes.data_as(C.POINTER(C.c_int32)), ch.ctypes.data_as(_FP),
+                                    n2.ctypes.data_as(_FP), cap)
+        self._check(rc, "tvs_debug_rows")
+        tot = int(rn[:count].sum())
+        return rn[:count], idx[:tot], ch[:tot], n2[:count]

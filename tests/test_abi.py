@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI: the library loads and exports every entry
+point declared in include/tvs.h, and argument validation that happens before
+any device work returns the documented status codes.  No kernel runs here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1803_01112_amd import tvs
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "tvs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tvs_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(tvs.LIB):
+        from paper_1803_01112_amd import _build
+        _build.build()
+    return tvs.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(tvs.EXPORTED) == [n for n in names if n in tvs.EXPORTED]
+    assert set(names) == set(tvs.EXPORTED)
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.tvs_strerror(code).decode()
+    assert lib.tvs_strerror(12345).decode() == "unknown status"
+
+
+def test_config_defaults(lib):
+    cfg = tvs.default_config()
+    assert cfg.block_size == 3200
+    assert cfg.path_mode == 0
+    assert cfg.mlp_log_term == 1 and cfg.mlp_const_power == 0
+
+
+def test_create_rejects_bad_arguments_before_touching_the_device(lib):
+    out = C.c_void_p()
+    cfg = tvs.default_config()
+    assert lib.tvs_create(None, C.byref(cfg), C.byref(out)) == tvs.TVS_EINVAL
+    assert lib.tvs_create(C.byref(tvs.Grid(0, 4, 4, 1, 1, 1, 0, 0, 0)), C.byref(cfg),
+                          C.byref(out)) == tvs.TVS_EINVAL
+    assert lib.tvs_create(C.byref(tvs.Grid(4, 4, 4, 1, -1, 1, 0, 0, 0)), C.byref(cfg),
+                          C.byref(out)) == tvs.TVS_EINVAL
+    assert lib.tvs_create(C.byref(tvs.Grid(4, 4, 4, 1, 1, float("nan"), 0, 0, 0)), C.byref(cfg),
+                          C.byref(out)) == tvs.TVS_EINVAL
+    big = tvs.Grid(2048, 2048, 1024, 1, 1, 1, 0, 0, 0)
+    assert lib.tvs_create(C.byref(big), C.byref(cfg), C.byref(out)) == tvs.TVS_EINVAL
+    g = tvs.Grid(4, 4, 4, 1, 1, 1, 0, 0, 0)
+    bad = tvs.default_config()
+    bad.block_size = 0
+    assert lib.tvs_create(C.byref(g), C.byref(bad), C.byref(out)) == tvs.TVS_EINVAL
+    bad = tvs.default_config()
+    bad.path_mode = 7
+    assert lib.tvs_create(C.byref(g), C.byref(bad), C.byref(out)) == tvs.TVS_EINVAL
+    bad = tvs.default_config()
+    bad.wave_rows = 48
+    assert lib.tvs_create(C.byref(g), C.byref(bad), C.byref(out)) == tvs.TVS_EINVAL
+    assert out.value is None
+    assert lib.tvs_create(C.byref(g), C.byref(cfg), None) == tvs.TVS_EINVAL
+
+
+def test_null_context_calls(lib):
+    lib.tvs_destroy(None)
+    assert lib.tvs_last_error(None) == b""
+    n = C.c_int64()
+    assert lib.tvs_get_step_log(None, None, 0, C.byref(n)) == tvs.TVS_EINVAL
+    assert lib.tvs_get_stats(None, None) == tvs.TVS_EINVAL
+    assert lib.tvs_iterate(None, None, 1, None) == tvs.TVS_EINVAL
+    assert lib.tvs_load_histories(None, 0, None, 0, None) == tvs.TVS_EINVAL
