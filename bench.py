@@ -81,14 +81,15 @@ def cpu_baseline(w, args, cores):
     x0 = w.initial_image()
     t0 = time.perf_counter()
     reps = 0
-    S = None
+    x = x0
+    state = None
     while True:
         rows = oracle.build_rows(w.grid, h, min(w.grid.vx, w.grid.vy))
-        if S is None:
-            S = oracle.Superiorizer(w.grid, rows, x0, args.block)
-        else:
-            S.rows = rows
+        S = oracle.Superiorizer(w.grid, rows, x, args.block)
+        if state is not None:
+            S.state = state
         S.iterate(1, args.lam, args.N, args.alpha, tv_check=args.check, seed=args.seed)
+        x, state = S.x.copy(), S.state
         reps += 1
         el = time.perf_counter() - t0
         if el > args.cpu_seconds or reps >= 20:

@@ -138,6 +138,10 @@ typedef struct {
     int64_t cycles_timed;  /* cycles of the call */
     int64_t rows_launches; /* row-formation launches of the call */
     int64_t drop_launches; /* DROP launches (persistent) or per-block launch pairs' spans */
+    double batch_ms_total; /* cycles of the last tvs_iterate_batch call */
+    int64_t batch_cycles;  /* cycles of that call */
+    int32_t batch_size;    /* S of the current batch (0: none) */
+    int32_t pad;
 } tvs_stats;
 
 /* One record per perturbation step (Appendix C; checked steps record TV). */
@@ -185,6 +189,25 @@ int tvs_iterate(tvs_ctx *ctx, const tvs_params *p, int32_t K, void *stream);
 /* Copies the current image (nx*ny*nz floats) to out (host or device). */
 int tvs_get_image(tvs_ctx *ctx, float *out, int on_device, void *stream);
 
+/* Batched reconstructions: S settings of the loaded histories (a parameter
+ * study over lambda, N, alpha as in Section III-E), each with its own
+ * tvs_params and all starting from the image set by tvs_set_image, advanced
+ * K cycles together.  Every cycle reads each row once and applies it to all
+ * S images; the launches of one cycle are captured in a hipGraph and
+ * replayed for every cycle.  Unchecked schedules only (TVS_NTVS with
+ * tv_check = 0, or TVS_DECOUPLED); 1 <= S <= 32; p points to S parameter
+ * sets.  A call with the same S and parameters as the previous one
+ * continues those reconstructions; otherwise they restart from the initial
+ * image.  The main image (tvs_iterate / tvs_get_image) is not touched.
+ * Waits for the work before returning.  TVS_EINVAL for an invalid setting,
+ * TVS_ESTATE before tvs_load_histories, TVS_ENOMEM when the S images do not
+ * fit the budget. */
+int tvs_iterate_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, int32_t K, void *stream);
+
+/* Copies image s (0 <= s < S) of the current batch to out (host or device);
+ * TVS_ERANGE for s outside the batch, TVS_ESTATE without a batch. */
+int tvs_get_batch_image(tvs_ctx *ctx, int32_t s, float *out, int on_device, void *stream);
+
 /* Counters and timings of the context. */
 int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out);
 
@@ -200,6 +223,81 @@ int tvs_get_step_log(tvs_ctx *ctx, tvs_step_log *out, int64_t cap, int64_t *n);
  * (row_nnz is still filled then). */
 int tvs_debug_rows(tvs_ctx *ctx, int64_t first, int64_t count, int64_t *row_nnz, int32_t *idx,
                    float *chord, float *norm2, int64_t cap);
+
+/* ------------------------------------------------------------------------
+ * Serving: a continuous-batching server of reconstruction requests.
+ * Requests queue in arrival order and are admitted first-in first-out when
+ * a slot is free and their device-memory footprint fits under the server's
+ * HBM budget together with the running requests.  Each admitted request
+ * runs on its own context and stream (one worker thread per slot), so
+ * requests overlap on the device; a request that arrives while others run
+ * starts as soon as a slot and memory free up.  A failing request fails
+ * alone.  With `simulate` set no device work is done: a request sleeps
+ * sim_ns_per_history_cycle * n * K nanoseconds (for testing the policy).
+ * ------------------------------------------------------------------------ */
+typedef struct tvs_server tvs_server;
+
+typedef struct {
+    int32_t device;
+    int32_t max_active;         /* requests running at once, 1..16 (default 3) */
+    uint64_t hbm_budget_bytes;  /* bound on the sum of admitted footprints; 0: 80 % of free */
+    int64_t chunk_histories;    /* on-the-fly row chunk of each request (default 262144) */
+    int32_t simulate;           /* 1: no device work (policy testing); needs a budget */
+    int32_t pad;
+    double sim_ns_per_history_cycle;
+} tvs_server_config;
+
+/* One reconstruction request.  The history arrays are host memory borrowed
+ * until the request completes (tvs_server_wait returned or the server was
+ * destroyed); x0 (nx*ny*nz floats, or NULL for zeros) is copied at submit. */
+typedef struct {
+    tvs_grid grid;
+    int32_t block_size;         /* <= 0: 3200 */
+    int32_t path_mode;          /* enum tvs_path_mode */
+    tvs_params params;
+    int32_t K;                  /* cycles */
+    int32_t pad;
+    int64_t n;
+    tvs_histories h;
+    const float *x0;
+} tvs_request;
+
+typedef struct {
+    int32_t state;              /* 0 queued, 1 running, 2 done, 3 failed */
+    int32_t status;             /* TVS_* status of a finished request */
+    double submit_ms, admit_ms, done_ms;  /* steady-clock ms since the server started */
+    uint64_t bytes;             /* footprint reserved while running */
+    int64_t admit_order;        /* 1-based admission rank */
+} tvs_request_info;
+
+typedef struct {
+    uint64_t budget_bytes, in_use_bytes, peak_bytes;
+    int32_t active, peak_active, queued, pad;
+    int64_t completed, failed;
+} tvs_server_counters;
+
+/* Fills *cfg with defaults (device 0, 3 slots, budget 80 % of free memory). */
+void tvs_server_config_default(tvs_server_config *cfg);
+/* Starts the worker threads.  TVS_EINVAL for max_active outside 1..16 or a
+ * simulated server without a budget; TVS_EDEVICE if the device is unusable. */
+int tvs_server_create(const tvs_server_config *cfg, tvs_server **out);
+/* Device bytes reserved for a request (history streams, row lengths, row
+ * buffers of one chunk or the whole store, image buffers); an upper
+ * estimate that also bounds the request's own context. */
+uint64_t tvs_server_footprint(const tvs_server *sv, const tvs_request *r);
+/* Queues a request; *id receives its handle.  TVS_EINVAL for a bad grid or
+ * sizes, TVS_ENOMEM when its footprint alone exceeds the budget. */
+int tvs_server_submit(tvs_server *sv, const tvs_request *r, int64_t *id);
+/* State of a request without waiting. */
+int tvs_server_query(tvs_server *sv, int64_t id, tvs_request_info *info);
+/* Waits for the request; copies its image (image_len >= nx*ny*nz floats, or
+ * image = NULL) and info.  Returns the request's status. */
+int tvs_server_wait(tvs_server *sv, int64_t id, float *image, int64_t image_len,
+                    tvs_request_info *info);
+int tvs_server_get_counters(tvs_server *sv, tvs_server_counters *out);
+/* Lets running requests finish, fails queued ones (TVS_ESTATE), joins the
+ * workers and frees the server. */
+void tvs_server_destroy(tvs_server *sv);
 
 /* Static description of a status code. */
 const char *tvs_strerror(int status);

@@ -22,6 +22,7 @@ SOURCES = {
     "rows.hip": ["-ffp-contract=off"],
     "drop.hip": [],
     "tv.hip": ["-ffp-contract=off"],
+    "batch.hip": ["-ffp-contract=off"],
     "tvs_api.cpp": ["-x", "hip"],
 }
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",

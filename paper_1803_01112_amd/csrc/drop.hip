@@ -12,7 +12,7 @@
 // chord).  A group of LPR lanes (a wavefront for LPR = 64) reads one row
 // coalesced, gathers x (float64), reduces the dot product in float64 with
 // cross-lane shuffles,
-// and scatters r a_ij / 1 with hardware float / integer atomics.  The first
+// and scatters r a_ij / 1 with hardware float64 / integer atomics.  The first
 // hit of a voxel in a block appends it to a touched list (one atomic per
 // wavefront), so the apply phase visits only touched voxels and clears them.
 //
@@ -20,49 +20,22 @@
 // per sweep with a device-wide barrier between phases.  The barrier spins a
 // bounded number of times; on timeout it raises an error flag that makes
 // every workgroup leave, and the host reports a device error.
+#include "device_common.hpp"
 #include "tvs_internal.hpp"
 
 namespace tvs {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr uint32_t kSpinLimit = 1u << 22;
-
-template <typename CH>
-__device__ inline float chord_at(const CH *p, int64_t e)
-{
-    if constexpr (sizeof(CH) == 4) return p[e];
-    else return __half2float(p[e]);
-}
-
-template <int LPR>
-__device__ inline double group_sum(double v)
-{
-#pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Appends j to the touched list when `first` (wavefront-aggregated).
-__device__ inline void append_touched(bool first, int32_t j, int32_t *touched, uint32_t *cnt)
-{
-    unsigned long long m = __ballot(first);
-    if (m == 0) return;
-    int lane = threadIdx.x & 63;
-    int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(m));
-    base = __shfl(base, leader, 64);
-    if (first) {
-        unsigned long long below = m & ((1ull << lane) - 1ull);
-        touched[base + (uint32_t)__popcll(below)] = j;
-    }
-}
+using dev::append_touched;
+using dev::chord_at;
+using dev::grid_barrier;
+using dev::group_sum;
 
 // One row: dot, residual, scatter.  All LPR lanes of the group call it.
 template <int LPR, typename CH>
 __device__ inline void drop_row(const RowSet &rs, const CH *chord, const float *wepl, int64_t row,
-                                const double *x, float *c, uint32_t *s, int32_t *touched,
+                                const double *x, double *c, uint32_t *s, int32_t *touched,
                                 uint32_t *cnt)
 {
     const int lane = threadIdx.x & (LPR - 1);
@@ -74,7 +47,7 @@ __device__ inline void drop_row(const RowSet &rs, const CH *chord, const float *
         for (int64_t e = off + lane; e < end; e += LPR)
             acc += (double)chord_at(chord, e) * x[rs.idx[e]];
     acc = group_sum<LPR>(acc);
-    const float r = (n2 > 0.0f) ? (float)(((double)wepl[row] - acc) / (double)n2) : 0.0f;
+    const double r = (n2 > 0.0f) ? ((double)wepl[row] - acc) / (double)n2 : 0.0;
     const int64_t trips = (n2 > 0.0f) ? (end - off + LPR - 1) / LPR : 0;
     // Uniform trip count inside the group so the wavefront-wide ballot sees
     // every lane of the group.
@@ -84,7 +57,7 @@ __device__ inline void drop_row(const RowSet &rs, const CH *chord, const float *
         int32_t j = 0;
         if (e < end) {
             j = rs.idx[e];
-            unsafeAtomicAdd(c + j, r * chord_at(chord, e));
+            unsafeAtomicAdd(c + j, r * (double)chord_at(chord, e));
             first = (atomicAdd(s + j, 1u) == 0u);
         }
         append_touched(first, j, touched, cnt);
@@ -94,24 +67,24 @@ __device__ inline void drop_row(const RowSet &rs, const CH *chord, const float *
 template <int LPR, typename CH>
 __global__ void __launch_bounds__(kThreads)
 k_drop_rows(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1, const double *x,
-            float *c, uint32_t *s, int32_t *touched, uint32_t *cnt)
+            double *c, uint32_t *s, int32_t *touched, uint32_t *cnt)
 {
     const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
     if (row >= r1) return;   // groups never straddle a wavefront boundary
     drop_row<LPR, CH>(rs, chord, wepl, row, x, c, s, touched, cnt);
 }
 
-__device__ inline void apply_voxel(int32_t j, double lambda, double *x, float *c, uint32_t *s)
+__device__ inline void apply_voxel(int32_t j, double lambda, double *x, double *c, uint32_t *s)
 {
-    float cj = c[j];
+    double cj = c[j];
     uint32_t sj = s[j];
-    x[j] += lambda * (double)cj / (double)sj;
-    c[j] = 0.0f;
+    x[j] += lambda * cj / (double)sj;
+    c[j] = 0.0;
     s[j] = 0u;
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_drop_apply(double lambda, double *x, float *c, uint32_t *s, const int32_t *touched,
+k_drop_apply(double lambda, double *x, double *c, uint32_t *s, const int32_t *touched,
              const uint32_t *cnt, uint32_t *cnt_next)
 {
     const uint32_t n = *cnt;
@@ -125,48 +98,10 @@ __global__ void k_zero_counters(uint32_t *cnt)
     if (threadIdx.x < 2) cnt[threadIdx.x] = 0u;
 }
 
-// Sense-free grid barrier: bar[0] = arrivals, bar[1] = generation,
-// bar[2] = error flag.  The last arriving workgroup resets the count and
-// bumps the generation; the others wait for the generation to change.
-__device__ inline bool grid_barrier(uint32_t *bar)
-{
-    __shared__ uint32_t ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t good = 1;
-        __threadfence();
-        uint32_t gen = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_AGENT) + 1u;
-        if (arrived == gridDim.x) {
-            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            uint32_t spins = 0;
-            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                    good = 0;
-                    break;
-                }
-                if (++spins > kSpinLimit) {
-                    __hip_atomic_store(bar + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    good = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        __threadfence();
-        ok = good;
-    }
-    __syncthreads();
-    return ok != 0u;
-}
-
 template <int LPR, typename CH>
 __global__ void __launch_bounds__(kThreads)
 k_drop_persistent(RowSet rs, const CH *chord, const float *wepl, int64_t block_size, double lambda,
-                  double *x, float *c, uint32_t *s, int32_t *touched, uint32_t *cnt, uint32_t *bar)
+                  double *x, double *c, uint32_t *s, int32_t *touched, uint32_t *cnt, uint32_t *bar)
 {
     const int64_t groups = (int64_t)gridDim.x * (kThreads / LPR);
     const int64_t gid = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;

@@ -63,9 +63,8 @@ struct tvs_ctx {
     uint64_t bytes = 0;
     std::string err;
 
-    // image-side buffers (image and subgradient float64; corrections float32)
-    double *x = nullptr, *g = nullptr;
-    float *c = nullptr;
+    // image-side buffers (image, subgradient and corrections float64)
+    double *x = nullptr, *g = nullptr, *c = nullptr;
     float *xio = nullptr;           // float32 staging of the image at the ABI
     uint32_t *s = nullptr;
     int32_t *touched = nullptr;
@@ -106,6 +105,24 @@ struct tvs_ctx {
     int64_t tot_n[4] = {0, 0, 0, 0};
     int lpr = 64;
     int pgrid = 0;
+
+    // initial iterate (float64), the starting image of batches
+    double *x0 = nullptr;
+
+    // batched reconstructions
+    struct Batch {
+        int S = 0;
+        bool valid = false;
+        std::vector<tvs_params> p;
+        tvs::BatchBuffers b;
+        int64_t k = 0;
+        std::vector<int64_t> ell;
+        std::vector<uint64_t> rng;
+        int64_t beta_cap = 0;
+        int grid = 0;
+        double ms_total = 0;
+        int64_t cycles = 0;
+    } batch;
 };
 
 namespace {
@@ -178,6 +195,23 @@ void free_histories(tvs_ctx *ctx)
     ctx->nh = 0;
     ctx->nnz = ctx->max_row = ctx->skipped = 0;
     ctx->chunk_base.clear();
+}
+
+void free_batch(tvs_ctx *ctx)
+{
+    auto &B = ctx->batch;
+    const size_t n = (size_t)(ctx->nvox * B.S);
+    dfree(ctx, &B.b.x, n);
+    dfree(ctx, &B.b.g, n);
+    dfree(ctx, &B.b.c, n);
+    dfree(ctx, &B.b.part, (size_t)(tvs::batch_num_parts(ctx->gd, std::max(B.S, 1)) * B.S));
+    dfree(ctx, &B.b.ticket, (size_t)4);
+    dfree(ctx, &B.b.norm2, (size_t)B.S);
+    dfree(ctx, &B.b.lambda, (size_t)B.S);
+    dfree(ctx, &B.b.eps, (size_t)B.S);
+    dfree(ctx, &B.b.beta_tab, (size_t)B.beta_cap);
+    dfree(ctx, &B.b.cyc, (size_t)4);
+    B = tvs_ctx::Batch();
 }
 
 HistDev hist_dev(const tvs_ctx *ctx)
@@ -368,6 +402,8 @@ void tvs_destroy(tvs_ctx *ctx)
     (void)hipSetDevice(ctx->cfg.device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     free_histories(ctx);
+    free_batch(ctx);
+    dfree(ctx, &ctx->x0, (size_t)ctx->nvox);
     dfree(ctx, &ctx->x, (size_t)ctx->nvox);
     dfree(ctx, &ctx->xio, (size_t)ctx->nvox);
     dfree(ctx, &ctx->c, (size_t)ctx->nvox);
@@ -432,6 +468,7 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     int rc = TVS_OK;
     ctx->nparts = tvs::tv_num_parts(ctx->gd);
     if (!rc) rc = dalloc(ctx, &ctx->x, (size_t)nvox);
+    if (!rc) rc = dalloc(ctx, &ctx->x0, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->xio, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->c, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->g, (size_t)nvox);
@@ -451,7 +488,8 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemsetAsync(ctx->x, 0, sizeof(double) * nvox, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->c, 0, sizeof(float) * nvox, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->x0, 0, sizeof(double) * nvox, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->c, 0, sizeof(double) * nvox, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->s, 0, sizeof(uint32_t) * nvox, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->ntouched, 0, sizeof(uint32_t) * 8, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->ticket, 0, sizeof(uint32_t) * 4, ctx->stream);
@@ -489,6 +527,8 @@ int tvs_load_histories(tvs_ctx *ctx, int64_t n, const tvs_histories *h, int on_d
     free_histories(ctx);
     reset_state(ctx);
     HIPCHK(hipMemsetAsync(ctx->x, 0, sizeof(double) * ctx->nvox, st));
+    HIPCHK(hipMemsetAsync(ctx->x0, 0, sizeof(double) * ctx->nvox, st));
+    ctx->batch.valid = false;
     ctx->nh = n;
 
     int rc = dalloc(ctx, &ctx->hist, (size_t)(kNumStreams * n));
@@ -599,8 +639,10 @@ int tvs_set_image(tvs_ctx *ctx, const float *x0, int on_device, void *stream)
     HIPCHK(hipMemcpyAsync(ctx->xio, x0, sizeof(float) * ctx->nvox,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     HIPCHK(tvs::launch_widen(ctx->xio, ctx->x, ctx->nvox, st));
+    HIPCHK(hipMemcpyAsync(ctx->x0, ctx->x, sizeof(double) * ctx->nvox, hipMemcpyDeviceToDevice, st));
     if (!on_device) HIPCHK(hipStreamSynchronize(st));
     reset_state(ctx);
+    ctx->batch.valid = false;
     return TVS_OK;
 }
 
@@ -762,6 +804,10 @@ int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out)
     out->cycles_timed = ctx->tot_n[1];
     out->rows_launches = ctx->tot_n[2];
     out->drop_launches = ctx->tot_n[3];
+    out->batch_ms_total = ctx->batch.ms_total;
+    out->batch_cycles = ctx->batch.cycles;
+    out->batch_size = ctx->batch.valid ? ctx->batch.S : 0;
+    out->pad = 0;
     return TVS_OK;
 }
 
@@ -832,6 +878,216 @@ int tvs_debug_rows(tvs_ctx *ctx, int64_t first, int64_t count, int64_t *row_nnz,
     dfree(ctx, &dn, (size_t)count);
     dfree(ctx, &off, (size_t)(count + 1));
     return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+bool same_params(const tvs_params &a, const tvs_params &b)
+{
+    return a.lambda == b.lambda && a.N == b.N && a.alpha == b.alpha && a.tv_check == b.tv_check &&
+           a.variant == b.variant && a.tv_eps == b.tv_eps && a.seed == b.seed &&
+           (a.variant != TVS_DECOUPLED || a.gamma == b.gamma);
+}
+
+// (Re)allocates the S-image buffers and starts every setting from x0.
+int batch_init(tvs_ctx *ctx, const tvs_params *p, int S, hipStream_t st)
+{
+    auto &B = ctx->batch;
+    if (B.S != S) {
+        free_batch(ctx);
+        B.S = S;
+        const size_t n = (size_t)(ctx->nvox * S);
+        int rc = dalloc(ctx, &B.b.x, n);
+        if (!rc) rc = dalloc(ctx, &B.b.g, n);
+        if (!rc) rc = dalloc(ctx, &B.b.c, n);
+        if (!rc) rc = dalloc(ctx, &B.b.part, (size_t)(tvs::batch_num_parts(ctx->gd, S) * S));
+        if (!rc) rc = dalloc(ctx, &B.b.ticket, (size_t)4);
+        if (!rc) rc = dalloc(ctx, &B.b.norm2, (size_t)S);
+        if (!rc) rc = dalloc(ctx, &B.b.lambda, (size_t)S);
+        if (!rc) rc = dalloc(ctx, &B.b.eps, (size_t)S);
+        if (!rc) rc = dalloc(ctx, &B.b.cyc, (size_t)4);
+        if (rc) {
+            free_batch(ctx);
+            return rc;
+        }
+        B.b.S = S;
+        B.b.nvox = ctx->nvox;
+        B.grid = tvs::batch_grid_size(ctx->cfg.device, S);
+        if (B.grid <= 0) {
+            free_batch(ctx);
+            return fail(ctx, TVS_EDEVICE, "no occupancy for the batched sweep");
+        }
+        HIPCHK(hipMemsetAsync(B.b.ticket, 0, sizeof(uint32_t) * 4, st));
+    }
+    B.b.s = ctx->s;
+    B.b.touched = ctx->touched;
+    B.b.ntouched = ctx->ntouched;
+    B.b.barrier = ctx->ntouched + 2;
+    B.p.assign(p, p + S);
+    std::vector<double> lam(S), eps(S);
+    for (int q = 0; q < S; q++) {
+        lam[q] = p[q].lambda;
+        eps[q] = p[q].tv_eps;
+    }
+    HIPCHK(hipMemcpyAsync(B.b.lambda, lam.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B.b.eps, eps.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+    HIPCHK(tvs::launch_replicate(ctx->x0, B.b, st));
+    HIPCHK(hipStreamSynchronize(st));
+    B.k = 0;
+    B.ell.assign(S, 0);
+    B.rng.assign(S, 0);
+    for (int q = 0; q < S; q++) B.rng[q] = p[q].seed;
+    B.valid = true;
+    return TVS_OK;
+}
+
+// Enqueues the launches of one batched cycle (captured into a graph).
+int batch_cycle(tvs_ctx *ctx, int nmax, hipStream_t st)
+{
+    auto &B = ctx->batch;
+    for (int n = 0; n < nmax; n++) {
+        uint32_t active = 0;
+        for (int q = 0; q < B.S; q++)
+            if (B.p[q].N > n) active |= 1u << q;
+        HIPCHK(tvs::launch_tvb_grad(ctx->gd, B.b, active, st));
+        HIPCHK(tvs::launch_tvb_step(B.b, active, n, nmax, st));
+    }
+    const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
+    const int64_t step = otf ? ctx->chunk : ctx->nh;
+    const float *wepl = ctx->hist + 12 * ctx->nh;
+    for (int64_t first = 0, q = 0; first < ctx->nh; first += step, q++) {
+        const int64_t n = std::min(step, ctx->nh - first);
+        RowSet rs = rowset(ctx, first, n, otf ? ctx->chunk_base[q] : 0);
+        if (otf) HIPCHK(tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rs, st));
+        HIPCHK(tvs::launch_drop_batch(rs, wepl, ctx->cfg.block_size, B.b, B.grid, st));
+    }
+    HIPCHK(tvs::launch_tick(B.b.cyc, st));
+    return TVS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tvs_iterate_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, int32_t K, void *stream)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    if (S < 1 || S > 32) return fail(ctx, TVS_EINVAL, "batch size must lie in [1, 32]");
+    if (!p) return fail(ctx, TVS_EINVAL, "params is NULL");
+    if (K < 0) return fail(ctx, TVS_EINVAL, "K must be >= 0");
+    for (int q = 0; q < S; q++) {
+        int rc = validate_params(ctx, p + q);
+        if (rc) return rc;
+        if (p[q].variant == TVS_OTVS || (p[q].variant == TVS_NTVS && p[q].tv_check))
+            return fail(ctx, TVS_EINVAL, "batches take unchecked schedules only");
+    }
+    if (!ctx->loaded) return fail(ctx, TVS_ESTATE, "tvs_iterate_batch before tvs_load_histories");
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    auto &B = ctx->batch;
+    bool same = B.valid && B.S == S;
+    for (int q = 0; same && q < S; q++) same = same_params(B.p[q], p[q]);
+    if (!same) {
+        int rc = batch_init(ctx, p, S, st);
+        if (rc) return rc;
+    }
+    B.ms_total = 0;
+    B.cycles = 0;
+    if (K == 0) return TVS_OK;
+
+    // beta of every (cycle, step, setting) of this call, drawn on the host
+    int nmax = 0;
+    for (int q = 0; q < S; q++) nmax = std::max(nmax, (int)p[q].N);
+    const int64_t need = std::max<int64_t>((int64_t)K * std::max(nmax, 1) * S, 1);
+    if (need > B.beta_cap) {
+        dfree(ctx, &B.b.beta_tab, (size_t)B.beta_cap);
+        B.beta_cap = 0;
+        int rc = dalloc(ctx, &B.b.beta_tab, (size_t)need);
+        if (rc) return rc;
+        B.beta_cap = need;
+    }
+    std::vector<double> beta((size_t)need, 0.0);
+    for (int32_t kk = 0; kk < K; kk++) {
+        const int64_t k = B.k + kk;
+        for (int q = 0; q < S; q++) {
+            if (p[q].variant == TVS_NTVS) B.ell[q] = draw_ell(k, B.ell[q], B.rng[q]);
+            for (int n = 0; n < p[q].N; n++) {
+                double b = (p[q].variant == TVS_DECOUPLED)
+                               ? std::pow(p[q].alpha, (double)(n + 1)) * std::pow(p[q].gamma, (double)k)
+                               : std::pow(p[q].alpha, (double)B.ell[q]);
+                beta[((size_t)kk * nmax + n) * S + q] = b;
+                B.ell[q] += 1;
+            }
+        }
+    }
+    B.k += K;
+    HIPCHK(hipMemcpyAsync(B.b.beta_tab, beta.data(), sizeof(double) * need, hipMemcpyHostToDevice, st));
+    HIPCHK(tvs::launch_set_counter(B.b.cyc, 0, st));
+
+    // capture one cycle, replay it K times
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    int rc = batch_cycle(ctx, nmax, st);
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ce != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+    ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ce != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(ctx, TVS_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ce));
+    }
+    std::vector<long> ev;
+    ev.push_back(mark(ctx, st));
+    for (int32_t kk = 0; kk < K && ce == hipSuccess; kk++) {
+        ce = hipGraphLaunch(exec, st);
+        ev.push_back(mark(ctx, st));
+    }
+    hipError_t se = hipStreamSynchronize(st);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (ce != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("graph launch: ") + hipGetErrorString(ce));
+    if (se != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("batch sync: ") + hipGetErrorString(se));
+    for (size_t q = 1; q < ev.size(); q++) {
+        float ms = 0;
+        if (ev[q - 1] >= 0 && ev[q] >= 0 &&
+            hipEventElapsedTime(&ms, ctx->tev[(size_t)ev[q - 1]], ctx->tev[(size_t)ev[q]]) == hipSuccess)
+            B.ms_total += ms;
+    }
+    B.cycles = K;
+    ctx->tev_used = 0;
+    ctx->spans.clear();
+    ctx->timed = false;
+    uint32_t flag = 0;
+    HIPCHK(hipMemcpy(&flag, ctx->ntouched + 4, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (flag) {
+        HIPCHK(hipMemset(ctx->ntouched, 0, sizeof(uint32_t) * 5));
+        B.valid = false;
+        return fail(ctx, TVS_EDEVICE, "batched sweep grid barrier timed out");
+    }
+    return TVS_OK;
+}
+
+int tvs_get_batch_image(tvs_ctx *ctx, int32_t s, float *out, int on_device, void *stream)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    if (!out) return fail(ctx, TVS_EINVAL, "output is NULL");
+    if (!ctx->batch.valid) return fail(ctx, TVS_ESTATE, "no batch");
+    if (s < 0 || s >= ctx->batch.S) return fail(ctx, TVS_ERANGE, "setting outside the batch");
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    HIPCHK(tvs::launch_extract(ctx->batch.b, s, ctx->xio, st));
+    HIPCHK(hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nvox,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    if (!on_device) HIPCHK(hipStreamSynchronize(st));
+    return TVS_OK;
 }
 
 }  // extern "C"

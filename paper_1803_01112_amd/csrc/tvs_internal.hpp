@@ -68,7 +68,7 @@ hipError_t launch_scan(const int32_t *cnt, int64_t n, int64_t *off, int64_t *tmp
 struct DropBuffers {
     double *x;           // image (float64: keeps the small DROP increments exact
                          // enough for the scale-free TV subgradient)
-    float *c;            // correction sums
+    double *c;           // correction sums (float64: see DESIGN, image precision)
     uint32_t *s;         // hit counts
     int32_t *touched;    // voxels touched by the current block (capacity nvox)
     uint32_t *ntouched;  // two counters used alternately by consecutive blocks
@@ -113,5 +113,39 @@ hipError_t launch_tv_phi(const GridDev &g, const double *x, double beta, double 
 hipError_t launch_widen(const float *src, double *dst, int64_t n, hipStream_t stream);
 hipError_t launch_narrow(const double *src, float *dst, int64_t n, hipStream_t stream);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream);
+
+// ----------------------------------------------------------------- batch.hip
+// S images interleaved by voxel (x[p*S + s]); hit counts and the touched list
+// are shared by all settings.
+struct BatchBuffers {
+    int S = 0;
+    int64_t nvox = 0;
+    double *x = nullptr;        // nvox * S
+    double *g = nullptr;        // nvox * S
+    double *c = nullptr;        // nvox * S
+    uint32_t *s = nullptr;      // nvox (shared)
+    int32_t *touched = nullptr; // nvox (shared)
+    uint32_t *ntouched = nullptr, *barrier = nullptr;
+    double *part = nullptr;     // batch_num_parts * S
+    uint32_t *ticket = nullptr;
+    double *norm2 = nullptr;    // S
+    double *lambda = nullptr;   // S
+    double *eps = nullptr;      // S
+    double *beta_tab = nullptr; // cycles * nmax * S
+    int32_t *cyc = nullptr;     // device cycle counter
+};
+int batch_vox_per_wg(int S);
+int64_t batch_num_parts(const GridDev &g, int S);
+int batch_grid_size(int device, int S);
+hipError_t launch_tvb_grad(const GridDev &g, const BatchBuffers &b, uint32_t active,
+                           hipStream_t stream);
+hipError_t launch_tvb_step(const BatchBuffers &b, uint32_t active, int n, int nmax,
+                           hipStream_t stream);
+hipError_t launch_set_counter(int32_t *cyc, int32_t v, hipStream_t stream);
+hipError_t launch_tick(int32_t *cyc, hipStream_t stream);
+hipError_t launch_replicate(const double *x0, const BatchBuffers &b, hipStream_t stream);
+hipError_t launch_extract(const BatchBuffers &b, int s, float *out, hipStream_t stream);
+hipError_t launch_drop_batch(const RowSet &rs, const float *wepl, int64_t block_size,
+                             const BatchBuffers &b, int grid_wgs, hipStream_t stream);
 
 }  // namespace tvs

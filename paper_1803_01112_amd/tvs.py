@@ -23,7 +23,8 @@ VARIANTS = {"ntvs": 0, "otvs": 1, "decoupled": 2}
 
 EXPORTED = ("tvs_config_default", "tvs_create", "tvs_destroy", "tvs_load_histories",
             "tvs_set_image", "tvs_iterate", "tvs_get_image", "tvs_get_stats", "tvs_get_step_log",
-            "tvs_debug_rows", "tvs_strerror", "tvs_last_error")
+            "tvs_debug_rows", "tvs_strerror", "tvs_last_error", "tvs_iterate_batch",
+            "tvs_get_batch_image")
 
 
 class TvsError(RuntimeError):
@@ -67,7 +68,9 @@ class Stats(C.Structure):
                 ("device_bytes", C.c_uint64), ("tv_ms_total", C.c_double),
                 ("sweep_ms_total", C.c_double), ("rows_ms_total", C.c_double),
                 ("drop_ms_total", C.c_double), ("cycles_timed", C.c_int64),
-                ("rows_launches", C.c_int64), ("drop_launches", C.c_int64)]
+                ("rows_launches", C.c_int64), ("drop_launches", C.c_int64),
+                ("batch_ms_total", C.c_double), ("batch_cycles", C.c_int64),
+                ("batch_size", C.c_int32), ("pad", C.c_int32)]
 
 
 class StepLog(C.Structure):
@@ -98,6 +101,8 @@ def load_library(path: str = LIB):
     L.tvs_iterate.argtypes = [C.c_void_p, P(Params), C.c_int32, C.c_void_p]
     L.tvs_get_image.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     L.tvs_get_stats.argtypes = [C.c_void_p, P(Stats)]
+    L.tvs_iterate_batch.argtypes = [C.c_void_p, P(Params), C.c_int32, C.c_int32, C.c_void_p]
+    L.tvs_get_batch_image.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int, C.c_void_p]
     L.tvs_get_step_log.argtypes = [C.c_void_p, P(StepLog), C.c_int64, P(C.c_int64)]
     L.tvs_debug_rows.argtypes = [C.c_void_p, C.c_int64, C.c_int64, P(C.c_int64), P(C.c_int32),
                                  _FP, _FP, C.c_int64]
@@ -106,7 +111,8 @@ def load_library(path: str = LIB):
     L.tvs_last_error.argtypes = [C.c_void_p]
     L.tvs_last_error.restype = C.c_char_p
     for name in ("tvs_create", "tvs_load_histories", "tvs_set_image", "tvs_iterate",
-                 "tvs_get_image", "tvs_get_stats", "tvs_get_step_log", "tvs_debug_rows"):
+                 "tvs_get_image", "tvs_get_stats", "tvs_get_step_log", "tvs_debug_rows",
+                 "tvs_iterate_batch", "tvs_get_batch_image"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -230,6 +236,31 @@ class Context:
                    int(seed) & (2**64 - 1), float(gamma))
         self._check(self._L.tvs_iterate(self._h, C.byref(p), int(K), _stream_handle(stream)),
                     "tvs_iterate")
+
+    def iterate_batch(self, K, settings, stream=None):
+        """K cycles of S settings together; settings: list of dicts with keys
+        lam, N, alpha and optionally variant, tv_eps, seed, gamma."""
+        S = len(settings)
+        arr = (Params * max(S, 1))()
+        for q, st in enumerate(settings):
+            v = st.get("variant", "ntvs")
+            v = VARIANTS[v] if isinstance(v, str) else int(v)
+            arr[q] = Params(float(st["lam"]), int(st["N"]), float(st["alpha"]),
+                            int(bool(st.get("tv_check", False))), v, float(st.get("tv_eps", 0.0)),
+                            int(st.get("seed", 0)) & (2**64 - 1), float(st.get("gamma", 0.5)))
+        self._check(self._L.tvs_iterate_batch(self._h, arr, S, int(K), _stream_handle(stream)),
+                    "tvs_iterate_batch")
+
+    def get_batch_image(self, s, out=None, stream=None):
+        if out is None:
+            out = np.zeros(self.nvox, np.float32)
+        if _is_device(out):
+            self._check(self._L.tvs_get_batch_image(self._h, int(s), C.c_void_p(out.data_ptr()), 1,
+                                                    _stream_handle(stream)), "tvs_get_batch_image")
+            return out
+        self._check(self._L.tvs_get_batch_image(self._h, int(s), C.c_void_p(out.ctypes.data), 0,
+                                                _stream_handle(stream)), "tvs_get_batch_image")
+        return out
 
     def get_image(self, out=None, stream=None):
         if out is None:
