@@ -76,7 +76,9 @@ typedef struct {
     uint64_t hbm_budget_bytes; /* 0: 80 % of the device memory free at tvs_create */
     int32_t device;          /* HIP device ordinal */
     int32_t max_tries;       /* bound on the retries of one checked TV step; 0: 100000 */
-    int32_t sweep_kernel;    /* 0: auto; 1: one launch per block phase; 2: persistent */
+    int32_t sweep_kernel;    /* 0 or 1: one launch per block phase (path stores: voxel-major
+                                apply without atomics); 2: one persistent launch per sweep
+                                with device-wide barriers and atomic scatter */
     int32_t wave_rows;       /* lanes per row in the DROP row kernels (8..64); 0: auto */
 } tvs_config;
 

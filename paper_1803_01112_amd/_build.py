@@ -23,6 +23,8 @@ SOURCES = {
     "drop.hip": [],
     "tv.hip": ["-ffp-contract=off"],
     "batch.hip": ["-ffp-contract=off"],
+    "csc.hip": [],
+    "serve.cpp": ["-x", "hip"],
     "tvs_api.cpp": ["-x", "hip"],
 }
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",

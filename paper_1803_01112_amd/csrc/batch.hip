@@ -231,6 +231,60 @@ k_drop_batch(RowSet rs, const CH *chord, const float *wepl, int64_t block_size, 
     }
 }
 
+// ------------------------------------------------------------- voxel-major form
+// Residuals r[q*S + s] of the rows [r0, r1) for every setting: one wavefront
+// per row, S float64 dot products over the row's entries.
+template <int SMAX, typename CH>
+__global__ void __launch_bounds__(kThreads)
+k_batch_resid(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1, int S,
+              const double *x, double *rbuf)
+{
+    const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 64;
+    if (row >= r1) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t lr = row - rs.first;
+    const float n2 = rs.norm2[lr];
+    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
+    double acc[SMAX];
+#pragma unroll
+    for (int k = 0; k < SMAX; k++) acc[k] = 0.0;
+    for (int64_t e = off + lane; e < end; e += 64) {
+        const double ch = (double)chord_at(chord, e);
+        const double *xp = x + (int64_t)rs.idx[e] * S;
+#pragma unroll
+        for (int k = 0; k < SMAX; k++)
+            if (k < S) acc[k] += ch * xp[k];
+    }
+    const double b = (double)wepl[row];
+    double *rp = rbuf + (row - r0) * S;
+#pragma unroll
+    for (int k = 0; k < SMAX; k++) {
+        if (k < S) {
+            const double d = group_sum<64>(acc[k]);
+            if (lane == k) rp[k] = (n2 > 0.0f) ? (b - d) / (double)n2 : 0.0;
+        }
+    }
+}
+
+// One thread per (distinct voxel, setting): the column sum in row order.
+template <typename CH>
+__global__ void __launch_bounds__(kThreads)
+k_batch_apply_csc(const int32_t *uvox, const uint32_t *ucol, int64_t U, int64_t ne,
+                  const uint16_t *cq, const CH *cch, const double *rbuf, int S,
+                  const double *lambda, double *x)
+{
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < U * S;
+         t += (int64_t)gridDim.x * kThreads) {
+        const int64_t u = t / S;
+        const int k = (int)(t - u * S);
+        const int64_t s0 = ucol[u];
+        const int64_t e0 = (u + 1 < U) ? (int64_t)ucol[u + 1] : ne;
+        double c = 0.0;
+        for (int64_t q = s0; q < e0; q++) c += rbuf[(int64_t)cq[q] * S + k] * (double)chord_at(cch, q);
+        x[(int64_t)uvox[u] * S + k] += lambda[k] * c / (double)(e0 - s0);
+    }
+}
+
 unsigned elem_grid(int64_t n)
 {
     int64_t wgs = (n + kThreads - 1) / kThreads;
@@ -265,7 +319,41 @@ int occupancy_of()
     return per_cu;
 }
 
+template <int SMAX>
+hipError_t batch_csc_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
+                            const CscBlock &cb, const BatchBuffers &b, double *rbuf,
+                            hipStream_t stream)
+{
+    const int64_t rows = r1 - r0;
+    if (rows <= 0) return hipSuccess;
+    dim3 grid((unsigned)((rows * 64 + kThreads - 1) / kThreads));
+    if (rs.chord16)
+        hipLaunchKernelGGL((k_batch_resid<SMAX, __half>), grid, dim3(kThreads), 0, stream, rs,
+                           rs.chord16, wepl, r0, r1, b.S, b.x, rbuf);
+    else
+        hipLaunchKernelGGL((k_batch_resid<SMAX, float>), grid, dim3(kThreads), 0, stream, rs,
+                           rs.chord32, wepl, r0, r1, b.S, b.x, rbuf);
+    if (cb.U <= 0) return hipGetLastError();
+    const unsigned wgs = elem_grid(cb.U * b.S);
+    if (cb.cch16)
+        hipLaunchKernelGGL((k_batch_apply_csc<__half>), dim3(wgs), dim3(kThreads), 0, stream,
+                           cb.uvox, cb.ucol, cb.U, cb.ne, cb.cq, cb.cch16, rbuf, b.S, b.lambda, b.x);
+    else
+        hipLaunchKernelGGL((k_batch_apply_csc<float>), dim3(wgs), dim3(kThreads), 0, stream,
+                           cb.uvox, cb.ucol, cb.U, cb.ne, cb.cq, cb.cch32, rbuf, b.S, b.lambda, b.x);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_batch_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
+                                  const CscBlock &cb, const BatchBuffers &b, double *rbuf,
+                                  hipStream_t stream)
+{
+    if (b.S <= 8) return batch_csc_launch<8>(rs, wepl, r0, r1, cb, b, rbuf, stream);
+    if (b.S <= 16) return batch_csc_launch<16>(rs, wepl, r0, r1, cb, b, rbuf, stream);
+    return batch_csc_launch<32>(rs, wepl, r0, r1, cb, b, rbuf, stream);
+}
 
 int batch_vox_per_wg(int S) { return kThreads / S; }
 

@@ -161,7 +161,80 @@ hipError_t persistent_launch(const RowSet &rs, const float *wepl, int64_t block_
     return hipGetLastError();
 }
 
+// Residuals of the rows [r0, r1) into rbuf[row - r0] (voxel-major apply).
+template <int LPR, typename CH>
+__global__ void __launch_bounds__(kThreads)
+k_drop_resid(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1,
+             const double *x, double *rbuf)
+{
+    const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
+    if (row >= r1) return;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int64_t lr = row - rs.first;
+    const float n2 = rs.norm2[lr];
+    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
+    double acc = 0.0;
+    for (int64_t e = off + lane; e < end; e += LPR)
+        acc += (double)chord_at(chord, e) * x[rs.idx[e]];
+    acc = group_sum<LPR>(acc);
+    if (lane == 0) rbuf[row - r0] = (n2 > 0.0f) ? ((double)wepl[row] - acc) / (double)n2 : 0.0;
+}
+
+// x_j += lambda * (sum over column j of r_q a_qj) / (column length), one
+// thread per distinct voxel of the block; columns are summed in row order.
+template <typename CH>
+__global__ void __launch_bounds__(kThreads)
+k_drop_apply_csc(const int32_t *uvox, const uint32_t *ucol, int64_t U, int64_t ne,
+                 const uint16_t *cq, const CH *cch, const double *rbuf, double lambda, double *x)
+{
+    for (int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x; u < U;
+         u += (int64_t)gridDim.x * kThreads) {
+        const int64_t s = ucol[u];
+        const int64_t e = (u + 1 < U) ? (int64_t)ucol[u + 1] : ne;
+        double c = 0.0;
+        for (int64_t k = s; k < e; k++) c += rbuf[cq[k]] * (double)chord_at(cch, k);
+        x[uvox[u]] += lambda * c / (double)(e - s);
+    }
+}
+
+template <int LPR>
+hipError_t csc_block_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
+                            double lambda, const CscBlock &cb, double *x, double *rbuf,
+                            hipStream_t stream)
+{
+    const int64_t rows = r1 - r0;
+    if (rows <= 0) return hipSuccess;
+    dim3 grid((unsigned)((rows * LPR + kThreads - 1) / kThreads));
+    if (rs.chord16)
+        hipLaunchKernelGGL((k_drop_resid<LPR, __half>), grid, dim3(kThreads), 0, stream, rs,
+                           rs.chord16, wepl, r0, r1, x, rbuf);
+    else
+        hipLaunchKernelGGL((k_drop_resid<LPR, float>), grid, dim3(kThreads), 0, stream, rs,
+                           rs.chord32, wepl, r0, r1, x, rbuf);
+    if (cb.U <= 0) return hipGetLastError();
+    int64_t wgs = (cb.U + kThreads - 1) / kThreads;
+    if (wgs > 4096) wgs = 4096;
+    if (cb.cch16)
+        hipLaunchKernelGGL((k_drop_apply_csc<__half>), dim3((unsigned)wgs), dim3(kThreads), 0,
+                           stream, cb.uvox, cb.ucol, cb.U, cb.ne, cb.cq, cb.cch16, rbuf, lambda, x);
+    else
+        hipLaunchKernelGGL((k_drop_apply_csc<float>), dim3((unsigned)wgs), dim3(kThreads), 0,
+                           stream, cb.uvox, cb.ucol, cb.U, cb.ne, cb.cq, cb.cch32, rbuf, lambda, x);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_drop_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
+                                 double lambda, const CscBlock &cb, double *x, double *rbuf,
+                                 int lanes_per_row, hipStream_t stream)
+{
+    switch (lanes_per_row) {
+    case 16: return csc_block_launch<16>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream);
+    case 32: return csc_block_launch<32>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream);
+    default: return csc_block_launch<64>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream);
+    }
+}
 
 hipError_t launch_drop_block(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                              double lambda, const DropBuffers &b, int parity, int lanes_per_row,

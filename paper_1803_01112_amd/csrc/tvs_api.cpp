@@ -86,6 +86,17 @@ struct tvs_ctx {
     int64_t chunk = 0;              // histories per chunk (on-the-fly)
     std::vector<int64_t> chunk_base; // row_off at each chunk start (and the end)
 
+    // voxel-major form of every block of a path store (csc.hip)
+    bool csc = false;
+    int32_t *uvox = nullptr;
+    uint32_t *ucol = nullptr;
+    uint16_t *cq = nullptr;
+    float *cch32 = nullptr;
+    __half *cch16 = nullptr;
+    double *rbuf = nullptr;         // residuals of one block
+    int64_t n_unique = 0;
+    std::vector<int64_t> blk_u, blk_ubase, blk_ebase, blk_ne;
+
     // cycle state
     int64_t k = 0, ell = 0;
     uint64_t rng = 0;
@@ -122,6 +133,7 @@ struct tvs_ctx {
         int grid = 0;
         double ms_total = 0;
         int64_t cycles = 0;
+        double *rbuf = nullptr;     // B * S residuals (voxel-major form)
     } batch;
 };
 
@@ -191,6 +203,18 @@ void free_histories(tvs_ctx *ctx)
     dfree(ctx, &ctx->idx, (size_t)cap);
     dfree(ctx, &ctx->chord32, (size_t)cap);
     dfree(ctx, &ctx->chord16, (size_t)cap);
+    dfree(ctx, &ctx->uvox, (size_t)ctx->n_unique);
+    dfree(ctx, &ctx->ucol, (size_t)ctx->n_unique);
+    dfree(ctx, &ctx->cq, (size_t)(ctx->csc ? ctx->nnz : 0));
+    dfree(ctx, &ctx->cch32, (size_t)(ctx->csc ? ctx->nnz : 0));
+    dfree(ctx, &ctx->cch16, (size_t)(ctx->csc ? ctx->nnz : 0));
+    dfree(ctx, &ctx->rbuf, (size_t)ctx->cfg.block_size);
+    ctx->csc = false;
+    ctx->n_unique = 0;
+    ctx->blk_u.clear();
+    ctx->blk_ubase.clear();
+    ctx->blk_ebase.clear();
+    ctx->blk_ne.clear();
     ctx->loaded = false;
     ctx->nh = 0;
     ctx->nnz = ctx->max_row = ctx->skipped = 0;
@@ -211,6 +235,7 @@ void free_batch(tvs_ctx *ctx)
     dfree(ctx, &B.b.eps, (size_t)B.S);
     dfree(ctx, &B.b.beta_tab, (size_t)B.beta_cap);
     dfree(ctx, &B.b.cyc, (size_t)4);
+    dfree(ctx, &B.rbuf, (size_t)(ctx->cfg.block_size * B.S));
     B = tvs_ctx::Batch();
 }
 
@@ -302,7 +327,21 @@ int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st)
             span(ctx, 2, e0, e1);
             e0 = e1;
         }
-        if (persistent) {
+        if (ctx->csc) {
+            for (int64_t r0 = first, t = first / B; r0 < first + n; r0 += B, t++) {
+                const int64_t r1 = std::min(r0 + B, first + n);
+                tvs::CscBlock cb;
+                cb.uvox = ctx->uvox + ctx->blk_ubase[t];
+                cb.ucol = ctx->ucol + ctx->blk_ubase[t];
+                cb.U = ctx->blk_u[t];
+                cb.ne = ctx->blk_ne[t];
+                cb.cq = ctx->cq + ctx->blk_ebase[t];
+                if (ctx->cch16) cb.cch16 = ctx->cch16 + ctx->blk_ebase[t];
+                else cb.cch32 = ctx->cch32 + ctx->blk_ebase[t];
+                HIPCHK(tvs::launch_drop_block_csc(rs, wepl, r0, r1, lambda, cb, ctx->x, ctx->rbuf,
+                                                  ctx->lpr, st));
+            }
+        } else if (persistent) {
             HIPCHK(tvs::launch_drop_persistent(rs, wepl, B, lambda, db, ctx->lpr, ctx->pgrid, st));
         } else {
             int parity = 0;
@@ -360,9 +399,127 @@ int count_rows(tvs_ctx *ctx, int64_t first, int64_t n, int64_t *row_off_dev, hip
     return TVS_OK;
 }
 
+// Builds the voxel-major form of every block of the path store.
+int build_csc(tvs_ctx *ctx, hipStream_t st)
+{
+    const int64_t B = ctx->cfg.block_size, nh = ctx->nh, nvox = ctx->nvox;
+    const int64_t T = (nh + B - 1) / B;
+    if (T == 0) return TVS_OK;
+    std::vector<int64_t> off((size_t)nh + 1);
+    HIPCHK(hipMemcpy(off.data(), ctx->row_off, sizeof(int64_t) * (nh + 1), hipMemcpyDeviceToHost));
+    ctx->blk_ebase.resize((size_t)T);
+    ctx->blk_ne.resize((size_t)T);
+    ctx->blk_u.assign((size_t)T, 0);
+    ctx->blk_ubase.assign((size_t)T, 0);
+    for (int64_t t = 0; t < T; t++) {
+        const int64_t r0 = t * B, r1 = std::min(r0 + B, nh);
+        ctx->blk_ebase[t] = off[(size_t)r0];
+        ctx->blk_ne[t] = off[(size_t)r1] - off[(size_t)r0];
+    }
+    int64_t NB = (int64_t)((256ll << 20) / (24 * std::max<int64_t>(nvox, 1)));
+    NB = std::max<int64_t>(1, std::min<int64_t>(NB, 64));
+    NB = std::min(NB, T);
+    const int64_t n = NB * nvox;
+    uint32_t *cnt = nullptr;
+    int32_t *flag = nullptr;
+    int64_t *urank = nullptr, *cstart = nullptr, *tmp = nullptr, *meta = nullptr;
+    auto cleanup = [&]() {
+        dfree(ctx, &cnt, (size_t)n);
+        dfree(ctx, &flag, (size_t)n);
+        dfree(ctx, &urank, (size_t)n + 1);
+        dfree(ctx, &cstart, (size_t)n + 1);
+        dfree(ctx, &tmp, (size_t)tvs::scan_tmp_elems(n) + 1);
+        dfree(ctx, &meta, (size_t)(5 * (NB + 1)));
+    };
+    int rc = dalloc(ctx, &cnt, (size_t)n);
+    if (!rc) rc = dalloc(ctx, &flag, (size_t)n);
+    if (!rc) rc = dalloc(ctx, &urank, (size_t)n + 1);
+    if (!rc) rc = dalloc(ctx, &cstart, (size_t)n + 1);
+    if (!rc) rc = dalloc(ctx, &tmp, (size_t)tvs::scan_tmp_elems(n) + 1);
+    if (!rc) rc = dalloc(ctx, &meta, (size_t)(5 * (NB + 1)));
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    RowSet rs = rowset(ctx, 0, nh, 0);
+    std::vector<int64_t> picks((size_t)NB + 1);
+    hipError_t e = hipSuccess;
+    // pass 1: distinct voxels per block
+    for (int64_t b0 = 0; b0 < T && e == hipSuccess; b0 += NB) {
+        const int64_t nb = std::min(NB, T - b0);
+        const int64_t r0 = b0 * B, r1 = std::min((b0 + nb) * B, nh);
+        e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb * nvox, st);
+        if (e == hipSuccess) e = tvs::csc_count(rs, r0, r1, B, b0, nvox, cnt, st);
+        if (e == hipSuccess) e = tvs::csc_flags(cnt, nb * nvox, flag, st);
+        if (e == hipSuccess) e = tvs::launch_scan(flag, nb * nvox, urank, tmp, st);
+        if (e == hipSuccess) e = tvs::csc_pick(urank, nvox, nb, meta, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(picks.data(), meta, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        for (int64_t b = 0; b < nb && e == hipSuccess; b++) ctx->blk_u[b0 + b] = picks[b + 1] - picks[b];
+    }
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(ctx, TVS_EDEVICE, std::string("voxel-major build: ") + hipGetErrorString(e));
+    }
+    int64_t tot = 0;
+    for (int64_t t = 0; t < T; t++) {
+        ctx->blk_ubase[t] = tot;
+        tot += ctx->blk_u[t];
+    }
+    ctx->n_unique = tot;
+    rc = dalloc(ctx, &ctx->uvox, (size_t)tot);
+    if (!rc) rc = dalloc(ctx, &ctx->ucol, (size_t)tot);
+    if (!rc) rc = dalloc(ctx, &ctx->cq, (size_t)ctx->nnz);
+    if (!rc) {
+        if (ctx->chord16) rc = dalloc(ctx, &ctx->cch16, (size_t)ctx->nnz);
+        else rc = dalloc(ctx, &ctx->cch32, (size_t)ctx->nnz);
+    }
+    if (!rc) rc = dalloc(ctx, &ctx->rbuf, (size_t)B);
+    ctx->csc = true;   // so that a failure frees the column arrays with the right sizes
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    // pass 2: distinct-voxel records, column placement, column sort
+    std::vector<int64_t> hm((size_t)(4 * NB));
+    for (int64_t b0 = 0; b0 < T && e == hipSuccess; b0 += NB) {
+        const int64_t nb = std::min(NB, T - b0);
+        const int64_t r0 = b0 * B, r1 = std::min((b0 + nb) * B, nh);
+        int64_t maxu = 0;
+        for (int64_t b = 0; b < nb; b++) {
+            hm[(size_t)b] = ctx->blk_ubase[b0 + b];
+            hm[(size_t)(NB + b)] = ctx->blk_ebase[b0 + b];
+            hm[(size_t)(2 * NB + b)] = ctx->blk_u[b0 + b];
+            hm[(size_t)(3 * NB + b)] = ctx->blk_ne[b0 + b];
+            maxu = std::max(maxu, ctx->blk_u[b0 + b]);
+        }
+        int64_t *d_ubase = meta, *d_ebase = meta + NB, *d_ucnt = meta + 2 * NB, *d_ecnt = meta + 3 * NB;
+        e = hipMemcpyAsync(meta, hm.data(), sizeof(int64_t) * 4 * NB, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb * nvox, st);
+        if (e == hipSuccess) e = tvs::csc_count(rs, r0, r1, B, b0, nvox, cnt, st);
+        if (e == hipSuccess) e = tvs::csc_flags(cnt, nb * nvox, flag, st);
+        if (e == hipSuccess) e = tvs::launch_scan(flag, nb * nvox, urank, tmp, st);
+        if (e == hipSuccess) e = tvs::csc_as_int(cnt, nb * nvox, flag, st);
+        if (e == hipSuccess) e = tvs::launch_scan(flag, nb * nvox, cstart, tmp, st);
+        if (e == hipSuccess)
+            e = tvs::csc_emit(cnt, urank, cstart, nb, nvox, d_ubase, d_ebase, ctx->uvox, ctx->ucol, st);
+        if (e == hipSuccess)
+            e = tvs::csc_place(rs, r0, r1, B, b0, nvox, cnt, d_ebase, ctx->cq, ctx->cch32, ctx->cch16, st);
+        if (e == hipSuccess)
+            e = tvs::csc_sort(ctx->ucol, d_ubase, d_ucnt, d_ebase, d_ecnt, nb, maxu, ctx->cq,
+                              ctx->cch32, ctx->cch16, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);   // meta is reused by the next batch
+    }
+    cleanup();
+    if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("voxel-major build: ") + hipGetErrorString(e));
+    return TVS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
 
 void tvs_config_default(tvs_config *cfg)
 {
@@ -499,7 +656,9 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
         tvs_destroy(ctx);
         return TVS_EDEVICE;
     }
-    int sk = cfg.sweep_kernel ? cfg.sweep_kernel : 2;
+    // launches are far cheaper than device-wide barriers on gfx950, so the
+    // default sweep is one launch per block phase; 2 keeps the persistent form
+    int sk = cfg.sweep_kernel ? cfg.sweep_kernel : 1;
     ctx->pgrid = (sk == 2) ? tvs::persistent_grid_size(cfg.device, ctx->lpr) : 0;
     *out = ctx;
     return TVS_OK;
@@ -617,6 +776,14 @@ int tvs_load_histories(tvs_ctx *ctx, int64_t n, const tvs_histories *h, int on_d
         if (e != hipSuccess) {
             free_histories(ctx);
             return fail(ctx, TVS_EDEVICE, std::string("row fill: ") + hipGetErrorString(e));
+        }
+        if (ctx->cfg.block_size <= 65536 && ctx->cfg.sweep_kernel != 2) {
+            rc = build_csc(ctx, st);
+            if (rc) {
+                std::string msg = ctx->err;
+                free_histories(ctx);
+                return fail(ctx, rc, msg);
+            }
         }
     }
     ctx->loaded = true;
@@ -908,6 +1075,7 @@ int batch_init(tvs_ctx *ctx, const tvs_params *p, int S, hipStream_t st)
         if (!rc) rc = dalloc(ctx, &B.b.lambda, (size_t)S);
         if (!rc) rc = dalloc(ctx, &B.b.eps, (size_t)S);
         if (!rc) rc = dalloc(ctx, &B.b.cyc, (size_t)4);
+        if (!rc) rc = dalloc(ctx, &B.rbuf, (size_t)(ctx->cfg.block_size * S));
         if (rc) {
             free_batch(ctx);
             return rc;
@@ -961,7 +1129,23 @@ int batch_cycle(tvs_ctx *ctx, int nmax, hipStream_t st)
         const int64_t n = std::min(step, ctx->nh - first);
         RowSet rs = rowset(ctx, first, n, otf ? ctx->chunk_base[q] : 0);
         if (otf) HIPCHK(tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rs, st));
-        HIPCHK(tvs::launch_drop_batch(rs, wepl, ctx->cfg.block_size, B.b, B.grid, st));
+        if (ctx->csc) {
+            const int64_t Bs = ctx->cfg.block_size;
+            for (int64_t r0 = first, t = first / Bs; r0 < first + n; r0 += Bs, t++) {
+                const int64_t r1 = std::min(r0 + Bs, first + n);
+                tvs::CscBlock cb;
+                cb.uvox = ctx->uvox + ctx->blk_ubase[t];
+                cb.ucol = ctx->ucol + ctx->blk_ubase[t];
+                cb.U = ctx->blk_u[t];
+                cb.ne = ctx->blk_ne[t];
+                cb.cq = ctx->cq + ctx->blk_ebase[t];
+                if (ctx->cch16) cb.cch16 = ctx->cch16 + ctx->blk_ebase[t];
+                else cb.cch32 = ctx->cch32 + ctx->blk_ebase[t];
+                HIPCHK(tvs::launch_batch_block_csc(rs, wepl, r0, r1, cb, B.b, B.rbuf, st));
+            }
+        } else {
+            HIPCHK(tvs::launch_drop_batch(rs, wepl, ctx->cfg.block_size, B.b, B.grid, st));
+        }
     }
     HIPCHK(tvs::launch_tick(B.b.cyc, st));
     return TVS_OK;

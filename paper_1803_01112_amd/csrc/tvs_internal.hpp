@@ -89,6 +89,37 @@ int persistent_grid_size(int device, int lanes_per_row);
 // Clears both touched-list counters.
 hipError_t launch_zero_counters(uint32_t *cnt, hipStream_t stream);
 
+// Voxel-major form of one DROP block (csc.hip): distinct voxels uvox[0..U),
+// their column starts ucol (relative to the block's first entry), and the
+// block's ne column entries (row within the block, chord).
+struct CscBlock {
+    const int32_t *uvox = nullptr;
+    const uint32_t *ucol = nullptr;
+    int64_t U = 0, ne = 0;
+    const uint16_t *cq = nullptr;
+    const float *cch32 = nullptr;
+    const __half *cch16 = nullptr;
+};
+// Residual launch + voxel-major apply launch of one block (no atomics).
+hipError_t launch_drop_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
+                                 double lambda, const CscBlock &cb, double *x, double *rbuf,
+                                 int lanes_per_row, hipStream_t stream);
+// Build steps of the voxel-major form for a batch of nb blocks from b0.
+hipError_t csc_count(const RowSet &rs, int64_t r0, int64_t r1, int64_t block_size, int64_t b0,
+                     int64_t nvox, uint32_t *cnt, hipStream_t st);
+hipError_t csc_pick(const int64_t *src, int64_t stride, int64_t n, int64_t *dst, hipStream_t st);
+hipError_t csc_flags(const uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t st);
+hipError_t csc_as_int(const uint32_t *cnt, int64_t n, int32_t *out, hipStream_t st);
+hipError_t csc_emit(uint32_t *cnt, const int64_t *urank, const int64_t *cstart, int64_t nb,
+                    int64_t nvox, const int64_t *ubase, const int64_t *ebase, int32_t *uvox,
+                    uint32_t *ucol, hipStream_t st);
+hipError_t csc_place(const RowSet &rs, int64_t r0, int64_t r1, int64_t block_size, int64_t b0,
+                     int64_t nvox, uint32_t *cursor, const int64_t *ebase, uint16_t *cq,
+                     float *cch32, __half *cch16, hipStream_t st);
+hipError_t csc_sort(const uint32_t *ucol, const int64_t *ubase, const int64_t *ucount,
+                    const int64_t *ebase, const int64_t *ecount, int64_t nb, int64_t max_u,
+                    uint16_t *cq, float *cch32, __half *cch16, hipStream_t st);
+
 // ----------------------------------------------------------------- tv.hip
 struct TvBuffers {
     double *g;           // subgradient
@@ -147,5 +178,10 @@ hipError_t launch_replicate(const double *x0, const BatchBuffers &b, hipStream_t
 hipError_t launch_extract(const BatchBuffers &b, int s, float *out, hipStream_t stream);
 hipError_t launch_drop_batch(const RowSet &rs, const float *wepl, int64_t block_size,
                              const BatchBuffers &b, int grid_wgs, hipStream_t stream);
+// Voxel-major block of a batch: S residuals per row into rbuf (B*S), then S
+// corrections per distinct voxel.
+hipError_t launch_batch_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
+                                  const CscBlock &cb, const BatchBuffers &b, double *rbuf,
+                                  hipStream_t stream);
 
 }  // namespace tvs

@@ -24,7 +24,9 @@ VARIANTS = {"ntvs": 0, "otvs": 1, "decoupled": 2}
 EXPORTED = ("tvs_config_default", "tvs_create", "tvs_destroy", "tvs_load_histories",
             "tvs_set_image", "tvs_iterate", "tvs_get_image", "tvs_get_stats", "tvs_get_step_log",
             "tvs_debug_rows", "tvs_strerror", "tvs_last_error", "tvs_iterate_batch",
-            "tvs_get_batch_image")
+            "tvs_get_batch_image", "tvs_server_config_default", "tvs_server_create",
+            "tvs_server_footprint", "tvs_server_submit", "tvs_server_query", "tvs_server_wait",
+            "tvs_server_get_counters", "tvs_server_destroy")
 
 
 class TvsError(RuntimeError):
@@ -79,6 +81,32 @@ class StepLog(C.Structure):
                 ("gnorm", C.c_double)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("device", C.c_int32), ("max_active", C.c_int32),
+                ("hbm_budget_bytes", C.c_uint64), ("chunk_histories", C.c_int64),
+                ("simulate", C.c_int32), ("pad", C.c_int32),
+                ("sim_ns_per_history_cycle", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("grid", Grid), ("block_size", C.c_int32), ("path_mode", C.c_int32),
+                ("params", Params), ("K", C.c_int32), ("pad", C.c_int32), ("n", C.c_int64),
+                ("h", Histories), ("x0", C.c_void_p)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("submit_ms", C.c_double),
+                ("admit_ms", C.c_double), ("done_ms", C.c_double), ("bytes", C.c_uint64),
+                ("admit_order", C.c_int64)]
+
+
+class ServerCounters(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("in_use_bytes", C.c_uint64),
+                ("peak_bytes", C.c_uint64), ("active", C.c_int32), ("peak_active", C.c_int32),
+                ("queued", C.c_int32), ("pad", C.c_int32), ("completed", C.c_int64),
+                ("failed", C.c_int64)]
+
+
 _lib = None
 
 
@@ -110,6 +138,20 @@ def load_library(path: str = LIB):
     L.tvs_strerror.restype = C.c_char_p
     L.tvs_last_error.argtypes = [C.c_void_p]
     L.tvs_last_error.restype = C.c_char_p
+    L.tvs_server_config_default.argtypes = [P(ServerConfig)]
+    L.tvs_server_config_default.restype = None
+    L.tvs_server_create.argtypes = [P(ServerConfig), P(C.c_void_p)]
+    L.tvs_server_footprint.argtypes = [C.c_void_p, P(Request)]
+    L.tvs_server_footprint.restype = C.c_uint64
+    L.tvs_server_submit.argtypes = [C.c_void_p, P(Request), P(C.c_int64)]
+    L.tvs_server_query.argtypes = [C.c_void_p, C.c_int64, P(RequestInfo)]
+    L.tvs_server_wait.argtypes = [C.c_void_p, C.c_int64, _FP, C.c_int64, P(RequestInfo)]
+    L.tvs_server_get_counters.argtypes = [C.c_void_p, P(ServerCounters)]
+    L.tvs_server_destroy.argtypes = [C.c_void_p]
+    L.tvs_server_destroy.restype = None
+    for name in ("tvs_server_create", "tvs_server_submit", "tvs_server_query", "tvs_server_wait",
+                 "tvs_server_get_counters"):
+        getattr(L, name).restype = C.c_int
     for name in ("tvs_create", "tvs_load_histories", "tvs_set_image", "tvs_iterate",
                  "tvs_get_image", "tvs_get_stats", "tvs_get_step_log", "tvs_debug_rows",
                  "tvs_iterate_batch", "tvs_get_batch_image"):
@@ -302,3 +344,104 @@ class Context:
         self._check(rc, "tvs_debug_rows")
         tot = int(rn[:count].sum())
         return rn[:count], idx[:tot], ch[:tot], n2[:count]
+
+
+def _info(i: RequestInfo) -> dict:
+    return {f: getattr(i, f) for f, _ in RequestInfo._fields_}
+
+
+class Server:
+    """Continuous-batching server (tvs_server): FIFO admission by HBM budget and
+    slots, one context and stream per running request."""
+
+    def __init__(self, *, device=0, max_active=3, hbm_budget_bytes=0, chunk_histories=0,
+                 simulate=False, sim_ns_per_history_cycle=0.0):
+        self._L = load_library()
+        cfg = ServerConfig()
+        self._L.tvs_server_config_default(C.byref(cfg))
+        cfg.device = int(device)
+        cfg.max_active = int(max_active)
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        if chunk_histories:
+            cfg.chunk_histories = int(chunk_histories)
+        cfg.simulate = int(bool(simulate))
+        cfg.sim_ns_per_history_cycle = float(sim_ns_per_history_cycle)
+        h = C.c_void_p()
+        rc = self._L.tvs_server_create(C.byref(cfg), C.byref(h))
+        if rc != TVS_OK:
+            raise TvsError(rc, "tvs_server_create: " + self._L.tvs_strerror(rc).decode())
+        self._h = h
+        self._keep = {}
+        self._grids = {}
+
+    def _request(self, grid, hist, lam, N, alpha, K, block_size, path_mode, seed, x0, variant,
+                 tv_check):
+        n = len(hist["ex"])
+        arrs = {k: np.ascontiguousarray(hist[k], dtype=np.float32) for k in HIST_FIELDS}
+        hs = Histories(*[C.c_void_p(arrs[k].ctypes.data) for k in HIST_FIELDS])
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        prm = Params(float(lam), int(N), float(alpha), int(bool(tv_check)), v, 0.0,
+                     int(seed) & (2**64 - 1), 0.5)
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float32)
+        req = Request(grid_struct(grid), int(block_size),
+                      PATH_MODES[path_mode] if isinstance(path_mode, str) else int(path_mode),
+                      prm, int(K), 0, n, hs, None if x0a is None else C.c_void_p(x0a.ctypes.data))
+        return req, (arrs, x0a)
+
+    def footprint(self, grid, hist, **kw):
+        req, _ = self._request(grid, hist, kw.get("lam", 1e-4), kw.get("N", 1),
+                               kw.get("alpha", 0.5), kw.get("K", 1), kw.get("block_size", 3200),
+                               kw.get("path_mode", "otf"), 0, None, "ntvs", False)
+        return int(self._L.tvs_server_footprint(self._h, C.byref(req)))
+
+    def submit(self, grid, hist, *, lam, N, alpha, K, block_size=3200, path_mode="otf", seed=0,
+               x0=None, variant="ntvs", tv_check=False):
+        req, keep = self._request(grid, hist, lam, N, alpha, K, block_size, path_mode, seed, x0,
+                                  variant, tv_check)
+        rid = C.c_int64()
+        rc = self._L.tvs_server_submit(self._h, C.byref(req), C.byref(rid))
+        if rc != TVS_OK:
+            raise TvsError(rc, "tvs_server_submit: " + self._L.tvs_strerror(rc).decode())
+        self._keep[rid.value] = keep   # histories are borrowed until the request is done
+        self._grids[rid.value] = int(grid.nx) * int(grid.ny) * int(grid.nz)
+        return rid.value
+
+    def query(self, rid):
+        info = RequestInfo()
+        rc = self._L.tvs_server_query(self._h, int(rid), C.byref(info))
+        if rc != TVS_OK:
+            raise TvsError(rc, "tvs_server_query")
+        return _info(info)
+
+    def wait(self, rid):
+        """(image or None, info dict); the request's status is info['status']."""
+        nv = self._grids[rid]
+        img = np.zeros(nv, np.float32)
+        info = RequestInfo()
+        rc = self._L.tvs_server_wait(self._h, int(rid), img.ctypes.data_as(_FP), nv,
+                                     C.byref(info))
+        self._keep.pop(rid, None)
+        return (img if rc == TVS_OK else None), _info(info)
+
+    def counters(self):
+        c = ServerCounters()
+        self._L.tvs_server_get_counters(self._h, C.byref(c))
+        return {f: getattr(c, f) for f, _ in ServerCounters._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.tvs_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
