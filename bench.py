@@ -100,6 +100,93 @@ def cpu_baseline(w, args, cores):
                        f"N={args.N} TV steps and one DROP sweep (single thread); {el:.1f} s")
 
 
+def batch_settings():
+    """24 settings: lambda in {1e-4, 2e-4} x N in {1, 3, 6} x alpha in {0.5, 0.75, 0.85, 0.95}."""
+    out = []
+    for lam in (1e-4, 2e-4):
+        for N in (1, 3, 6):
+            for alpha in (0.5, 0.75, 0.85, 0.95):
+                out.append(dict(lam=lam, N=N, alpha=alpha, seed=1803 + len(out)))
+    return out
+
+
+def run_batch(tvs, torch, w, dev, x0, args):
+    """All 24 settings of the parameter study advanced together (one row stream)."""
+    sets = batch_settings()
+    ctx = tvs.Context(w.grid, block_size=args.block, path_mode=args.batch_path)
+    ctx.load_histories(dev)
+    ctx.set_image(x0)
+    ctx.iterate_batch(1, sets)                     # warm-up cycle (captures the graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.iterate_batch(args.steps, sets)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ctx.stats()
+    ctx.close()
+    S = len(sets)
+    return dict(settings=S, value=w.n_hist * S * args.steps / dt,
+                unit="history-settings/s", ms_per_cycle=1e3 * dt / args.steps,
+                device_ms_per_cycle=st["batch_ms_total"] / max(st["batch_cycles"], 1),
+                path_mode=args.batch_path)
+
+
+def run_serving(tvs, args):
+    """Poisson stream of reconstruction requests of mixed grids and sizes."""
+    from paper_1803_01112_amd import synth
+    rng = np.random.default_rng(1803011124)
+    grids = ["vol64", "vol128", "vol200", "vol256"]
+    hmax = args.serve_hmax
+    pools = {}
+    for g in grids:
+        w = synth.workload(g, n_hist=hmax)
+        pools[g] = (w, w.histories(), w.initial_image())
+    pairs = [(1e-4, 12), (1.5e-4, 8), (2e-4, 6)]
+    reqs = []
+    for q in range(args.serve_requests):
+        g = grids[rng.integers(len(grids))]
+        n = int(10 ** rng.uniform(np.log10(args.serve_hmin), np.log10(hmax)))
+        lam, K = pairs[rng.integers(3)]
+        reqs.append(dict(g=g, n=n, lam=lam, K=K, N=int(rng.integers(1, 7)),
+                         alpha=float(rng.choice([0.5, 0.65, 0.75, 0.85, 0.95]))))
+    work = sum(r["n"] * r["K"] for r in reqs)
+
+    def sub(s, r):
+        w, h, x0 = pools[r["g"]]
+        hh = {k: v[:r["n"]] for k, v in h.items()}
+        return s.submit(w.grid, hh, lam=r["lam"], N=r["N"], alpha=r["alpha"], K=r["K"],
+                        path_mode=args.serve_path, x0=x0, seed=7)
+
+    # capacity: the same requests back to back, one at a time
+    with tvs.Server(max_active=1) as s:
+        t0 = time.perf_counter()
+        for r in reqs:
+            s.wait(sub(s, r))
+        t_alone = time.perf_counter() - t0
+    cap_rate = len(reqs) / t_alone
+    out = dict(requests=len(reqs), history_cycles=work, serial_s=t_alone,
+               serial_value=work / t_alone, loads={})
+    for rho in [float(v) for v in args.serve_loads.split(",")]:
+        gaps = rng.exponential(1.0 / (rho * cap_rate), len(reqs))
+        with tvs.Server(max_active=args.serve_slots) as s:
+            t0 = time.perf_counter()
+            ids = []
+            for r, gap in zip(reqs, gaps):
+                time.sleep(gap)
+                ids.append(sub(s, r))
+            res = [s.wait(i) for i in ids]
+            dt = time.perf_counter() - t0
+            c = s.counters()
+        lat = np.array([i["done_ms"] - i["submit_ms"] for _, i in res])
+        ok = sum(1 for _, i in res if i["status"] == 0)
+        out["loads"][str(rho)] = dict(value=work / dt, unit="histories/s", makespan_s=dt,
+                                      p50_ms=float(np.percentile(lat, 50)),
+                                      p99_ms=float(np.percentile(lat, 99)), completed=ok,
+                                      peak_active=c["peak_active"],
+                                      peak_gb=c["peak_bytes"] / 2**30)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +206,15 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=400_000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch", action="store_true", help="also time the 24-setting batch")
+    ap.add_argument("--batch-path", default="f32")
+    ap.add_argument("--serve", action="store_true", help="also run the serving stream")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-hmin", type=int, default=200_000)
+    ap.add_argument("--serve-hmax", type=int, default=4_000_000)
+    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
+    ap.add_argument("--serve-path", default="f32")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -193,6 +289,19 @@ def main():
         c2.close()
         log(f"{form}: {forms[form]}")
 
+    batch = None
+    if args.batch:
+        log("timing the 24-setting batch")
+        batch = run_batch(tvs, torch, w, dev, x0, args)
+        log(f"batch: {batch}")
+    serving = None
+    if args.serve:
+        del dev
+        torch.cuda.empty_cache()
+        log("serving stream")
+        serving = run_serving(tvs, args)
+        log(f"serving: {serving}")
+
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cpu = None if args.no_cpu else cpu_baseline(w, args, cores)
 
@@ -224,6 +333,8 @@ def main():
         "load_s": load_s,
         "roofline": roof,
         "forms": forms,
+        "batch": batch,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

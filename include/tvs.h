@@ -79,7 +79,9 @@ typedef struct {
     int32_t sweep_kernel;    /* 0 or 1: one launch per block phase (path stores: voxel-major
                                 apply without atomics); 2: one persistent launch per sweep
                                 with device-wide barriers and atomic scatter */
-    int32_t wave_rows;       /* lanes per row in the DROP row kernels (8..64); 0: auto */
+    int32_t wave_rows;       /* lanes per row in the DROP row kernels (16, 32, 64); 0: 64 */
+    int32_t time_sample;     /* k > 0: HIP events around both launches of every k-th DROP
+                                block (per-launch durations in tvs_stats); 0: off */
 } tvs_config;
 
 /* Fills *cfg with the defaults above (B = 3200, on-the-fly rows, log term on). */
@@ -140,6 +142,9 @@ typedef struct {
     int64_t cycles_timed;  /* cycles of the call */
     int64_t rows_launches; /* row-formation launches of the call */
     int64_t drop_launches; /* DROP launches (persistent) or per-block launch pairs' spans */
+    double k1_ms_total;    /* sampled blocks: first launch (row residuals / row scatter) */
+    double k2_ms_total;    /* sampled blocks: second launch (voxel apply) */
+    int64_t k_samples;     /* sampled blocks of the last tvs_iterate call */
     double batch_ms_total; /* cycles of the last tvs_iterate_batch call */
     int64_t batch_cycles;  /* cycles of that call */
     int32_t batch_size;    /* S of the current batch (0: none) */
@@ -300,6 +305,31 @@ int tvs_server_get_counters(tvs_server *sv, tvs_server_counters *out);
 /* Lets running requests finish, fails queued ones (TVS_ESTATE), joins the
  * workers and frees the server. */
 void tvs_server_destroy(tvs_server *sv);
+
+/* ------------------------------------------------------------------------
+ * Autotuning of the launch shape.  Times every candidate shape (lanes per
+ * row 16 / 32 / 64 of the row kernels; for on-the-fly rows also the
+ * persistent sweep) on the first blocks of the loaded histories, from the
+ * current image, which is restored afterwards, and keeps the fastest for
+ * the context.  The block size B is a parameter of the method and is never
+ * changed.  With cache_path (a text file, created if missing) a shape
+ * measured before for the same device, grid, history count, B and path mode
+ * is reused without timing, and new measurements are appended.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t lanes_per_row;   /* chosen shape */
+    int32_t sweep_kernel;
+    double ms_per_block;     /* its measured time per DROP block */
+    int32_t from_cache;      /* 1: taken from the cache file */
+    int32_t n_candidates;
+    int32_t cand_lanes[8];
+    int32_t cand_sweep[8];
+    double cand_ms[8];       /* per block, per candidate */
+} tvs_tune_result;
+
+/* TVS_ESTATE before tvs_load_histories; TVS_EINVAL for lambda <= 0. */
+int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_result *out,
+                 void *stream);
 
 /* Static description of a status code. */
 const char *tvs_strerror(int status);

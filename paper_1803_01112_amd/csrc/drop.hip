@@ -64,16 +64,6 @@ __device__ inline void drop_row(const RowSet &rs, const CH *chord, const float *
     }
 }
 
-template <int LPR, typename CH>
-__global__ void __launch_bounds__(kThreads)
-k_drop_rows(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1, const double *x,
-            double *c, uint32_t *s, int32_t *touched, uint32_t *cnt)
-{
-    const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
-    if (row >= r1) return;   // groups never straddle a wavefront boundary
-    drop_row<LPR, CH>(rs, chord, wepl, row, x, c, s, touched, cnt);
-}
-
 __device__ inline void apply_voxel(int32_t j, double lambda, double *x, double *c, uint32_t *s)
 {
     double cj = c[j];
@@ -81,16 +71,6 @@ __device__ inline void apply_voxel(int32_t j, double lambda, double *x, double *
     x[j] += lambda * cj / (double)sj;
     c[j] = 0.0;
     s[j] = 0u;
-}
-
-__global__ void __launch_bounds__(kThreads)
-k_drop_apply(double lambda, double *x, double *c, uint32_t *s, const int32_t *touched,
-             const uint32_t *cnt, uint32_t *cnt_next)
-{
-    const uint32_t n = *cnt;
-    for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
-        apply_voxel(touched[i], lambda, x, c, s);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_next = 0u;
 }
 
 __global__ void k_zero_counters(uint32_t *cnt)
@@ -127,25 +107,6 @@ k_drop_persistent(RowSet rs, const CH *chord, const float *wepl, int64_t block_s
 }
 
 template <int LPR>
-hipError_t block_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1, double lambda,
-                        const DropBuffers &b, int parity, hipStream_t stream)
-{
-    const int64_t rows = r1 - r0;
-    if (rows <= 0) return hipSuccess;
-    dim3 grid((unsigned)((rows * LPR + kThreads - 1) / kThreads));
-    uint32_t *cur = b.ntouched + (parity & 1), *nxt = b.ntouched + ((parity + 1) & 1);
-    if (rs.chord16)
-        hipLaunchKernelGGL((k_drop_rows<LPR, __half>), grid, dim3(kThreads), 0, stream, rs,
-                           rs.chord16, wepl, r0, r1, b.x, b.c, b.s, b.touched, cur);
-    else
-        hipLaunchKernelGGL((k_drop_rows<LPR, float>), grid, dim3(kThreads), 0, stream, rs,
-                           rs.chord32, wepl, r0, r1, b.x, b.c, b.s, b.touched, cur);
-    hipLaunchKernelGGL(k_drop_apply, dim3(1024), dim3(kThreads), 0, stream, lambda, b.x,
-                       b.c, b.s, b.touched, cur, nxt);
-    return hipGetLastError();
-}
-
-template <int LPR>
 hipError_t persistent_launch(const RowSet &rs, const float *wepl, int64_t block_size,
                              double lambda, const DropBuffers &b, int grid_wgs, hipStream_t stream)
 {
@@ -159,6 +120,48 @@ hipError_t persistent_launch(const RowSet &rs, const float *wepl, int64_t block_
                            stream, rs, rs.chord32, wepl, block_size, lambda, b.x, b.c, b.s,
                            b.touched, b.ntouched, b.barrier);
     return hipGetLastError();
+}
+
+// Scatter-only row kernel of the per-block form: dot, residual, then
+// fire-and-forget float64 / uint32 atomics (no touched list: the apply
+// pass scans the hit counts densely).
+template <int LPR, typename CH>
+__global__ void __launch_bounds__(kThreads)
+k_drop_rows_dense(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1,
+                  const double *x, double *c, uint32_t *s)
+{
+    const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
+    if (row >= r1) return;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int64_t lr = row - rs.first;
+    const float n2 = rs.norm2[lr];
+    if (!(n2 > 0.0f)) return;   // uniform over the group
+    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
+    double acc = 0.0;
+    for (int64_t e = off + lane; e < end; e += LPR)
+        acc += (double)chord_at(chord, e) * x[rs.idx[e]];
+    acc = group_sum<LPR>(acc);
+    const double r = ((double)wepl[row] - acc) / (double)n2;
+    for (int64_t e = off + lane; e < end; e += LPR) {
+        const int32_t j = rs.idx[e];
+        unsafeAtomicAdd(c + j, r * (double)chord_at(chord, e));
+        __hip_atomic_fetch_add(s + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Dense apply: every voxel with hits in the block takes its correction and
+// clears its accumulators (a coalesced pass over the hit counts).
+__global__ void __launch_bounds__(kThreads)
+k_drop_apply_dense(double lambda, double *x, double *c, uint32_t *s, int64_t nvox)
+{
+    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < nvox;
+         j += (int64_t)gridDim.x * kThreads) {
+        const uint32_t sj = s[j];
+        if (sj == 0u) continue;
+        x[j] += lambda * c[j] / (double)sj;
+        c[j] = 0.0;
+        s[j] = 0u;
+    }
 }
 
 // Residuals of the rows [r0, r1) into rbuf[row - r0] (voxel-major apply).
@@ -198,9 +201,31 @@ k_drop_apply_csc(const int32_t *uvox, const uint32_t *ucol, int64_t U, int64_t n
 }
 
 template <int LPR>
+hipError_t block_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1, double lambda,
+                        const DropBuffers &b, int parity, hipStream_t stream, hipEvent_t mid)
+{
+    (void)parity;
+    const int64_t rows = r1 - r0;
+    if (rows <= 0) return hipSuccess;
+    dim3 grid((unsigned)((rows * LPR + kThreads - 1) / kThreads));
+    if (rs.chord16)
+        hipLaunchKernelGGL((k_drop_rows_dense<LPR, __half>), grid, dim3(kThreads), 0, stream, rs,
+                           rs.chord16, wepl, r0, r1, b.x, b.c, b.s);
+    else
+        hipLaunchKernelGGL((k_drop_rows_dense<LPR, float>), grid, dim3(kThreads), 0, stream, rs,
+                           rs.chord32, wepl, r0, r1, b.x, b.c, b.s);
+    if (mid && hipEventRecord(mid, stream) != hipSuccess) return hipErrorInvalidValue;
+    int64_t wgs = (b.nvox + kThreads - 1) / kThreads;
+    if (wgs > 8192) wgs = 8192;
+    hipLaunchKernelGGL(k_drop_apply_dense, dim3((unsigned)wgs), dim3(kThreads), 0, stream, lambda,
+                       b.x, b.c, b.s, b.nvox);
+    return hipGetLastError();
+}
+
+template <int LPR>
 hipError_t csc_block_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                             double lambda, const CscBlock &cb, double *x, double *rbuf,
-                            hipStream_t stream)
+                            hipStream_t stream, hipEvent_t mid)
 {
     const int64_t rows = r1 - r0;
     if (rows <= 0) return hipSuccess;
@@ -211,6 +236,7 @@ hipError_t csc_block_launch(const RowSet &rs, const float *wepl, int64_t r0, int
     else
         hipLaunchKernelGGL((k_drop_resid<LPR, float>), grid, dim3(kThreads), 0, stream, rs,
                            rs.chord32, wepl, r0, r1, x, rbuf);
+    if (mid && hipEventRecord(mid, stream) != hipSuccess) return hipErrorInvalidValue;
     if (cb.U <= 0) return hipGetLastError();
     int64_t wgs = (cb.U + kThreads - 1) / kThreads;
     if (wgs > 4096) wgs = 4096;
@@ -227,23 +253,23 @@ hipError_t csc_block_launch(const RowSet &rs, const float *wepl, int64_t r0, int
 
 hipError_t launch_drop_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                                  double lambda, const CscBlock &cb, double *x, double *rbuf,
-                                 int lanes_per_row, hipStream_t stream)
+                                 int lanes_per_row, hipStream_t stream, hipEvent_t mid)
 {
     switch (lanes_per_row) {
-    case 16: return csc_block_launch<16>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream);
-    case 32: return csc_block_launch<32>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream);
-    default: return csc_block_launch<64>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream);
+    case 16: return csc_block_launch<16>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, mid);
+    case 32: return csc_block_launch<32>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, mid);
+    default: return csc_block_launch<64>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, mid);
     }
 }
 
 hipError_t launch_drop_block(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                              double lambda, const DropBuffers &b, int parity, int lanes_per_row,
-                             hipStream_t stream)
+                             hipStream_t stream, hipEvent_t mid)
 {
     switch (lanes_per_row) {
-    case 16: return block_launch<16>(rs, wepl, r0, r1, lambda, b, parity, stream);
-    case 32: return block_launch<32>(rs, wepl, r0, r1, lambda, b, parity, stream);
-    default: return block_launch<64>(rs, wepl, r0, r1, lambda, b, parity, stream);
+    case 16: return block_launch<16>(rs, wepl, r0, r1, lambda, b, parity, stream, mid);
+    case 32: return block_launch<32>(rs, wepl, r0, r1, lambda, b, parity, stream, mid);
+    default: return block_launch<64>(rs, wepl, r0, r1, lambda, b, parity, stream, mid);
     }
 }
 

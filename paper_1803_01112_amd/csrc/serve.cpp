@@ -54,9 +54,14 @@ uint64_t footprint(const tvs_request &r, int64_t chunk)
     uint64_t rows_held;
     if (r.path_mode == TVS_PATH_ON_THE_FLY) rows_held = std::min<uint64_t>(n, (uint64_t)chunk);
     else rows_held = n;
-    const uint64_t entry = (r.path_mode == TVS_PATH_STORE_F16) ? 6 : 8;
+    // on the fly: two chunk buffers of int32 index + float32 chord; stores:
+    // row entries, their voxel-major copy (row id + chord) and at most one
+    // distinct-voxel record per entry, plus the build's scratch
+    uint64_t entry = 2 * 8, scratch = 0;
+    if (r.path_mode == TVS_PATH_STORE_F32) entry = 8 + 6 + 8, scratch = 256ull << 20;
+    if (r.path_mode == TVS_PATH_STORE_F16) entry = 6 + 4 + 8, scratch = 256ull << 20;
     return 52 * n + 12 * n + 8 * n /* load-time count + scan */ + rows_held * row_est * entry +
-           48 * nvox + (64ull << 20);
+           56 * nvox + scratch + (64ull << 20);
 }
 
 }  // namespace

@@ -79,9 +79,14 @@ struct tvs_ctx {
     float *hist = nullptr;          // 13 * nh floats
     int64_t *row_off = nullptr;     // nh + 1
     float *norm2 = nullptr;         // nh
-    int32_t *idx = nullptr;         // store or chunk buffer
+    int32_t *idx = nullptr;         // store, or the first chunk buffer
     float *chord32 = nullptr;
     __half *chord16 = nullptr;
+    int32_t *idx2 = nullptr;        // second chunk buffer (on-the-fly rows)
+    float *chord32b = nullptr;
+    hipStream_t fill_stream = nullptr;          // row formation of the next chunk
+    hipEvent_t ev_filled[2] = {nullptr, nullptr};
+    hipEvent_t ev_dropped[2] = {nullptr, nullptr};
     int64_t nnz = 0, max_row = 0, skipped = 0;
     int64_t chunk = 0;              // histories per chunk (on-the-fly)
     std::vector<int64_t> chunk_base; // row_off at each chunk start (and the end)
@@ -108,12 +113,13 @@ struct tvs_ctx {
     // the last tvs_iterate call, resolved lazily by tvs_get_stats
     std::vector<hipEvent_t> tev;
     size_t tev_used = 0;
-    struct Span { int kind; size_t a, b; };   // kind: 0 TV steps, 1 sweep, 2 rows, 3 DROP
+    // kind: 0 TV steps, 1 sweep, 2 rows, 3 DROP, 4 first / 5 second launch of a sampled block
+    struct Span { int kind; size_t a, b; };
     std::vector<Span> spans;
     bool timed = false;
     double last_sweep_ms = 0, last_tv_ms = 0, last_rows_ms = 0;
-    double tot_ms[4] = {0, 0, 0, 0};
-    int64_t tot_n[4] = {0, 0, 0, 0};
+    double tot_ms[6] = {0, 0, 0, 0, 0, 0};
+    int64_t tot_n[6] = {0, 0, 0, 0, 0, 0};
     int lpr = 64;
     int pgrid = 0;
 
@@ -203,6 +209,8 @@ void free_histories(tvs_ctx *ctx)
     dfree(ctx, &ctx->idx, (size_t)cap);
     dfree(ctx, &ctx->chord32, (size_t)cap);
     dfree(ctx, &ctx->chord16, (size_t)cap);
+    dfree(ctx, &ctx->idx2, (size_t)cap);
+    dfree(ctx, &ctx->chord32b, (size_t)cap);
     dfree(ctx, &ctx->uvox, (size_t)ctx->n_unique);
     dfree(ctx, &ctx->ucol, (size_t)ctx->n_unique);
     dfree(ctx, &ctx->cq, (size_t)(ctx->csc ? ctx->nnz : 0));
@@ -287,6 +295,17 @@ long mark(tvs_ctx *ctx, hipStream_t st)
     return (long)ctx->tev_used++;
 }
 
+// Reserves an event of the pool without recording it (recorded by a launcher).
+long slot(tvs_ctx *ctx)
+{
+    if (ctx->tev_used == ctx->tev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        ctx->tev.push_back(e);
+    }
+    return (long)ctx->tev_used++;
+}
+
 void span(tvs_ctx *ctx, int kind, long a, long b)
 {
     if (a >= 0 && b >= 0) ctx->spans.push_back({kind, (size_t)a, (size_t)b});
@@ -308,25 +327,52 @@ RowSet rowset(tvs_ctx *ctx, int64_t first, int64_t n, int64_t base)
     return rs;
 }
 
-// One P_T sweep over all loaded histories.
-int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st)
+// One P_T sweep over the loaded histories (the first `limit` of them when
+// limit >= 0: used to time launch shapes).
+int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st, int64_t limit = -1)
 {
     const int64_t B = ctx->cfg.block_size;
+    const int64_t nh_run = (limit >= 0) ? std::min(limit, ctx->nh) : ctx->nh;
     const float *wepl = ctx->hist + 12 * ctx->nh;
     tvs::DropBuffers db = drop_bufs(ctx);
     const bool persistent = ctx->pgrid > 0;
     const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
     const int64_t step = otf ? ctx->chunk : ctx->nh;
-    for (int64_t first = 0, q = 0; first < ctx->nh; first += step, q++) {
-        const int64_t n = std::min(step, ctx->nh - first);
-        RowSet rs = rowset(ctx, first, n, otf ? ctx->chunk_base[q] : 0);
-        long e0 = mark(ctx, st);
-        if (otf) {
-            HIPCHK(tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rs, st));
-            long e1 = mark(ctx, st);
-            span(ctx, 2, e0, e1);
-            e0 = e1;
+    const int64_t nchunks = (nh_run + step - 1) / std::max<int64_t>(step, 1);
+    const bool two = otf && ctx->idx2 != nullptr;
+    hipStream_t fs = two ? ctx->fill_stream : st;
+    // forms the rows of chunk q into buffer q & 1 on the fill stream
+    auto fill = [&](int64_t q) -> int {
+        const int64_t f0 = q * step, n0 = std::min(step, nh_run - f0);
+        RowSet rq = rowset(ctx, f0, n0, ctx->chunk_base[q]);
+        if (two && (q & 1)) {
+            rq.idx = ctx->idx2;
+            rq.chord32 = ctx->chord32b;
         }
+        if (two) HIPCHK(hipStreamWaitEvent(fs, ctx->ev_dropped[q & 1], 0));
+        long a = mark(ctx, fs);
+        HIPCHK(tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rq, fs));
+        span(ctx, 2, a, mark(ctx, fs));
+        if (two) HIPCHK(hipEventRecord(ctx->ev_filled[q & 1], fs));
+        return TVS_OK;
+    };
+    if (otf && nchunks > 0) {
+        int rc = fill(0);
+        if (rc) return rc;
+    }
+    for (int64_t first = 0, q = 0; first < nh_run; first += step, q++) {
+        const int64_t n = std::min(step, nh_run - first);
+        RowSet rs = rowset(ctx, first, n, otf ? ctx->chunk_base[q] : 0);
+        if (two && (q & 1)) {
+            rs.idx = ctx->idx2;
+            rs.chord32 = ctx->chord32b;
+        }
+        if (otf && q + 1 < nchunks) {
+            int rc = fill(q + 1);   // overlaps the DROP chain of chunk q
+            if (rc) return rc;
+        }
+        if (two) HIPCHK(hipStreamWaitEvent(st, ctx->ev_filled[q & 1], 0));
+        long e0 = mark(ctx, st);
         if (ctx->csc) {
             for (int64_t r0 = first, t = first / B; r0 < first + n; r0 += B, t++) {
                 const int64_t r1 = std::min(r0 + B, first + n);
@@ -338,20 +384,38 @@ int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st)
                 cb.cq = ctx->cq + ctx->blk_ebase[t];
                 if (ctx->cch16) cb.cch16 = ctx->cch16 + ctx->blk_ebase[t];
                 else cb.cch32 = ctx->cch32 + ctx->blk_ebase[t];
+                const bool samp = ctx->cfg.time_sample > 0 && t % ctx->cfg.time_sample == 0;
+                long k0 = samp ? mark(ctx, st) : -1;
+                long km = samp ? slot(ctx) : -1;
                 HIPCHK(tvs::launch_drop_block_csc(rs, wepl, r0, r1, lambda, cb, ctx->x, ctx->rbuf,
-                                                  ctx->lpr, st));
+                                                  ctx->lpr, st, km >= 0 ? ctx->tev[(size_t)km] : nullptr));
+                if (samp) {
+                    long k2 = mark(ctx, st);
+                    span(ctx, 4, k0, km);
+                    span(ctx, 5, km, k2);
+                }
             }
         } else if (persistent) {
             HIPCHK(tvs::launch_drop_persistent(rs, wepl, B, lambda, db, ctx->lpr, ctx->pgrid, st));
         } else {
             int parity = 0;
-            for (int64_t r0 = first; r0 < first + n; r0 += B, parity ^= 1) {
+            for (int64_t r0 = first, t = first / B; r0 < first + n; r0 += B, parity ^= 1, t++) {
                 int64_t r1 = std::min(r0 + B, first + n);
-                HIPCHK(tvs::launch_drop_block(rs, wepl, r0, r1, lambda, db, parity, ctx->lpr, st));
+                const bool samp = ctx->cfg.time_sample > 0 && t % ctx->cfg.time_sample == 0;
+                long k0 = samp ? mark(ctx, st) : -1;
+                long km = samp ? slot(ctx) : -1;
+                HIPCHK(tvs::launch_drop_block(rs, wepl, r0, r1, lambda, db, parity, ctx->lpr, st,
+                                              km >= 0 ? ctx->tev[(size_t)km] : nullptr));
+                if (samp) {
+                    long k2 = mark(ctx, st);
+                    span(ctx, 4, k0, km);
+                    span(ctx, 5, km, k2);
+                }
             }
             HIPCHK(tvs::launch_zero_counters(ctx->ntouched, st));
         }
         span(ctx, 3, e0, mark(ctx, st));
+        if (two) HIPCHK(hipEventRecord(ctx->ev_dropped[q & 1], st));
     }
     return TVS_OK;
 }
@@ -536,6 +600,7 @@ void tvs_config_default(tvs_config *cfg)
     cfg->max_tries = 0;
     cfg->sweep_kernel = 0;
     cfg->wave_rows = 0;
+    cfg->time_sample = 0;
 }
 
 const char *tvs_strerror(int status)
@@ -558,6 +623,7 @@ void tvs_destroy(tvs_ctx *ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->cfg.device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->fill_stream) (void)hipStreamSynchronize(ctx->fill_stream);
     free_histories(ctx);
     free_batch(ctx);
     dfree(ctx, &ctx->x0, (size_t)ctx->nvox);
@@ -573,6 +639,11 @@ void tvs_destroy(tvs_ctx *ctx)
     dfree(ctx, &ctx->ticket, (size_t)4);
     for (auto &e : ctx->tev)
         if (e) (void)hipEventDestroy(e);
+    for (int q = 0; q < 2; q++) {
+        if (ctx->ev_filled[q]) (void)hipEventDestroy(ctx->ev_filled[q]);
+        if (ctx->ev_dropped[q]) (void)hipEventDestroy(ctx->ev_dropped[q]);
+    }
+    if (ctx->fill_stream) (void)hipStreamDestroy(ctx->fill_stream);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -599,6 +670,7 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (cfg.sweep_kernel < 0 || cfg.sweep_kernel > 2) return TVS_EINVAL;
     if (cfg.wave_rows != 0 && cfg.wave_rows != 16 && cfg.wave_rows != 32 && cfg.wave_rows != 64)
         return TVS_EINVAL;
+    if (cfg.time_sample < 0) return TVS_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg.device < 0 || cfg.device >= ndev)
         return TVS_EDEVICE;
@@ -639,9 +711,18 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
         tvs_destroy(ctx);
         return rc;
     }
-    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->fill_stream, hipStreamNonBlocking) != hipSuccess) {
         tvs_destroy(ctx);
         return TVS_EDEVICE;
+    }
+    for (int q = 0; q < 2; q++) {
+        if (hipEventCreateWithFlags(&ctx->ev_filled[q], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->ev_dropped[q], hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ctx->ev_dropped[q], ctx->stream) != hipSuccess) {
+            tvs_destroy(ctx);
+            return TVS_EDEVICE;
+        }
     }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemsetAsync(ctx->x, 0, sizeof(double) * nvox, ctx->stream);
@@ -764,6 +845,10 @@ int tvs_load_histories(tvs_ctx *ctx, int64_t n, const tvs_histories *h, int on_d
     if (!rc) {
         if (ctx->cfg.path_mode == TVS_PATH_STORE_F16) rc = dalloc(ctx, &ctx->chord16, (size_t)cap);
         else rc = dalloc(ctx, &ctx->chord32, (size_t)cap);
+    }
+    if (!rc && ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY && ctx->chunk_base.size() > 2) {
+        rc = dalloc(ctx, &ctx->idx2, (size_t)cap);
+        if (!rc) rc = dalloc(ctx, &ctx->chord32b, (size_t)cap);
     }
     if (rc) {
         free_histories(ctx);
@@ -926,7 +1011,7 @@ int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out)
     HIPCHK(hipSetDevice(ctx->cfg.device));
     if (ctx->timed && !ctx->spans.empty()) {
         HIPCHK(hipEventSynchronize(ctx->tev[ctx->spans.back().b]));
-        for (int q = 0; q < 4; q++) {
+        for (int q = 0; q < 6; q++) {
             ctx->tot_ms[q] = 0.0;
             ctx->tot_n[q] = 0;
         }
@@ -971,6 +1056,9 @@ int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out)
     out->cycles_timed = ctx->tot_n[1];
     out->rows_launches = ctx->tot_n[2];
     out->drop_launches = ctx->tot_n[3];
+    out->k1_ms_total = ctx->tot_ms[4];
+    out->k2_ms_total = ctx->tot_ms[5];
+    out->k_samples = ctx->tot_n[4];
     out->batch_ms_total = ctx->batch.ms_total;
     out->batch_cycles = ctx->batch.cycles;
     out->batch_size = ctx->batch.valid ? ctx->batch.S : 0;
@@ -1271,6 +1359,126 @@ int tvs_get_batch_image(tvs_ctx *ctx, int32_t s, float *out, int on_device, void
     HIPCHK(hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nvox,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
     if (!on_device) HIPCHK(hipStreamSynchronize(st));
+    return TVS_OK;
+}
+
+int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_result *out,
+                 void *stream)
+{
+    if (!ctx || !out) return TVS_EINVAL;
+    ctx->err.clear();
+    std::memset(out, 0, sizeof(*out));
+    if (!finite_pos(lambda)) return fail(ctx, TVS_EINVAL, "lambda must be finite and > 0");
+    if (!ctx->loaded) return fail(ctx, TVS_ESTATE, "tvs_autotune before tvs_load_histories");
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, ctx->cfg.device));
+    char key[512];
+    std::snprintf(key, sizeof(key), "%s|%dx%dx%d|%.6gx%.6gx%.6g|H%lld|B%d|P%d", prop.gcnArchName,
+                  ctx->grid.nx, ctx->grid.ny, ctx->grid.nz, ctx->grid.vx, ctx->grid.vy,
+                  ctx->grid.vz, (long long)ctx->nh, ctx->cfg.block_size, ctx->cfg.path_mode);
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char line[1024];
+            while (std::fgets(line, sizeof(line), f)) {
+                char k[512];
+                int l = 0, sw = 0;
+                double ms = 0;
+                if (std::sscanf(line, "%511s %d %d %lf", k, &l, &sw, &ms) == 4 &&
+                    std::strcmp(k, key) == 0 && (l == 16 || l == 32 || l == 64) &&
+                    (sw == 1 || sw == 2)) {
+                    out->lanes_per_row = l;
+                    out->sweep_kernel = sw;
+                    out->ms_per_block = ms;
+                    out->from_cache = 1;
+                }
+            }
+            std::fclose(f);
+        }
+        if (out->from_cache) {
+            ctx->lpr = out->lanes_per_row;
+            ctx->pgrid = (out->sweep_kernel == 2 && !ctx->csc)
+                             ? tvs::persistent_grid_size(ctx->cfg.device, ctx->lpr) : 0;
+            return TVS_OK;
+        }
+    }
+    const int64_t B = ctx->cfg.block_size;
+    const int64_t T = (ctx->nh + B - 1) / B;
+    const int64_t nb = std::min<int64_t>(T, 48);
+    if (nb == 0) {
+        out->lanes_per_row = ctx->lpr;
+        out->sweep_kernel = ctx->pgrid > 0 ? 2 : 1;
+        return TVS_OK;
+    }
+    double *saved = nullptr;
+    int rc = dalloc(ctx, &saved, (size_t)ctx->nvox);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(saved, ctx->x, sizeof(double) * ctx->nvox, hipMemcpyDeviceToDevice, st));
+    const int lprs[3] = {16, 32, 64};
+    const int old_lpr = ctx->lpr, old_pgrid = ctx->pgrid;
+    double best = 1e300;
+    int nc = 0;
+    for (int sw = 1; sw <= 2 && rc == TVS_OK; sw++) {
+        if (sw == 2 && ctx->csc) break;   // path stores use the voxel-major launches
+        for (int li = 0; li < 3 && rc == TVS_OK; li++) {
+            ctx->lpr = lprs[li];
+            ctx->pgrid = (sw == 2) ? tvs::persistent_grid_size(ctx->cfg.device, ctx->lpr) : 0;
+            if (sw == 2 && ctx->pgrid <= 0) continue;
+            double tbest = 1e300;
+            for (int rep = 0; rep < 3 && rc == TVS_OK; rep++) {
+                ctx->tev_used = 0;
+                ctx->spans.clear();
+                long a = mark(ctx, st);
+                rc = run_sweep(ctx, lambda, st, nb * B);
+                long b = mark(ctx, st);
+                if (rc) break;
+                hipError_t e = hipMemcpyAsync(ctx->x, saved, sizeof(double) * ctx->nvox,
+                                              hipMemcpyDeviceToDevice, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                float ms = 0;
+                if (e == hipSuccess && a >= 0 && b >= 0)
+                    e = hipEventElapsedTime(&ms, ctx->tev[(size_t)a], ctx->tev[(size_t)b]);
+                if (e != hipSuccess) {
+                    rc = fail(ctx, TVS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+                    break;
+                }
+                if (rep > 0) tbest = std::min(tbest, (double)ms / nb);   // rep 0 warms up
+            }
+            if (rc) break;
+            if (nc < 8) {
+                out->cand_lanes[nc] = lprs[li];
+                out->cand_sweep[nc] = sw;
+                out->cand_ms[nc] = tbest;
+                nc++;
+            }
+            if (tbest < best) {
+                best = tbest;
+                out->lanes_per_row = lprs[li];
+                out->sweep_kernel = sw;
+                out->ms_per_block = tbest;
+            }
+        }
+    }
+    dfree(ctx, &saved, (size_t)ctx->nvox);
+    ctx->tev_used = 0;
+    ctx->spans.clear();
+    ctx->timed = false;
+    out->n_candidates = nc;
+    if (rc || best == 1e300) {
+        ctx->lpr = old_lpr;
+        ctx->pgrid = old_pgrid;
+        return rc ? rc : fail(ctx, TVS_EDEVICE, "autotune: no candidate ran");
+    }
+    ctx->lpr = out->lanes_per_row;
+    ctx->pgrid = (out->sweep_kernel == 2) ? tvs::persistent_grid_size(ctx->cfg.device, ctx->lpr) : 0;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s %d %d %.6f\n", key, out->lanes_per_row, out->sweep_kernel,
+                         out->ms_per_block);
+            std::fclose(f);
+        }
+    }
     return TVS_OK;
 }
 

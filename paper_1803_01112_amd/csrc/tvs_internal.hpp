@@ -78,9 +78,10 @@ struct DropBuffers {
 
 // One DROP block [r0, r1) (global history indices inside rs) with the
 // one-launch-per-phase kernels; `parity` selects the touched counter.
+// `mid` (may be null) is recorded between the block's two launches.
 hipError_t launch_drop_block(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                              double lambda, const DropBuffers &b, int parity, int lanes_per_row,
-                             hipStream_t stream);
+                             hipStream_t stream, hipEvent_t mid = nullptr);
 // All blocks of rs in one persistent launch with grid barriers.
 hipError_t launch_drop_persistent(const RowSet &rs, const float *wepl, int64_t block_size,
                                   double lambda, const DropBuffers &b, int lanes_per_row,
@@ -103,7 +104,7 @@ struct CscBlock {
 // Residual launch + voxel-major apply launch of one block (no atomics).
 hipError_t launch_drop_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                                  double lambda, const CscBlock &cb, double *x, double *rbuf,
-                                 int lanes_per_row, hipStream_t stream);
+                                 int lanes_per_row, hipStream_t stream, hipEvent_t mid = nullptr);
 // Build steps of the voxel-major form for a batch of nb blocks from b0.
 hipError_t csc_count(const RowSet &rs, int64_t r0, int64_t r1, int64_t block_size, int64_t b0,
                      int64_t nvox, uint32_t *cnt, hipStream_t st);

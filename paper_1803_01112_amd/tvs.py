@@ -26,7 +26,7 @@ EXPORTED = ("tvs_config_default", "tvs_create", "tvs_destroy", "tvs_load_histori
             "tvs_debug_rows", "tvs_strerror", "tvs_last_error", "tvs_iterate_batch",
             "tvs_get_batch_image", "tvs_server_config_default", "tvs_server_create",
             "tvs_server_footprint", "tvs_server_submit", "tvs_server_query", "tvs_server_wait",
-            "tvs_server_get_counters", "tvs_server_destroy")
+            "tvs_server_get_counters", "tvs_server_destroy", "tvs_autotune")
 
 
 class TvsError(RuntimeError):
@@ -46,7 +46,7 @@ class Config(C.Structure):
                 ("mlp_log_term", C.c_int32), ("mlp_const_power", C.c_int32),
                 ("chunk_histories", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
                 ("device", C.c_int32), ("max_tries", C.c_int32), ("sweep_kernel", C.c_int32),
-                ("wave_rows", C.c_int32)]
+                ("wave_rows", C.c_int32), ("time_sample", C.c_int32)]
 
 
 _FP = C.POINTER(C.c_float)
@@ -71,7 +71,8 @@ class Stats(C.Structure):
                 ("sweep_ms_total", C.c_double), ("rows_ms_total", C.c_double),
                 ("drop_ms_total", C.c_double), ("cycles_timed", C.c_int64),
                 ("rows_launches", C.c_int64), ("drop_launches", C.c_int64),
-                ("batch_ms_total", C.c_double), ("batch_cycles", C.c_int64),
+                ("k1_ms_total", C.c_double), ("k2_ms_total", C.c_double),
+                ("k_samples", C.c_int64), ("batch_ms_total", C.c_double), ("batch_cycles", C.c_int64),
                 ("batch_size", C.c_int32), ("pad", C.c_int32)]
 
 
@@ -79,6 +80,13 @@ class StepLog(C.Structure):
     _fields_ = [("k", C.c_int32), ("n", C.c_int32), ("tries", C.c_int32), ("accepted", C.c_int32),
                 ("ell_start", C.c_int64), ("phi_x", C.c_double), ("phi_z", C.c_double),
                 ("gnorm", C.c_double)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("lanes_per_row", C.c_int32), ("sweep_kernel", C.c_int32),
+                ("ms_per_block", C.c_double), ("from_cache", C.c_int32),
+                ("n_candidates", C.c_int32), ("cand_lanes", C.c_int32 * 8),
+                ("cand_sweep", C.c_int32 * 8), ("cand_ms", C.c_double * 8)]
 
 
 class ServerConfig(C.Structure):
@@ -138,6 +146,8 @@ def load_library(path: str = LIB):
     L.tvs_strerror.restype = C.c_char_p
     L.tvs_last_error.argtypes = [C.c_void_p]
     L.tvs_last_error.restype = C.c_char_p
+    L.tvs_autotune.argtypes = [C.c_void_p, C.c_double, C.c_char_p, P(TuneResult), C.c_void_p]
+    L.tvs_autotune.restype = C.c_int
     L.tvs_server_config_default.argtypes = [P(ServerConfig)]
     L.tvs_server_config_default.restype = None
     L.tvs_server_create.argtypes = [P(ServerConfig), P(C.c_void_p)]
@@ -199,7 +209,8 @@ class Context:
 
     def __init__(self, grid, *, block_size=3200, path_mode="otf", mlp_step_mm=0.0,
                  mlp_log_term=True, mlp_const_power=False, chunk_histories=0,
-                 hbm_budget_bytes=0, device=0, max_tries=0, sweep_kernel=0, wave_rows=0):
+                 hbm_budget_bytes=0, device=0, max_tries=0, sweep_kernel=0, wave_rows=0,
+                 time_sample=0):
         self._L = load_library()
         self.grid = grid
         self.nvox = int(grid.nx) * int(grid.ny) * int(grid.nz)
@@ -215,6 +226,7 @@ class Context:
         cfg.max_tries = int(max_tries)
         cfg.sweep_kernel = int(sweep_kernel)
         cfg.wave_rows = int(wave_rows)
+        cfg.time_sample = int(time_sample)
         self.cfg = cfg
         h = C.c_void_p()
         g = grid_struct(grid)
@@ -292,6 +304,18 @@ class Context:
                             int(st.get("seed", 0)) & (2**64 - 1), float(st.get("gamma", 0.5)))
         self._check(self._L.tvs_iterate_batch(self._h, arr, S, int(K), _stream_handle(stream)),
                     "tvs_iterate_batch")
+
+    def autotune(self, lam=1e-4, cache_path=None, stream=None):
+        """Times the launch-shape candidates and keeps the fastest; returns a dict."""
+        r = TuneResult()
+        cp = cache_path.encode() if cache_path else None
+        self._check(self._L.tvs_autotune(self._h, float(lam), cp, C.byref(r),
+                                         _stream_handle(stream)), "tvs_autotune")
+        n = r.n_candidates
+        return dict(lanes_per_row=r.lanes_per_row, sweep_kernel=r.sweep_kernel,
+                    ms_per_block=r.ms_per_block, from_cache=bool(r.from_cache),
+                    candidates=[dict(lanes=r.cand_lanes[q], sweep=r.cand_sweep[q],
+                                     ms=r.cand_ms[q]) for q in range(n)])
 
     def get_batch_image(self, s, out=None, stream=None):
         if out is None:
