@@ -54,7 +54,8 @@ def mlp_vertices(h, step):
 
 
 def run_form(tvs, torch, w, dev_hist, x0, args, path_mode, K, W):
-    ctx = tvs.Context(w.grid, block_size=args.block, path_mode=path_mode)
+    ctx = tvs.Context(w.grid, block_size=args.block, path_mode=path_mode,
+                      time_sample=args.time_sample)
     t0 = time.perf_counter()
     ctx.load_histories(dev_hist)
     torch.cuda.synchronize()
@@ -201,6 +202,8 @@ def main():
     ap.add_argument("--check", type=int, default=0)
     ap.add_argument("--seed", type=int, default=1803011121)
     ap.add_argument("--path-mode", default="otf")
+    ap.add_argument("--time-sample", type=int, default=16,
+                    help="HIP events around both launches of every k-th DROP block")
     ap.add_argument("--forms", default="f32,f16", help="extra path-store forms to time")
     ap.add_argument("--latency-cycles", type=int, default=6)
     ap.add_argument("--cpu-sample", type=int, default=400_000)
@@ -256,25 +259,43 @@ def main():
         lat.append(1e3 * (time.perf_counter() - t0))
     ctx.close()
 
-    # dominant kernel of the timed region
-    drop_ms = st["drop_ms_total"] / max(st["drop_launches"], 1)
-    rows_ms = st["rows_ms_total"] / max(st["rows_launches"], 1)
+    # dominant kernel of the timed region: the two launches of a DROP block
+    # (timed with HIP events on every k-th block) and the row formation
     nnz = st["nnz"]
-    if st["rows_ms_total"] > st["drop_ms_total"]:
-        flops_sweep = FP64_FLOPS_PER_VERTEX * vertices
-        per_launch = flops_sweep / max(st["rows_launches"] / max(st["cycles_timed"], 1), 1)
+    T = math.ceil(H / args.block)
+    ns = max(st["k_samples"], 1)
+    k1_ms, k2_ms = st["k1_ms_total"] / ns, st["k2_ms_total"] / ns
+    rows_ms = st["rows_ms_total"] / max(st["rows_launches"], 1)
+    chord_b = {"otf": 4, "f32": 4, "f16": 2}[args.path_mode]
+    names = {"otf": ("k_drop_rows_packed", "k_drop_apply_packed"),
+             "f32": ("k_drop_resid", "k_drop_apply_csc"),
+             "f16": ("k_drop_resid", "k_drop_apply_csc")}[args.path_mode]
+    per_cycle = {names[0]: k1_ms * T, names[1]: k2_ms * T}
+    if args.path_mode == "otf":
+        per_cycle["k_rows_fill"] = st["rows_ms_total"] / max(st["cycles_timed"], 1)
+    dom = max(per_cycle, key=per_cycle.get)
+    if dom == "k_rows_fill":
+        launches = max(st["rows_launches"] / max(st["cycles_timed"], 1), 1)
+        per_launch = FP64_FLOPS_PER_VERTEX * vertices / launches
         achieved = per_launch / (rows_ms * 1e-3) / 1e12
-        roof = dict(bound="alu", kernel="k_rows_fill (float64 MLP + walk)", achieved=achieved,
-                    peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS,
-                    traffic=None, avg_launch_ms=rows_ms)
+        roof = dict(bound="alu", kernel=dom, achieved=achieved, peak=FP64_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS, traffic=None,
+                    avg_launch_ms=rows_ms, algorithmic_per_launch=per_launch)
     else:
-        chord_b = {"otf": 4, "f32": 4, "f16": 2}[args.path_mode]
-        launches_per_sweep = max(st["drop_launches"] / max(st["cycles_timed"], 1), 1)
-        per_launch = row_stream_bytes(H, nnz, chord_b) / launches_per_sweep
-        achieved = per_launch / (drop_ms * 1e-3) / 1e9
-        roof = dict(bound="hbm", kernel="k_drop_persistent", achieved=achieved,
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
-                    avg_launch_ms=drop_ms)
+        if dom == names[0]:
+            per_launch = row_stream_bytes(H, nnz, chord_b) / T
+            avg = k1_ms
+        elif args.path_mode == "otf":
+            per_launch = 8.0 * w.grid.nvox          # packed words of the dense pass
+            avg = k2_ms
+        else:
+            per_launch = (6.0 if chord_b == 4 else 4.0) * nnz / T
+            avg = k2_ms
+        achieved = per_launch / (avg * 1e-3) / 1e9
+        roof = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_ms=avg,
+                    algorithmic_per_launch=per_launch)
+    roof["per_cycle_ms"] = per_cycle
 
     forms = {}
     for form in [f for f in args.forms.split(",") if f]:

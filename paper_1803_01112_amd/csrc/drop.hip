@@ -149,6 +149,62 @@ k_drop_rows_dense(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int
     }
 }
 
+// Packed scatter: correction and hit count of an entry in one 64-bit integer
+// atomic.  Bits 48..63 count hits; bits 0..47 hold the correction in two's-
+// complement fixed point with kFrac fraction bits (exact, order-independent
+// integer sums).  A contribution larger than `big` (chosen by the host so
+// that no voxel's sum can leave the 48-bit field) goes to a float64 atomic
+// instead, with a count-only packed increment.
+constexpr int kFrac = 30;
+constexpr double kScale = (double)(1ull << kFrac);
+constexpr uint64_t kHit = 1ull << 48;
+
+template <int LPR, typename CH>
+__global__ void __launch_bounds__(kThreads)
+k_drop_rows_packed(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1,
+                   const double *x, unsigned long long *P, double *c64, double big)
+{
+    const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
+    if (row >= r1) return;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int64_t lr = row - rs.first;
+    const float n2 = rs.norm2[lr];
+    if (!(n2 > 0.0f)) return;
+    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
+    double acc = 0.0;
+    for (int64_t e = off + lane; e < end; e += LPR)
+        acc += (double)chord_at(chord, e) * x[rs.idx[e]];
+    acc = group_sum<LPR>(acc);
+    const double r = ((double)wepl[row] - acc) / (double)n2;
+    for (int64_t e = off + lane; e < end; e += LPR) {
+        const int32_t j = rs.idx[e];
+        const double v = r * (double)chord_at(chord, e);
+        if (fabs(v) <= big) {
+            const long long f = __double2ll_rn(v * kScale);
+            atomicAdd(P + j, (unsigned long long)kHit + (unsigned long long)f);
+        } else {
+            unsafeAtomicAdd(c64 + j, v);
+            atomicAdd(P + j, (unsigned long long)kHit);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_drop_apply_packed(double lambda, double *x, unsigned long long *P, double *c64, int64_t nvox)
+{
+    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < nvox;
+         j += (int64_t)gridDim.x * kThreads) {
+        const unsigned long long p = P[j];
+        if (p == 0ull) continue;
+        const unsigned long long hits = (p + (1ull << 47)) >> 48;
+        const long long fixed = (long long)(p - (hits << 48));
+        const double c = (double)fixed * (1.0 / kScale) + c64[j];
+        x[j] += lambda * c / (double)hits;
+        P[j] = 0ull;
+        c64[j] = 0.0;
+    }
+}
+
 // Dense apply: every voxel with hits in the block takes its correction and
 // clears its accumulators (a coalesced pass over the hit counts).
 __global__ void __launch_bounds__(kThreads)
@@ -208,6 +264,21 @@ hipError_t block_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t
     const int64_t rows = r1 - r0;
     if (rows <= 0) return hipSuccess;
     dim3 grid((unsigned)((rows * LPR + kThreads - 1) / kThreads));
+    if (b.c64) {
+        unsigned long long *P = reinterpret_cast<unsigned long long *>(b.c);
+        if (rs.chord16)
+            hipLaunchKernelGGL((k_drop_rows_packed<LPR, __half>), grid, dim3(kThreads), 0, stream,
+                               rs, rs.chord16, wepl, r0, r1, b.x, P, b.c64, b.big);
+        else
+            hipLaunchKernelGGL((k_drop_rows_packed<LPR, float>), grid, dim3(kThreads), 0, stream,
+                               rs, rs.chord32, wepl, r0, r1, b.x, P, b.c64, b.big);
+        if (mid && hipEventRecord(mid, stream) != hipSuccess) return hipErrorInvalidValue;
+        int64_t wgs = (b.nvox + kThreads - 1) / kThreads;
+        if (wgs > 8192) wgs = 8192;
+        hipLaunchKernelGGL(k_drop_apply_packed, dim3((unsigned)wgs), dim3(kThreads), 0, stream,
+                           lambda, b.x, P, b.c64, b.nvox);
+        return hipGetLastError();
+    }
     if (rs.chord16)
         hipLaunchKernelGGL((k_drop_rows_dense<LPR, __half>), grid, dim3(kThreads), 0, stream, rs,
                            rs.chord16, wepl, r0, r1, b.x, b.c, b.s);

@@ -65,6 +65,7 @@ struct tvs_ctx {
 
     // image-side buffers (image, subgradient and corrections float64)
     double *x = nullptr, *g = nullptr, *c = nullptr;
+    double *c64 = nullptr;          // float64 part of large packed contributions
     float *xio = nullptr;           // float32 staging of the image at the ABI
     uint32_t *s = nullptr;
     int32_t *touched = nullptr;
@@ -257,8 +258,16 @@ HistDev hist_dev(const tvs_ctx *ctx)
 
 tvs::DropBuffers drop_bufs(tvs_ctx *ctx)
 {
-    return tvs::DropBuffers{ctx->x, ctx->c, ctx->s, ctx->touched, ctx->ntouched,
-                            ctx->ntouched + 2, ctx->nvox};
+    tvs::DropBuffers b{ctx->x, ctx->c, ctx->s, ctx->touched, ctx->ntouched, ctx->ntouched + 2,
+                       ctx->nvox};
+    // Packed scatter (one 64-bit atomic per entry) when the hit count of a
+    // voxel in a block stays below 2^16: at most 8 entries per row and voxel.
+    const int64_t B = ctx->cfg.block_size;
+    if (B <= 8191) {
+        b.c64 = ctx->c64;
+        b.big = 65536.0 / (8.0 * (double)B);    // 2^(47-30) / (16 B): a factor 2 to spare
+    }
+    return b;
 }
 
 tvs::TvBuffers tv_bufs(tvs_ctx *ctx)
@@ -630,6 +639,7 @@ void tvs_destroy(tvs_ctx *ctx)
     dfree(ctx, &ctx->x, (size_t)ctx->nvox);
     dfree(ctx, &ctx->xio, (size_t)ctx->nvox);
     dfree(ctx, &ctx->c, (size_t)ctx->nvox);
+    dfree(ctx, &ctx->c64, (size_t)ctx->nvox);
     dfree(ctx, &ctx->g, (size_t)ctx->nvox);
     dfree(ctx, &ctx->s, (size_t)ctx->nvox);
     dfree(ctx, &ctx->touched, (size_t)ctx->nvox);
@@ -700,6 +710,7 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (!rc) rc = dalloc(ctx, &ctx->x0, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->xio, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->c, (size_t)nvox);
+    if (!rc) rc = dalloc(ctx, &ctx->c64, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->g, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->s, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->touched, (size_t)nvox);
@@ -728,6 +739,7 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (e == hipSuccess) e = hipMemsetAsync(ctx->x, 0, sizeof(double) * nvox, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->x0, 0, sizeof(double) * nvox, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->c, 0, sizeof(double) * nvox, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->c64, 0, sizeof(double) * nvox, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->s, 0, sizeof(uint32_t) * nvox, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->ntouched, 0, sizeof(uint32_t) * 8, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->ticket, 0, sizeof(uint32_t) * 4, ctx->stream);

@@ -74,6 +74,9 @@ struct DropBuffers {
     uint32_t *ntouched;  // two counters used alternately by consecutive blocks
     uint32_t *barrier;   // persistent sweep: grid barrier counter + error flag
     int64_t nvox;
+    double *c64 = nullptr;   // non-null: packed per-block scatter (c holds the packed words,
+                             // c64 the float64 part of large contributions)
+    double big = 0.0;        // largest contribution taken in fixed point
 };
 
 // One DROP block [r0, r1) (global history indices inside rs) with the
