@@ -34,13 +34,14 @@ k_tvb_grad(GridDev G, const double *x, int S, int V, uint32_t active, const doub
     const int t = threadIdx.x;
     const int v = t / S, s = t - v * S;
     const int64_t nx = G.nx, ny = G.ny;
-    const int64_t nvox = nx * ny * (int64_t)G.nz;
-    const int64_t p = (int64_t)blockIdx.x * V + v;
+    const int64_t nvox = padded_voxels(G);
+    const int64_t p = (int64_t)blockIdx.x * V + v;     // brick-layout word
+    int64_t i = 0, j = 0, k = 0;
+    if (p < nvox) vcoord(G, p, i, j, k);
     double sq = 0.0;
-    if (v < V && p < nvox && ((active >> s) & 1u)) {
-        const int64_t i = p % nx, j = (p / nx) % ny;
+    if (v < V && p < nvox && i < nx && j < ny && ((active >> s) & 1u)) {
         const double e2 = eps[s] * eps[s];
-        auto X = [&](int64_t di, int64_t dj) { return x[(p + di + dj * nx) * S + s]; };
+        auto X = [&](int64_t di, int64_t dj) { return x[vaddr(G, i + di, j + dj, k) * S + s]; };
         auto dxf = [&](int64_t ii, int64_t jj) {
             return (i + ii + 1 < nx) ? X(ii + 1, jj) - X(ii, jj) : 0.0;
         };
@@ -133,11 +134,14 @@ k_replicate(const double *x0, double *xb, int S, int64_t nvox)
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_extract(const double *xb, int S, int s, float *out, int64_t nvox)
+k_extract(GridDev G, const double *xb, int S, int s, float *out)
 {
-    for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < nvox;
-         p += (int64_t)gridDim.x * kThreads)
-        out[p] = (float)xb[p * S + s];
+    const int64_t n = (int64_t)G.nx * G.ny * G.nz;
+    for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = p % G.nx, t = p / G.nx, j = t % G.ny, k = t / G.ny;
+        out[p] = (float)xb[vaddr(G, i, j, k) * S + s];
+    }
 }
 
 __global__ void __launch_bounds__(kThreads) k_zero_d(double *p, int64_t n)
@@ -359,7 +363,7 @@ int batch_vox_per_wg(int S) { return kThreads / S; }
 
 int64_t batch_num_parts(const GridDev &g, int S)
 {
-    const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t nvox = padded_voxels(g);
     const int V = batch_vox_per_wg(S);
     return (nvox + V - 1) / V;
 }
@@ -404,10 +408,12 @@ hipError_t launch_replicate(const double *x0, const BatchBuffers &b, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_extract(const BatchBuffers &b, int s, float *out, hipStream_t stream)
+hipError_t launch_extract(const GridDev &g, const BatchBuffers &b, int s, float *out,
+                          hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_extract, dim3(elem_grid(b.nvox)), dim3(kThreads), 0, stream, b.x, b.S, s,
-                       out, b.nvox);
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_extract, dim3(elem_grid(n)), dim3(kThreads), 0, stream, g, b.x, b.S, s,
+                       out);
     return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@
 // per sweep with a device-wide barrier between phases.  The barrier spins a
 // bounded number of times; on timeout it raises an error flag that makes
 // every workgroup leave, and the host reports a device error.
+#include <hip/hip_ext.h>
+
 #include "device_common.hpp"
 #include "tvs_internal.hpp"
 
@@ -154,15 +156,23 @@ k_drop_rows_dense(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int
 // complement fixed point with kFrac fraction bits (exact, order-independent
 // integer sums).  A contribution larger than `big` (chosen by the host so
 // that no voxel's sum can leave the 48-bit field) goes to a float64 atomic
-// instead, with a count-only packed increment.
+// instead, with a count-only packed increment, and sets the voxel's bit in
+// the outlier mask so that the apply reads the float64 part only there.
 constexpr int kFrac = 30;
 constexpr double kScale = (double)(1ull << kFrac);
 constexpr uint64_t kHit = 1ull << 48;
 
+// The first kHeld chunks of LPR entries of a row are loaded once, all at
+// once (their gathers then overlap instead of forming a chain), and kept in
+// registers for the scatter; entries past them are streamed twice.  Every
+// lane sums its entries in ascending order either way.
+constexpr int kHeld = 4;
+
 template <int LPR, typename CH>
 __global__ void __launch_bounds__(kThreads)
 k_drop_rows_packed(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1,
-                   const double *x, unsigned long long *P, double *c64, double big)
+                   const double *x, unsigned long long *P, double *c64, uint32_t *omask,
+                   double big)
 {
     const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
     if (row >= r1) return;
@@ -171,37 +181,67 @@ k_drop_rows_packed(RowSet rs, const CH *chord, const float *wepl, int64_t r0, in
     const float n2 = rs.norm2[lr];
     if (!(n2 > 0.0f)) return;
     const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
+    int32_t jh[kHeld];
+    float ch[kHeld];
+#pragma unroll
+    for (int u = 0; u < kHeld; u++) {
+        const int64_t e = off + lane + (int64_t)u * LPR;
+        jh[u] = (e < end) ? rs.idx[e] : -1;
+        ch[u] = (e < end) ? chord_at(chord, e) : 0.0f;
+    }
+    double xh[kHeld];
+#pragma unroll
+    for (int u = 0; u < kHeld; u++) xh[u] = (jh[u] >= 0) ? x[jh[u]] : 0.0;
     double acc = 0.0;
-    for (int64_t e = off + lane; e < end; e += LPR)
+#pragma unroll
+    for (int u = 0; u < kHeld; u++)
+        if (jh[u] >= 0) acc += (double)ch[u] * xh[u];
+    for (int64_t e = off + lane + (int64_t)kHeld * LPR; e < end; e += LPR)
         acc += (double)chord_at(chord, e) * x[rs.idx[e]];
     acc = group_sum<LPR>(acc);
     const double r = ((double)wepl[row] - acc) / (double)n2;
-    for (int64_t e = off + lane; e < end; e += LPR) {
-        const int32_t j = rs.idx[e];
-        const double v = r * (double)chord_at(chord, e);
+    auto scatter = [&](int32_t j, float a) {
+        const double v = r * (double)a;
         if (fabs(v) <= big) {
             const long long f = __double2ll_rn(v * kScale);
             atomicAdd(P + j, (unsigned long long)kHit + (unsigned long long)f);
         } else {
             unsafeAtomicAdd(c64 + j, v);
             atomicAdd(P + j, (unsigned long long)kHit);
+            atomicOr(omask + (j >> 5), 1u << (j & 31));
         }
-    }
+    };
+#pragma unroll
+    for (int u = 0; u < kHeld; u++)
+        if (jh[u] >= 0) scatter(jh[u], ch[u]);
+    for (int64_t e = off + lane + (int64_t)kHeld * LPR; e < end; e += LPR)
+        scatter(rs.idx[e], chord_at(chord, e));
 }
 
+// Voxel j is handled by a lane of the same wavefront instruction as the 31
+// other voxels of its mask word (the stride is a multiple of 32), so the
+// word's first lane may clear it right after the wavefront has read it.
 __global__ void __launch_bounds__(kThreads)
-k_drop_apply_packed(double lambda, double *x, unsigned long long *P, double *c64, int64_t nvox)
+k_drop_apply_packed(double lambda, double *x, unsigned long long *P, double *c64,
+                    uint32_t *omask, int64_t nvox)
 {
     for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < nvox;
          j += (int64_t)gridDim.x * kThreads) {
+        // x is read with P (not after testing P) so the two loads overlap
         const unsigned long long p = P[j];
+        const uint32_t m = omask[j >> 5];
+        const double xj = x[j];
+        if (m != 0u && (j & 31) == 0) omask[j >> 5] = 0u;
         if (p == 0ull) continue;
         const unsigned long long hits = (p + (1ull << 47)) >> 48;
         const long long fixed = (long long)(p - (hits << 48));
-        const double c = (double)fixed * (1.0 / kScale) + c64[j];
-        x[j] += lambda * c / (double)hits;
+        double c = (double)fixed * (1.0 / kScale);
+        if ((m >> (j & 31)) & 1u) {
+            c += c64[j];
+            c64[j] = 0.0;
+        }
+        x[j] = xj + lambda * c / (double)hits;
         P[j] = 0ull;
-        c64[j] = 0.0;
     }
 }
 
@@ -232,8 +272,22 @@ k_drop_resid(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t 
     const int64_t lr = row - rs.first;
     const float n2 = rs.norm2[lr];
     const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
+    int32_t jh[kHeld];
+    float ch[kHeld];
+#pragma unroll
+    for (int u = 0; u < kHeld; u++) {
+        const int64_t e = off + lane + (int64_t)u * LPR;
+        jh[u] = (e < end) ? rs.idx[e] : -1;
+        ch[u] = (e < end) ? chord_at(chord, e) : 0.0f;
+    }
+    double xh[kHeld];
+#pragma unroll
+    for (int u = 0; u < kHeld; u++) xh[u] = (jh[u] >= 0) ? x[jh[u]] : 0.0;
     double acc = 0.0;
-    for (int64_t e = off + lane; e < end; e += LPR)
+#pragma unroll
+    for (int u = 0; u < kHeld; u++)
+        if (jh[u] >= 0) acc += (double)ch[u] * xh[u];
+    for (int64_t e = off + lane + (int64_t)kHeld * LPR; e < end; e += LPR)
         acc += (double)chord_at(chord, e) * x[rs.idx[e]];
     acc = group_sum<LPR>(acc);
     if (lane == 0) rbuf[row - r0] = (n2 > 0.0f) ? ((double)wepl[row] - acc) / (double)n2 : 0.0;
@@ -250,73 +304,90 @@ k_drop_apply_csc(const int32_t *uvox, const uint32_t *ucol, int64_t U, int64_t n
          u += (int64_t)gridDim.x * kThreads) {
         const int64_t s = ucol[u];
         const int64_t e = (u + 1 < U) ? (int64_t)ucol[u + 1] : ne;
+        const int32_t vj = uvox[u];
+        const double xj = x[vj];          // issued before the column's loads
         double c = 0.0;
-        for (int64_t k = s; k < e; k++) c += rbuf[cq[k]] * (double)chord_at(cch, k);
-        x[uvox[u]] += lambda * c / (double)(e - s);
+        int64_t k = s;
+        for (; k + 2 <= e; k += 2) {      // two entries' loads in flight at once
+            const uint16_t q0 = cq[k], q1 = cq[k + 1];
+            const float a0 = chord_at(cch, k), a1 = chord_at(cch, k + 1);
+            const double b0 = rbuf[q0], b1 = rbuf[q1];
+            c += b0 * (double)a0;
+            c += b1 * (double)a1;
+        }
+        if (k < e) c += rbuf[cq[k]] * (double)chord_at(cch, k);
+        x[vj] = xj + lambda * c / (double)(e - s);
     }
+}
+
+// Launches one kernel; with a timer pair the launch carries its own start and
+// stop events, which take the dispatch's timestamps (no gap around it).
+template <typename F, typename... Args>
+void launch(F kernel, dim3 grid, hipStream_t stream, hipEvent_t t0, hipEvent_t t1,
+            Args... args)
+{
+    hipExtLaunchKernelGGL(kernel, grid, dim3(kThreads), 0, stream, t0, t1, 0u, args...);
 }
 
 template <int LPR>
 hipError_t block_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1, double lambda,
-                        const DropBuffers &b, int parity, hipStream_t stream, hipEvent_t mid)
+                        const DropBuffers &b, hipStream_t stream, const KTimer *kt)
 {
-    (void)parity;
     const int64_t rows = r1 - r0;
     if (rows <= 0) return hipSuccess;
+    const KTimer none{};
+    const KTimer &t = kt ? *kt : none;
     dim3 grid((unsigned)((rows * LPR + kThreads - 1) / kThreads));
+    int64_t wgs = (b.nvox + kThreads - 1) / kThreads;
+    if (wgs > 8192) wgs = 8192;
     if (b.c64) {
         unsigned long long *P = reinterpret_cast<unsigned long long *>(b.c);
         if (rs.chord16)
-            hipLaunchKernelGGL((k_drop_rows_packed<LPR, __half>), grid, dim3(kThreads), 0, stream,
-                               rs, rs.chord16, wepl, r0, r1, b.x, P, b.c64, b.big);
+            launch(k_drop_rows_packed<LPR, __half>, grid, stream, t.e[0], t.e[1], rs, rs.chord16,
+                   wepl, r0, r1, (const double *)b.x, P, b.c64, b.omask, b.big);
         else
-            hipLaunchKernelGGL((k_drop_rows_packed<LPR, float>), grid, dim3(kThreads), 0, stream,
-                               rs, rs.chord32, wepl, r0, r1, b.x, P, b.c64, b.big);
-        if (mid && hipEventRecord(mid, stream) != hipSuccess) return hipErrorInvalidValue;
-        int64_t wgs = (b.nvox + kThreads - 1) / kThreads;
-        if (wgs > 8192) wgs = 8192;
-        hipLaunchKernelGGL(k_drop_apply_packed, dim3((unsigned)wgs), dim3(kThreads), 0, stream,
-                           lambda, b.x, P, b.c64, b.nvox);
+            launch(k_drop_rows_packed<LPR, float>, grid, stream, t.e[0], t.e[1], rs, rs.chord32,
+                   wepl, r0, r1, (const double *)b.x, P, b.c64, b.omask, b.big);
+        launch(k_drop_apply_packed, dim3((unsigned)wgs), stream, t.e[2], t.e[3], lambda, b.x, P,
+               b.c64, b.omask, b.nvox);
         return hipGetLastError();
     }
     if (rs.chord16)
-        hipLaunchKernelGGL((k_drop_rows_dense<LPR, __half>), grid, dim3(kThreads), 0, stream, rs,
-                           rs.chord16, wepl, r0, r1, b.x, b.c, b.s);
+        launch(k_drop_rows_dense<LPR, __half>, grid, stream, t.e[0], t.e[1], rs, rs.chord16, wepl,
+               r0, r1, (const double *)b.x, b.c, b.s);
     else
-        hipLaunchKernelGGL((k_drop_rows_dense<LPR, float>), grid, dim3(kThreads), 0, stream, rs,
-                           rs.chord32, wepl, r0, r1, b.x, b.c, b.s);
-    if (mid && hipEventRecord(mid, stream) != hipSuccess) return hipErrorInvalidValue;
-    int64_t wgs = (b.nvox + kThreads - 1) / kThreads;
-    if (wgs > 8192) wgs = 8192;
-    hipLaunchKernelGGL(k_drop_apply_dense, dim3((unsigned)wgs), dim3(kThreads), 0, stream, lambda,
-                       b.x, b.c, b.s, b.nvox);
+        launch(k_drop_rows_dense<LPR, float>, grid, stream, t.e[0], t.e[1], rs, rs.chord32, wepl,
+               r0, r1, (const double *)b.x, b.c, b.s);
+    launch(k_drop_apply_dense, dim3((unsigned)wgs), stream, t.e[2], t.e[3], lambda, b.x, b.c, b.s,
+           b.nvox);
     return hipGetLastError();
 }
 
 template <int LPR>
 hipError_t csc_block_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                             double lambda, const CscBlock &cb, double *x, double *rbuf,
-                            hipStream_t stream, hipEvent_t mid)
+                            hipStream_t stream, const KTimer *kt)
 {
     const int64_t rows = r1 - r0;
     if (rows <= 0) return hipSuccess;
+    const KTimer none{};
+    const KTimer &t = kt ? *kt : none;
     dim3 grid((unsigned)((rows * LPR + kThreads - 1) / kThreads));
     if (rs.chord16)
-        hipLaunchKernelGGL((k_drop_resid<LPR, __half>), grid, dim3(kThreads), 0, stream, rs,
-                           rs.chord16, wepl, r0, r1, x, rbuf);
+        launch(k_drop_resid<LPR, __half>, grid, stream, t.e[0], t.e[1], rs, rs.chord16, wepl, r0,
+               r1, (const double *)x, rbuf);
     else
-        hipLaunchKernelGGL((k_drop_resid<LPR, float>), grid, dim3(kThreads), 0, stream, rs,
-                           rs.chord32, wepl, r0, r1, x, rbuf);
-    if (mid && hipEventRecord(mid, stream) != hipSuccess) return hipErrorInvalidValue;
+        launch(k_drop_resid<LPR, float>, grid, stream, t.e[0], t.e[1], rs, rs.chord32, wepl, r0,
+               r1, (const double *)x, rbuf);
     if (cb.U <= 0) return hipGetLastError();
     int64_t wgs = (cb.U + kThreads - 1) / kThreads;
     if (wgs > 4096) wgs = 4096;
     if (cb.cch16)
-        hipLaunchKernelGGL((k_drop_apply_csc<__half>), dim3((unsigned)wgs), dim3(kThreads), 0,
-                           stream, cb.uvox, cb.ucol, cb.U, cb.ne, cb.cq, cb.cch16, rbuf, lambda, x);
+        launch(k_drop_apply_csc<__half>, dim3((unsigned)wgs), stream, t.e[2], t.e[3], cb.uvox,
+               cb.ucol, cb.U, cb.ne, cb.cq, cb.cch16, (const double *)rbuf, lambda, x);
     else
-        hipLaunchKernelGGL((k_drop_apply_csc<float>), dim3((unsigned)wgs), dim3(kThreads), 0,
-                           stream, cb.uvox, cb.ucol, cb.U, cb.ne, cb.cq, cb.cch32, rbuf, lambda, x);
+        launch(k_drop_apply_csc<float>, dim3((unsigned)wgs), stream, t.e[2], t.e[3], cb.uvox,
+               cb.ucol, cb.U, cb.ne, cb.cq, cb.cch32, (const double *)rbuf, lambda, x);
     return hipGetLastError();
 }
 
@@ -324,23 +395,24 @@ hipError_t csc_block_launch(const RowSet &rs, const float *wepl, int64_t r0, int
 
 hipError_t launch_drop_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                                  double lambda, const CscBlock &cb, double *x, double *rbuf,
-                                 int lanes_per_row, hipStream_t stream, hipEvent_t mid)
+                                 int lanes_per_row, hipStream_t stream, const KTimer *kt)
 {
     switch (lanes_per_row) {
-    case 16: return csc_block_launch<16>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, mid);
-    case 32: return csc_block_launch<32>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, mid);
-    default: return csc_block_launch<64>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, mid);
+    case 16: return csc_block_launch<16>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, kt);
+    case 32: return csc_block_launch<32>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, kt);
+    default: return csc_block_launch<64>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, kt);
     }
 }
 
 hipError_t launch_drop_block(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                              double lambda, const DropBuffers &b, int parity, int lanes_per_row,
-                             hipStream_t stream, hipEvent_t mid)
+                             hipStream_t stream, const KTimer *kt)
 {
+    (void)parity;
     switch (lanes_per_row) {
-    case 16: return block_launch<16>(rs, wepl, r0, r1, lambda, b, parity, stream, mid);
-    case 32: return block_launch<32>(rs, wepl, r0, r1, lambda, b, parity, stream, mid);
-    default: return block_launch<64>(rs, wepl, r0, r1, lambda, b, parity, stream, mid);
+    case 16: return block_launch<16>(rs, wepl, r0, r1, lambda, b, stream, kt);
+    case 32: return block_launch<32>(rs, wepl, r0, r1, lambda, b, stream, kt);
+    default: return block_launch<64>(rs, wepl, r0, r1, lambda, b, stream, kt);
     }
 }
 

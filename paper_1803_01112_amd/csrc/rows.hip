@@ -151,7 +151,7 @@ __device__ void walk_segment(const GridDev &g, const double q0[3], const double 
                 vi[a] = (int64_t)c;
             }
             if (inside) {
-                int32_t lin = (int32_t)(vi[0] + (int64_t)n[0] * (vi[1] + (int64_t)n[1] * vi[2]));
+                int32_t lin = (int32_t)vaddr(g, vi[0], vi[1], vi[2]);
                 double clen = (tb - ta) * len;
                 if (lin == e.cur) {
                     e.cur_len += clen;

@@ -46,7 +46,9 @@ struct Req {
 uint64_t footprint(const tvs_request &r, int64_t chunk)
 {
     // conservative device bytes of one context (see tvs_server_footprint)
-    const uint64_t nvox = (uint64_t)r.grid.nx * r.grid.ny * r.grid.nz;
+    // image words in the device's brick layout (padding included)
+    const uint64_t nvox = (uint64_t)(((r.grid.nx + 3) / 4) * 4) * (((r.grid.ny + 1) / 2) * 2) *
+                          (uint64_t)r.grid.nz;
     const double vmin = std::min(r.grid.vx, r.grid.vy);
     const double span = (r.grid.nx * r.grid.vx + r.grid.ny * r.grid.vy) / vmin;
     const uint64_t row_est = (uint64_t)(0.8 * span) + (uint64_t)r.grid.nz + 8;

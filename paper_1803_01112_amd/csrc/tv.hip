@@ -27,14 +27,14 @@ constexpr int HX = TX + 2, HY = TY + 2;
 // g != nullptr the staged values are z = x + s*g (the trial image of a
 // checked step), computed exactly as the accepting update computes them.
 __device__ inline void load_tile(double (*t)[HX], const double *x, const double *g, double s,
-                                 int nx, int ny, int64_t zoff, int i0, int j0)
+                                 const GridDev &G, int z, int i0, int j0)
 {
     for (int q = threadIdx.x; q < HX * HY; q += kThreads) {
         int ly = q / HX, lx = q - ly * HX;
         int i = i0 + lx - 1, j = j0 + ly - 1;
         double v = 0.0;
-        if (i >= 0 && i < nx && j >= 0 && j < ny) {
-            int64_t p = zoff + (int64_t)j * nx + i;
+        if (i >= 0 && i < G.nx && j >= 0 && j < G.ny) {
+            int64_t p = vaddr(G, i, j, z);
             v = x[p];
             if (g) v = fma(s, g[p], v);
         }
@@ -111,8 +111,7 @@ k_tv_grad(GridDev G, const double *x, double eps, double *gout, double *part, ui
 {
     __shared__ double tile[HY][HX];
     const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    const int64_t zoff = (int64_t)blockIdx.z * G.nx * G.ny;
-    load_tile(tile, x, nullptr, 0.0, G.nx, G.ny, zoff, i0, j0);
+    load_tile(tile, x, nullptr, 0.0, G, (int)blockIdx.z, i0, j0);
     const int i = i0 + (threadIdx.x % TX), j = j0 + (threadIdx.x / TX);
     double sq = 0.0;
     if (i < G.nx && j < G.ny) {
@@ -128,7 +127,7 @@ k_tv_grad(GridDev G, const double *x, double eps, double *gout, double *part, ui
             double mm = S.m(i, j - 1);
             if (mm > 0.0) gv += S.dy(i, j - 1) / mm;
         }
-        gout[zoff + (int64_t)j * G.nx + i] = gv;
+        gout[vaddr(G, i, j, blockIdx.z)] = gv;
         sq = gv * gv;
     }
     finish_reduction(block_sum(sq), part, ticket, out);
@@ -141,8 +140,7 @@ k_tv_phi(GridDev G, const double *x, const double *g, double beta, const double 
     __shared__ double tile[HY][HX];
     const double s = g ? step_scale(beta, n2) : 0.0;
     const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    const int64_t zoff = (int64_t)blockIdx.z * G.nx * G.ny;
-    load_tile(tile, x, (s != 0.0) ? g : nullptr, s, G.nx, G.ny, zoff, i0, j0);
+    load_tile(tile, x, (s != 0.0) ? g : nullptr, s, G, (int)blockIdx.z, i0, j0);
     const int i = i0 + (threadIdx.x % TX), j = j0 + (threadIdx.x / TX);
     double v = 0.0;
     if (i < G.nx && j < G.ny) {
@@ -162,18 +160,26 @@ k_tv_step(double *x, const double *g, int64_t n, double beta, const double *n2)
         x[p] = fma(s, g[p], x[p]);
 }
 
-__global__ void __launch_bounds__(kThreads) k_widen(const float *src, double *dst, int64_t n)
+// Image in: x-fastest float32 (the ABI order) to the float64 brick layout.
+__global__ void __launch_bounds__(kThreads) k_widen(GridDev G, const float *src, double *dst)
 {
+    const int64_t n = (int64_t)G.nx * G.ny * G.nz;
     for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * kThreads)
-        dst[p] = (double)src[p];
+         p += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = p % G.nx, t = p / G.nx, j = t % G.ny, k = t / G.ny;
+        dst[vaddr(G, i, j, k)] = (double)src[p];
+    }
 }
 
-__global__ void __launch_bounds__(kThreads) k_narrow(const double *src, float *dst, int64_t n)
+// Image out: brick layout to x-fastest float32.
+__global__ void __launch_bounds__(kThreads) k_narrow(GridDev G, const double *src, float *dst)
 {
+    const int64_t n = (int64_t)G.nx * G.ny * G.nz;
     for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * kThreads)
-        dst[p] = (float)src[p];
+         p += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = p % G.nx, t = p / G.nx, j = t % G.ny, k = t / G.ny;
+        dst[p] = (float)src[vaddr(G, i, j, k)];
+    }
 }
 
 __global__ void __launch_bounds__(kThreads) k_fill_zero(float *p, int64_t n)
@@ -215,21 +221,23 @@ hipError_t launch_tv_grad(const GridDev &g, const double *x, double eps, const T
 hipError_t launch_tv_step(const GridDev &g, double *x, double beta, const TvBuffers &t,
                           hipStream_t stream)
 {
-    int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t n = padded_voxels(g);   // the padding's subgradient is zero
     hipLaunchKernelGGL(k_tv_step, dim3(elem_grid(n)), dim3(kThreads), 0, stream, x, t.g, n, beta,
                        t.scal);
     return hipGetLastError();
 }
 
-hipError_t launch_widen(const float *src, double *dst, int64_t n, hipStream_t stream)
+hipError_t launch_widen(const GridDev &g, const float *src, double *dst, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_widen, dim3(elem_grid(n)), dim3(kThreads), 0, stream, src, dst, n);
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_widen, dim3(elem_grid(n)), dim3(kThreads), 0, stream, g, src, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_narrow(const double *src, float *dst, int64_t n, hipStream_t stream)
+hipError_t launch_narrow(const GridDev &g, const double *src, float *dst, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_narrow, dim3(elem_grid(n)), dim3(kThreads), 0, stream, src, dst, n);
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_narrow, dim3(elem_grid(n)), dim3(kThreads), 0, stream, g, src, dst);
     return hipGetLastError();
 }
 

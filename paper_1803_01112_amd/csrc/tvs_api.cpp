@@ -58,7 +58,8 @@ struct tvs_ctx {
     GridDev gd{};
     tvs::MlpCfg mlp{};
     hipStream_t stream = nullptr;
-    int64_t nvox = 0;
+    int64_t nvox = 0;               // words of a device image (brick layout, padding included)
+    int64_t nimg = 0;               // voxels of an image at the ABI (nx * ny * nz)
     uint64_t budget = 0;
     uint64_t bytes = 0;
     std::string err;
@@ -66,6 +67,7 @@ struct tvs_ctx {
     // image-side buffers (image, subgradient and corrections float64)
     double *x = nullptr, *g = nullptr, *c = nullptr;
     double *c64 = nullptr;          // float64 part of large packed contributions
+    uint32_t *omask = nullptr;      // bit per voxel: c64 holds a contribution
     float *xio = nullptr;           // float32 staging of the image at the ABI
     uint32_t *s = nullptr;
     int32_t *touched = nullptr;
@@ -265,6 +267,7 @@ tvs::DropBuffers drop_bufs(tvs_ctx *ctx)
     const int64_t B = ctx->cfg.block_size;
     if (B <= 8191) {
         b.c64 = ctx->c64;
+        b.omask = ctx->omask;
         b.big = 65536.0 / (8.0 * (double)B);    // 2^(47-30) / (16 B): a factor 2 to spare
     }
     return b;
@@ -318,6 +321,20 @@ long slot(tvs_ctx *ctx)
 void span(tvs_ctx *ctx, int kind, long a, long b)
 {
     if (a >= 0 && b >= 0) ctx->spans.push_back({kind, (size_t)a, (size_t)b});
+}
+
+// Four pool events for the kernels of one sampled block: the rows kernel's
+// start/stop (kind 4) and the apply kernel's (kind 5), stamped by the
+// launches themselves.
+bool ktimer(tvs_ctx *ctx, tvs::KTimer &kt)
+{
+    long q[4];
+    for (int i = 0; i < 4; i++)
+        if ((q[i] = slot(ctx)) < 0) return false;
+    for (int i = 0; i < 4; i++) kt.e[i] = ctx->tev[(size_t)q[i]];
+    span(ctx, 4, q[0], q[1]);
+    span(ctx, 5, q[2], q[3]);
+    return true;
 }
 
 // Row set covering histories [first, first + n) of the loaded data, with
@@ -394,15 +411,10 @@ int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st, int64_t limit = -1)
                 if (ctx->cch16) cb.cch16 = ctx->cch16 + ctx->blk_ebase[t];
                 else cb.cch32 = ctx->cch32 + ctx->blk_ebase[t];
                 const bool samp = ctx->cfg.time_sample > 0 && t % ctx->cfg.time_sample == 0;
-                long k0 = samp ? mark(ctx, st) : -1;
-                long km = samp ? slot(ctx) : -1;
+                tvs::KTimer kt;
+                const bool timed = samp && ktimer(ctx, kt);
                 HIPCHK(tvs::launch_drop_block_csc(rs, wepl, r0, r1, lambda, cb, ctx->x, ctx->rbuf,
-                                                  ctx->lpr, st, km >= 0 ? ctx->tev[(size_t)km] : nullptr));
-                if (samp) {
-                    long k2 = mark(ctx, st);
-                    span(ctx, 4, k0, km);
-                    span(ctx, 5, km, k2);
-                }
+                                                  ctx->lpr, st, timed ? &kt : nullptr));
             }
         } else if (persistent) {
             HIPCHK(tvs::launch_drop_persistent(rs, wepl, B, lambda, db, ctx->lpr, ctx->pgrid, st));
@@ -411,15 +423,10 @@ int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st, int64_t limit = -1)
             for (int64_t r0 = first, t = first / B; r0 < first + n; r0 += B, parity ^= 1, t++) {
                 int64_t r1 = std::min(r0 + B, first + n);
                 const bool samp = ctx->cfg.time_sample > 0 && t % ctx->cfg.time_sample == 0;
-                long k0 = samp ? mark(ctx, st) : -1;
-                long km = samp ? slot(ctx) : -1;
+                tvs::KTimer kt;
+                const bool timed = samp && ktimer(ctx, kt);
                 HIPCHK(tvs::launch_drop_block(rs, wepl, r0, r1, lambda, db, parity, ctx->lpr, st,
-                                              km >= 0 ? ctx->tev[(size_t)km] : nullptr));
-                if (samp) {
-                    long k2 = mark(ctx, st);
-                    span(ctx, 4, k0, km);
-                    span(ctx, 5, km, k2);
-                }
+                                              timed ? &kt : nullptr));
             }
             HIPCHK(tvs::launch_zero_counters(ctx->ntouched, st));
         }
@@ -640,6 +647,7 @@ void tvs_destroy(tvs_ctx *ctx)
     dfree(ctx, &ctx->xio, (size_t)ctx->nvox);
     dfree(ctx, &ctx->c, (size_t)ctx->nvox);
     dfree(ctx, &ctx->c64, (size_t)ctx->nvox);
+    dfree(ctx, &ctx->omask, (size_t)(ctx->nvox + 31) / 32);
     dfree(ctx, &ctx->g, (size_t)ctx->nvox);
     dfree(ctx, &ctx->s, (size_t)ctx->nvox);
     dfree(ctx, &ctx->touched, (size_t)ctx->nvox);
@@ -671,7 +679,9 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (!finite_pos(grid->vx) || !finite_pos(grid->vy) || !finite_pos(grid->vz)) return TVS_EINVAL;
     if (!std::isfinite(grid->ox) || !std::isfinite(grid->oy) || !std::isfinite(grid->oz))
         return TVS_EINVAL;
-    int64_t nvox = (int64_t)grid->nx * grid->ny * grid->nz;
+    const tvs::GridDev gdev = tvs::make_grid_dev(*grid);
+    const int64_t nimg = (int64_t)grid->nx * grid->ny * grid->nz;
+    const int64_t nvox = tvs::padded_voxels(gdev);     // device image words (brick layout)
     if (nvox >= ((int64_t)1 << 31)) return TVS_EINVAL;
     if (cfg.block_size < 1) return TVS_EINVAL;
     if (cfg.path_mode < 0 || cfg.path_mode > 2) return TVS_EINVAL;
@@ -689,8 +699,8 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     ctx = new tvs_ctx();
     ctx->grid = *grid;
     ctx->cfg = cfg;
-    ctx->gd = GridDev{grid->nx, grid->ny, grid->nz, grid->vx, grid->vy, grid->vz,
-                      grid->ox, grid->oy, grid->oz};
+    ctx->gd = gdev;
+    ctx->nimg = nimg;
     double step = cfg.mlp_step_mm > 0.0 ? cfg.mlp_step_mm : std::min(grid->vx, grid->vy);
     ctx->mlp = tvs::MlpCfg{step, cfg.mlp_log_term ? 1 : 0, cfg.mlp_const_power ? 1 : 0};
     if (ctx->cfg.max_tries == 0) ctx->cfg.max_tries = 100000;
@@ -711,6 +721,7 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (!rc) rc = dalloc(ctx, &ctx->xio, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->c, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->c64, (size_t)nvox);
+    if (!rc) rc = dalloc(ctx, &ctx->omask, (size_t)(nvox + 31) / 32);
     if (!rc) rc = dalloc(ctx, &ctx->g, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->s, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->touched, (size_t)nvox);
@@ -740,6 +751,8 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (e == hipSuccess) e = hipMemsetAsync(ctx->x0, 0, sizeof(double) * nvox, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->c, 0, sizeof(double) * nvox, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->c64, 0, sizeof(double) * nvox, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(ctx->omask, 0, sizeof(uint32_t) * ((nvox + 31) / 32), ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->s, 0, sizeof(uint32_t) * nvox, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->ntouched, 0, sizeof(uint32_t) * 8, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->ticket, 0, sizeof(uint32_t) * 4, ctx->stream);
@@ -897,12 +910,12 @@ int tvs_set_image(tvs_ctx *ctx, const float *x0, int on_device, void *stream)
     HIPCHK(hipSetDevice(ctx->cfg.device));
     hipStream_t st = pick(ctx, stream);
     if (!on_device) {
-        for (int64_t j = 0; j < ctx->nvox; j++)
+        for (int64_t j = 0; j < ctx->nimg; j++)
             if (!std::isfinite(x0[j])) return fail(ctx, TVS_EINVAL, "image holds NaN/inf");
     }
-    HIPCHK(hipMemcpyAsync(ctx->xio, x0, sizeof(float) * ctx->nvox,
+    HIPCHK(hipMemcpyAsync(ctx->xio, x0, sizeof(float) * ctx->nimg,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-    HIPCHK(tvs::launch_widen(ctx->xio, ctx->x, ctx->nvox, st));
+    HIPCHK(tvs::launch_widen(ctx->gd, ctx->xio, ctx->x, st));
     HIPCHK(hipMemcpyAsync(ctx->x0, ctx->x, sizeof(double) * ctx->nvox, hipMemcpyDeviceToDevice, st));
     if (!on_device) HIPCHK(hipStreamSynchronize(st));
     reset_state(ctx);
@@ -1009,8 +1022,8 @@ int tvs_get_image(tvs_ctx *ctx, float *out, int on_device, void *stream)
     if (!out) return fail(ctx, TVS_EINVAL, "output is NULL");
     HIPCHK(hipSetDevice(ctx->cfg.device));
     hipStream_t st = pick(ctx, stream);
-    HIPCHK(tvs::launch_narrow(ctx->x, ctx->xio, ctx->nvox, st));
-    HIPCHK(hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nvox,
+    HIPCHK(tvs::launch_narrow(ctx->gd, ctx->x, ctx->xio, st));
+    HIPCHK(hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nimg,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
     if (!on_device) HIPCHK(hipStreamSynchronize(st));
     return TVS_OK;
@@ -1134,6 +1147,16 @@ int tvs_debug_rows(tvs_ctx *ctx, int64_t first, int64_t count, int64_t *row_nnz,
         hipError_t e = tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rs, st);
         if (e == hipSuccess && tot > 0)
             e = hipMemcpyAsync(idx, di, sizeof(int32_t) * tot, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) {
+            // brick-layout words to x-fastest voxel indices (the ABI's order)
+            const GridDev &g = ctx->gd;
+            for (int64_t q = 0; q < tot; q++) {
+                int64_t i, j, k;
+                tvs::vcoord(g, idx[q], i, j, k);
+                idx[q] = (int32_t)((k * g.ny + j) * g.nx + i);
+            }
+        }
         if (e == hipSuccess && tot > 0)
             e = hipMemcpyAsync(chord, dc, sizeof(float) * tot, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipMemcpyAsync(norm2, dn, sizeof(float) * count, hipMemcpyDeviceToHost, st);
@@ -1367,8 +1390,8 @@ int tvs_get_batch_image(tvs_ctx *ctx, int32_t s, float *out, int on_device, void
     if (s < 0 || s >= ctx->batch.S) return fail(ctx, TVS_ERANGE, "setting outside the batch");
     HIPCHK(hipSetDevice(ctx->cfg.device));
     hipStream_t st = pick(ctx, stream);
-    HIPCHK(tvs::launch_extract(ctx->batch.b, s, ctx->xio, st));
-    HIPCHK(hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nvox,
+    HIPCHK(tvs::launch_extract(ctx->gd, ctx->batch.b, s, ctx->xio, st));
+    HIPCHK(hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nimg,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
     if (!on_device) HIPCHK(hipStreamSynchronize(st));
     return TVS_OK;

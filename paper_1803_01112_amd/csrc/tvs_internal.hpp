@@ -14,12 +14,52 @@
 
 namespace tvs {
 
-// Voxel grid as the kernels see it.
+// Voxel grid as the kernels see it.  Every device image (and every voxel
+// index a row holds) uses the brick layout below; images cross the ABI in
+// plain x-fastest order and are converted on the way in and out.
 struct GridDev {
     int32_t nx, ny, nz;
     double vx, vy, vz;
     double ox, oy, oz;
+    int32_t nbx, nby;         // bricks per slice along x and y
 };
+
+// Brick layout: each slice is tiled by 4 x 2 (x, y) bricks of 8 float64
+// words, one 64-byte line, bricks x-fastest, slices outermost.  A proton
+// path crosses a brick in a few consecutive entries, so the entries a
+// wavefront gathers or scatters at once touch about a third fewer lines
+// than in x-fastest order (atomics are priced per line).  Voxels past nx / ny
+// in the last brick column / row are padding: never indexed by a row, zero
+// in every image and subgradient.
+constexpr int kBrickX = 4, kBrickY = 2, kBrick = kBrickX * kBrickY;
+
+__host__ __device__ inline int64_t vaddr(const GridDev &g, int64_t i, int64_t j, int64_t k)
+{
+    return (((k * g.nby + (j >> 1)) * g.nbx + (i >> 2)) << 3) + ((j & 1) << 2) + (i & 3);
+}
+
+// Inverse of vaddr: voxel coordinates of brick-layout word a.
+__host__ __device__ inline void vcoord(const GridDev &g, int64_t a, int64_t &i, int64_t &j,
+                                       int64_t &k)
+{
+    const int64_t b = a >> 3, w = a & 7;
+    const int64_t t = b / g.nbx;
+    i = (b - t * g.nbx) * kBrickX + (w & 3);
+    k = t / g.nby;
+    j = (t - k * g.nby) * kBrickY + (w >> 2);
+}
+
+// Words of a device image (padding included).
+__host__ __device__ inline int64_t padded_voxels(const GridDev &g)
+{
+    return (int64_t)g.nbx * g.nby * kBrick * g.nz;
+}
+
+inline GridDev make_grid_dev(const tvs_grid &g)
+{
+    return GridDev{g.nx, g.ny, g.nz, g.vx, g.vy, g.vz, g.ox, g.oy, g.oz,
+                   (g.nx + kBrickX - 1) / kBrickX, (g.ny + kBrickY - 1) / kBrickY};
+}
 
 // SoA history streams on the device (13 float32 arrays of length n_hist).
 struct HistDev {
@@ -68,7 +108,7 @@ hipError_t launch_scan(const int32_t *cnt, int64_t n, int64_t *off, int64_t *tmp
 struct DropBuffers {
     double *x;           // image (float64: keeps the small DROP increments exact
                          // enough for the scale-free TV subgradient)
-    double *c;           // correction sums (float64: see DESIGN, image precision)
+    double *c;           // correction sums (float64, like the image)
     uint32_t *s;         // hit counts
     int32_t *touched;    // voxels touched by the current block (capacity nvox)
     uint32_t *ntouched;  // two counters used alternately by consecutive blocks
@@ -76,15 +116,22 @@ struct DropBuffers {
     int64_t nvox;
     double *c64 = nullptr;   // non-null: packed per-block scatter (c holds the packed words,
                              // c64 the float64 part of large contributions)
+    uint32_t *omask = nullptr;  // one bit per voxel: the float64 part is non-zero
     double big = 0.0;        // largest contribution taken in fixed point
+};
+
+// Start/stop events of the two kernels of one block (the rows kernel, then
+// the apply kernel); null events are not recorded.
+struct KTimer {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 // One DROP block [r0, r1) (global history indices inside rs) with the
 // one-launch-per-phase kernels; `parity` selects the touched counter.
-// `mid` (may be null) is recorded between the block's two launches.
+// `kt` (may be null) times the block's two kernels.
 hipError_t launch_drop_block(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                              double lambda, const DropBuffers &b, int parity, int lanes_per_row,
-                             hipStream_t stream, hipEvent_t mid = nullptr);
+                             hipStream_t stream, const KTimer *kt = nullptr);
 // All blocks of rs in one persistent launch with grid barriers.
 hipError_t launch_drop_persistent(const RowSet &rs, const float *wepl, int64_t block_size,
                                   double lambda, const DropBuffers &b, int lanes_per_row,
@@ -107,7 +154,7 @@ struct CscBlock {
 // Residual launch + voxel-major apply launch of one block (no atomics).
 hipError_t launch_drop_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
                                  double lambda, const CscBlock &cb, double *x, double *rbuf,
-                                 int lanes_per_row, hipStream_t stream, hipEvent_t mid = nullptr);
+                                 int lanes_per_row, hipStream_t stream, const KTimer *kt = nullptr);
 // Build steps of the voxel-major form for a batch of nb blocks from b0.
 hipError_t csc_count(const RowSet &rs, int64_t r0, int64_t r1, int64_t block_size, int64_t b0,
                      int64_t nvox, uint32_t *cnt, hipStream_t st);
@@ -145,8 +192,10 @@ hipError_t launch_tv_step(const GridDev &g, double *x, double beta, const TvBuff
 hipError_t launch_tv_phi(const GridDev &g, const double *x, double beta, double eps,
                          const TvBuffers &t, hipStream_t stream);
 // Image conversions between the float32 ABI and the float64 device image.
-hipError_t launch_widen(const float *src, double *dst, int64_t n, hipStream_t stream);
-hipError_t launch_narrow(const double *src, float *dst, int64_t n, hipStream_t stream);
+// Image conversion between the ABI's x-fastest float32 and the device's
+// float64 brick layout (the padding of dst is left untouched by widen).
+hipError_t launch_widen(const GridDev &g, const float *src, double *dst, hipStream_t stream);
+hipError_t launch_narrow(const GridDev &g, const double *src, float *dst, hipStream_t stream);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream);
 
 // ----------------------------------------------------------------- batch.hip
@@ -179,7 +228,8 @@ hipError_t launch_tvb_step(const BatchBuffers &b, uint32_t active, int n, int nm
 hipError_t launch_set_counter(int32_t *cyc, int32_t v, hipStream_t stream);
 hipError_t launch_tick(int32_t *cyc, hipStream_t stream);
 hipError_t launch_replicate(const double *x0, const BatchBuffers &b, hipStream_t stream);
-hipError_t launch_extract(const BatchBuffers &b, int s, float *out, hipStream_t stream);
+hipError_t launch_extract(const GridDev &g, const BatchBuffers &b, int s, float *out,
+                          hipStream_t stream);
 hipError_t launch_drop_batch(const RowSet &rs, const float *wepl, int64_t block_size,
                              const BatchBuffers &b, int grid_wgs, hipStream_t stream);
 // Voxel-major block of a batch: S residuals per row into rbuf (B*S), then S

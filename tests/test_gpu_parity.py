@@ -75,6 +75,23 @@ def test_drop_only_stress(slice64, path_mode, sweep_kernel):
     assert rel_err(x, S.x) <= TOL
 
 
+def test_packed_scatter_large_contributions(slice64):
+    """B = 8000 from a zero image: the first blocks' contributions exceed the
+    fixed-point range (|v| > 2^16 / 8B), so the float64 side path and its
+    per-voxel mask are exercised and must be cleared between blocks."""
+    w, h, rows = slice64
+    x0 = np.zeros(w.grid.nx * w.grid.ny * w.grid.nz, np.float32)
+    with tvs.Context(w.grid, block_size=8000, mlp_step_mm=2.0, chunk_histories=16000) as ctx:
+        ctx.load_histories(h)
+        ctx.set_image(x0)
+        ctx.iterate(2, 0.05, 0, 0.75, seed=3)
+        x = ctx.get_image()
+    S = oracle.Superiorizer(w.grid, rows, x0, 8000)
+    S.iterate(2, 0.05, 0, 0.75, seed=3)
+    assert np.max(np.abs(S.x)) > 0.05
+    assert rel_err(x, S.x) <= TOL
+
+
 @pytest.mark.parametrize("B,lam", [(3200, 1e-4), (64, 0.05)])
 def test_ntvs_without_check(slice64, B, lam):
     w, h, rows = slice64
@@ -180,6 +197,54 @@ def test_ragged_and_small(n, B):
     S = oracle.Superiorizer(w.grid, rows, x0, B)
     S.iterate(2, 0.05, 2, 0.75, seed=3)
     assert rel_err(x, S.x) <= TOL
+
+
+@pytest.fixture(scope="module")
+def odd_grid():
+    """Histories of the 64x64x4 volume reconstructed on a 61x37x3 grid over its
+    central 44x44x10 mm (paths cross every edge): neither nx nor ny is a
+    multiple of the device's 4x2 voxel bricks, so the last brick column and
+    row are part padding."""
+    w = synth.workload("vol64", n_hist=40_000)
+    h = w.histories()
+    grid = synth.centered_grid(61, 37, 3, 44.0 / 61, 44.0 / 37, 10.0 / 3)
+    rows = oracle.build_rows(grid, h, 1.0)
+    rng = np.random.default_rng(61373)
+    x0 = rng.uniform(0.5, 1.5, 61 * 37 * 3).astype(np.float32)
+    return grid, h, rows, x0
+
+
+@pytest.mark.parametrize("path_mode", ["otf", "f32"])
+def test_odd_grid(odd_grid, path_mode):
+    grid, h, rows, x0 = odd_grid
+    assert len(rows["idx"]) > 0 and rows["idx"].max() < 61 * 37 * 3
+    with tvs.Context(grid, block_size=64, mlp_step_mm=1.0, path_mode=path_mode,
+                     chunk_histories=8192) as ctx:
+        ctx.load_histories(h)
+        check_rows(ctx, rows, 0, len(h["wepl"]))
+        ctx.set_image(x0)
+        np.testing.assert_array_equal(ctx.get_image(), x0)    # layout round trip
+        ctx.iterate(2, 0.01, 3, 0.75, seed=7)
+        x = ctx.get_image()
+    S = oracle.Superiorizer(grid, rows, x0, 64)
+    S.iterate(2, 0.01, 3, 0.75, seed=7)
+    assert np.max(np.abs(S.x - x0)) > 0.05
+    assert rel_err(x, S.x) <= TOL
+
+
+def test_odd_grid_batch(odd_grid):
+    grid, h, rows, x0 = odd_grid
+    sets = [dict(lam=0.01, N=3, alpha=0.75, seed=11), dict(lam=0.005, N=1, alpha=0.5, seed=12),
+            dict(lam=0.01, N=6, alpha=0.95, seed=13)]
+    with tvs.Context(grid, block_size=64, mlp_step_mm=1.0, chunk_histories=8192) as ctx:
+        ctx.load_histories(h)
+        ctx.set_image(x0)
+        ctx.iterate_batch(2, sets)
+        imgs = [ctx.get_batch_image(q) for q in range(len(sets))]
+    for q, st in enumerate(sets):
+        S = oracle.Superiorizer(grid, rows, x0, 64)
+        S.iterate(2, st["lam"], st["N"], st["alpha"], seed=st["seed"])
+        assert rel_err(imgs[q], S.x) <= TOL, q
 
 
 def test_empty_and_skipped_histories():
