@@ -38,11 +38,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def row_stream_bytes(n_hist, nnz, chord_bytes):
-    """Algorithmic HBM bytes of one DROP pass over n_hist rows holding nnz entries:
-    per row an int64 offset, float32 ||a||^2 and float32 WEPL (16 B); per entry an
-    int32 voxel index and a chord of chord_bytes."""
-    return 16.0 * n_hist + (4.0 + chord_bytes) * nnz
+def tile_step_bytes(nnz, nblocks, chord_bytes, nvox, block):
+    """Algorithmic HBM bytes of one DROP step (one launch per block): the tile
+    lists of two blocks read once (block b - 1 finished, block b's dot
+    products formed), 4-byte tag + chord per entry; the image read and written
+    once (float64); per row of both blocks WEPL, ||a||^2 (float32) and the
+    64-bit dot product."""
+    return 2.0 * (4.0 + chord_bytes) * nnz / max(nblocks, 1) + 16.0 * nvox + 32.0 * block
 
 
 def mlp_vertices(h, step):
@@ -259,22 +261,20 @@ def main():
         lat.append(1e3 * (time.perf_counter() - t0))
     ctx.close()
 
-    # dominant kernel of the timed region: the two launches of a DROP block
-    # (timed with HIP events on every k-th block) and the row formation
+    # dominant kernel of the timed region: the DROP step (one launch per
+    # block, timed with kernel-stamped HIP events on every k-th block) or the
+    # row formation on the second stream
     nnz = st["nnz"]
     T = math.ceil(H / args.block)
     ns = max(st["k_samples"], 1)
-    k1_ms, k2_ms = st["k1_ms_total"] / ns, st["k2_ms_total"] / ns
+    k1_ms = st["k1_ms_total"] / ns
     rows_ms = st["rows_ms_total"] / max(st["rows_launches"], 1)
     chord_b = {"otf": 4, "f32": 4, "f16": 2}[args.path_mode]
-    names = {"otf": ("k_drop_rows_packed", "k_drop_apply_packed"),
-             "f32": ("k_drop_resid", "k_drop_apply_csc"),
-             "f16": ("k_drop_resid", "k_drop_apply_csc")}[args.path_mode]
-    per_cycle = {names[0]: k1_ms * T, names[1]: k2_ms * T}
+    per_cycle = {"k_drop_tile": k1_ms * (T + 1)}
     if args.path_mode == "otf":
-        per_cycle["k_rows_fill"] = st["rows_ms_total"] / max(st["cycles_timed"], 1)
+        per_cycle["k_rows_fill_tiled"] = st["rows_ms_total"] / max(st["cycles_timed"], 1)
     dom = max(per_cycle, key=per_cycle.get)
-    if dom == "k_rows_fill":
+    if dom == "k_rows_fill_tiled":
         launches = max(st["rows_launches"] / max(st["cycles_timed"], 1), 1)
         per_launch = FP64_FLOPS_PER_VERTEX * vertices / launches
         achieved = per_launch / (rows_ms * 1e-3) / 1e12
@@ -282,18 +282,10 @@ def main():
                     unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS, traffic=None,
                     avg_launch_ms=rows_ms, algorithmic_per_launch=per_launch)
     else:
-        if dom == names[0]:
-            per_launch = row_stream_bytes(H, nnz, chord_b) / T
-            avg = k1_ms
-        elif args.path_mode == "otf":
-            per_launch = 8.0 * w.grid.nvox          # packed words of the dense pass
-            avg = k2_ms
-        else:
-            per_launch = (6.0 if chord_b == 4 else 4.0) * nnz / T
-            avg = k2_ms
-        achieved = per_launch / (avg * 1e-3) / 1e9
+        per_launch = tile_step_bytes(nnz, T, chord_b, w.grid.nvox, args.block)
+        achieved = per_launch / (k1_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_ms=avg,
+                    frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_ms=k1_ms,
                     algorithmic_per_launch=per_launch)
     roof["per_cycle_ms"] = per_cycle
 
@@ -303,7 +295,7 @@ def main():
         c2, s2, d2, l2 = run_form(tvs, torch, w, dev, x0, args, form, args.steps, 1)
         dms = s2["drop_ms_total"] / max(s2["drop_launches"], 1)
         cb = 2 if form == "f16" else 4
-        gbs = row_stream_bytes(H, s2["nnz"], cb) / (dms * 1e-3) / 1e9
+        gbs = (T + 1) * tile_step_bytes(s2["nnz"], T, cb, w.grid.nvox, args.block) / (dms * 1e-3) / 1e9
         forms[form] = dict(value=H * args.steps / d2, ms_per_step=1e3 * d2 / args.steps,
                            drop_ms=dms, drop_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
                            store_build_s=l2)

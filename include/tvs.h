@@ -62,8 +62,8 @@ typedef struct {
 /* How the rows of the system are formed during a sweep. */
 enum tvs_path_mode {
     TVS_PATH_ON_THE_FLY = 0, /* MLP walked for every history on every sweep */
-    TVS_PATH_STORE_F32 = 1,  /* rows formed once: int32 voxel index + float32 chord */
-    TVS_PATH_STORE_F16 = 2   /* rows formed once: int32 voxel index + float16 chord */
+    TVS_PATH_STORE_F32 = 1,  /* rows formed once: 32-bit entry tag + float32 chord */
+    TVS_PATH_STORE_F16 = 2   /* rows formed once: 32-bit entry tag + float16 chord */
 };
 
 typedef struct {
@@ -76,12 +76,13 @@ typedef struct {
     uint64_t hbm_budget_bytes; /* 0: 80 % of the device memory free at tvs_create */
     int32_t device;          /* HIP device ordinal */
     int32_t max_tries;       /* bound on the retries of one checked TV step; 0: 100000 */
-    int32_t sweep_kernel;    /* 0 or 1: one launch per block phase (path stores: voxel-major
-                                apply without atomics); 2: one persistent launch per sweep
-                                with device-wide barriers and atomic scatter */
-    int32_t wave_rows;       /* lanes per row in the DROP row kernels (16, 32, 64); 0: 64 */
-    int32_t time_sample;     /* k > 0: HIP events around both launches of every k-th DROP
-                                block (per-launch durations in tvs_stats); 0: off */
+    int32_t sweep_kernel;    /* 0 or 1: one launch per DROP block (finish the previous block
+                                and form this block's dot products, tile by tile);
+                                2: the same work in two launches per block */
+    int32_t tile_threads;    /* threads per image-tile workgroup of the DROP kernels
+                                (64, 128, 256); 0: 256 */
+    int32_t time_sample;     /* k > 0: kernel-stamped HIP events on the launches of every
+                                k-th DROP block (per-launch durations in tvs_stats); 0: off */
 } tvs_config;
 
 /* Fills *cfg with the defaults above (B = 3200, on-the-fly rows, log term on). */
@@ -141,9 +142,10 @@ typedef struct {
     double drop_ms_total;  /* all DROP launches of the call */
     int64_t cycles_timed;  /* cycles of the call */
     int64_t rows_launches; /* row-formation launches of the call */
-    int64_t drop_launches; /* DROP launches (persistent) or per-block launch pairs' spans */
-    double k1_ms_total;    /* sampled blocks: first launch (row residuals / row scatter) */
-    double k2_ms_total;    /* sampled blocks: second launch (voxel apply) */
+    int64_t drop_launches; /* DROP chains timed (one per sweep) */
+    double k1_ms_total;    /* sampled blocks: the block's launch (with sweep_kernel 2 its
+                              first launch, the finish of the previous block) */
+    double k2_ms_total;    /* sampled blocks, sweep_kernel 2 only: the second launch */
     int64_t k_samples;     /* sampled blocks of the last tvs_iterate call */
     double batch_ms_total; /* cycles of the last tvs_iterate_batch call */
     int64_t batch_cycles;  /* cycles of that call */
@@ -193,7 +195,11 @@ int tvs_set_image(tvs_ctx *ctx, const float *x0, int on_device, void *stream);
  * TVS_ESTATE before tvs_load_histories. */
 int tvs_iterate(tvs_ctx *ctx, const tvs_params *p, int32_t K, void *stream);
 
-/* Copies the current image (nx*ny*nz floats) to out (host or device). */
+/* Copies the current image (nx*ny*nz floats) to out (host or device).  The
+ * DROP sums are exact 64-bit integers in units of 2^-36 (row dot products)
+ * and 2^-40 (corrections); a product |a_ij x_j| beyond 2^26 / (longest row)
+ * cannot be summed so and is reported here, by tvs_get_stats and by
+ * tvs_get_batch_image as TVS_ERANGE (until the next tvs_set_image). */
 int tvs_get_image(tvs_ctx *ctx, float *out, int on_device, void *stream);
 
 /* Batched reconstructions: S settings of the loaded histories (a parameter
@@ -307,22 +313,22 @@ int tvs_server_get_counters(tvs_server *sv, tvs_server_counters *out);
 void tvs_server_destroy(tvs_server *sv);
 
 /* ------------------------------------------------------------------------
- * Autotuning of the launch shape.  Times every candidate shape (lanes per
- * row 16 / 32 / 64 of the row kernels; for on-the-fly rows also the
- * persistent sweep) on the first blocks of the loaded histories, from the
- * current image, which is restored afterwards, and keeps the fastest for
- * the context.  The block size B is a parameter of the method and is never
- * changed.  With cache_path (a text file, created if missing) a shape
- * measured before for the same device, grid, history count, B and path mode
- * is reused without timing, and new measurements are appended.
+ * Autotuning of the launch shape.  Times every candidate shape (threads per
+ * image-tile workgroup 64 / 128 / 256, one or two launches per DROP block)
+ * on the first blocks of the loaded histories, from the current image,
+ * which is restored afterwards, and keeps the fastest for the context.  The
+ * block size B is a parameter of the method and is never changed.  With
+ * cache_path (a text file, created if missing) a shape measured before for
+ * the same device, grid, history count, B and path mode is reused without
+ * timing, and new measurements are appended.
  * ------------------------------------------------------------------------ */
 typedef struct {
-    int32_t lanes_per_row;   /* chosen shape */
-    int32_t sweep_kernel;
+    int32_t tile_threads;    /* chosen shape */
+    int32_t sweep_kernel;    /* 1: one launch per block, 2: two */
     double ms_per_block;     /* its measured time per DROP block */
     int32_t from_cache;      /* 1: taken from the cache file */
     int32_t n_candidates;
-    int32_t cand_lanes[8];
+    int32_t cand_threads[8];
     int32_t cand_sweep[8];
     double cand_ms[8];       /* per block, per candidate */
 } tvs_tune_result;

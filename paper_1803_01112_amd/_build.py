@@ -1,9 +1,9 @@
 """Build of the gfx950 shared library libtvs.so (hipcc, in-tree).
 
 Every HIP source is compiled for gfx950 only, with packed-FP32 instructions
-disabled; the row-formation kernels are compiled without multiply-add
-contraction so their float64 voxel decisions follow the written order of
-operations.
+disabled; the kernels are compiled without multiply-add contraction so
+their float64 arithmetic (voxel decisions in particular) follows the written
+order of operations.
 """
 from __future__ import annotations
 
@@ -20,10 +20,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = {
     "rows.hip": ["-ffp-contract=off"],
-    "drop.hip": [],
+    "drop.hip": ["-ffp-contract=off"],
     "tv.hip": ["-ffp-contract=off"],
     "batch.hip": ["-ffp-contract=off"],
-    "csc.hip": [],
     "serve.cpp": ["-x", "hip"],
     "tvs_api.cpp": ["-x", "hip"],
 }

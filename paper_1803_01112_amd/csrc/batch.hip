@@ -2,15 +2,14 @@
 // (a parameter study over (lambda, N, alpha) as in arXiv 1803.01112,
 // Section III-E, run as one job instead of one reconstruction each).
 //
-// The S images are interleaved by voxel, x[p*S + s], so that the S values a
-// row entry gathers (or scatters) are contiguous.  One persistent sweep reads
-// each row once from HBM and applies it to all S images: per row, S float64
-// dot products (cross-lane sums), S residuals, S float64 atomic scatters per
-// entry; hit counts s_j and the touched list depend only on the rows and are
-// shared.  The TV steps of every setting run in one kernel per step index n,
-// with per-setting beta read from a device table indexed by a device cycle
-// counter, so the launches of one cycle can be captured once in a hipGraph
-// and replayed for every cycle.
+// The S images are interleaved by voxel, x[p*S + s], so that the S values an
+// entry reads are contiguous.  The DROP sweep is the tile-wise chain of
+// drop.hip with S images at once: every entry of a tile list is read once
+// and applied to all S settings (settings taken 8 at a time through LDS);
+// hit counts depend only on the rows and are shared.  The TV steps of every
+// setting run in one kernel per step index n, with per-setting beta read
+// from a device table indexed by a device cycle counter, so the launches of
+// one cycle can be captured once in a hipGraph and replayed for every cycle.
 #include "device_common.hpp"
 #include "tvs_internal.hpp"
 
@@ -18,10 +17,11 @@ namespace tvs {
 namespace {
 
 constexpr int kThreads = 256;
-using dev::append_touched;
 using dev::chord_at;
-using dev::grid_barrier;
-using dev::group_sum;
+using dev::kNoRow;
+
+constexpr double kDotUnit = 1.0 / kDotScale;
+constexpr double kCorrUnit = 1.0 / kCorrScale;
 
 // ------------------------------------------------------------- TV, S images
 // Thread t of a workgroup handles setting s = t % S of voxel w*V + t / S.
@@ -144,220 +144,139 @@ k_extract(GridDev G, const double *xb, int S, int s, float *out)
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_zero_d(double *p, int64_t n)
-{
-    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * kThreads)
-        p[q] = 0.0;
-}
-
-// ------------------------------------------------------------- DROP, S images
-template <int SMAX, typename CH>
-__device__ inline void drop_row_batch(const RowSet &rs, const CH *chord, const float *wepl,
-                                      int64_t row, int S, const double *x, double *c,
-                                      uint32_t *s, int32_t *touched, uint32_t *cnt)
-{
-    const int lane = threadIdx.x & 63;
-    const int64_t lr = row - rs.first;
-    const float n2 = rs.norm2[lr];
-    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
-    if (!(n2 > 0.0f)) return;   // uniform over the wavefront
-    double acc[SMAX];
-#pragma unroll
-    for (int k = 0; k < SMAX; k++) acc[k] = 0.0;
-    for (int64_t e = off + lane; e < end; e += 64) {
-        const double ch = (double)chord_at(chord, e);
-        const double *xp = x + (int64_t)rs.idx[e] * S;
-#pragma unroll
-        for (int k = 0; k < SMAX; k++)
-            if (k < S) acc[k] += ch * xp[k];
-    }
-    const double b = (double)wepl[row];
-#pragma unroll
-    for (int k = 0; k < SMAX; k++) {
-        if (k < S) acc[k] = (b - group_sum<64>(acc[k])) / (double)n2;   // residual r_k
-        else acc[k] = 0.0;
-    }
-    const int64_t trips = (end - off + 63) / 64;
-    for (int64_t q = 0; q < trips; q++) {
-        const int64_t e = off + q * 64 + lane;
-        bool first = false;
-        int32_t j = 0;
-        if (e < end) {
-            j = rs.idx[e];
-            const double ch = (double)chord_at(chord, e);
-            double *cp = c + (int64_t)j * S;
-#pragma unroll
-            for (int k = 0; k < SMAX; k++)
-                if (k < S) unsafeAtomicAdd(cp + k, acc[k] * ch);
-            first = (atomicAdd(s + j, 1u) == 0u);
-        }
-        append_touched(first, j, touched, cnt);
-    }
-}
-
-template <int SMAX, typename CH>
-__global__ void __launch_bounds__(kThreads)
-k_drop_batch(RowSet rs, const CH *chord, const float *wepl, int64_t block_size, int S,
-             const double *lambda, double *x, double *c, uint32_t *s, int32_t *touched,
-             uint32_t *cnt, uint32_t *bar)
-{
-    const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
-    const int64_t wid = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 64;
-    const int64_t gthreads = (int64_t)gridDim.x * kThreads;
-    const int64_t gtid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int64_t nblocks = (rs.n + block_size - 1) / block_size;
-    for (int64_t t = 0; t < nblocks; t++) {
-        const int64_t r0 = rs.first + t * block_size;
-        const int64_t r1 = (r0 + block_size < rs.first + rs.n) ? r0 + block_size : rs.first + rs.n;
-        uint32_t *cur = cnt + (t & 1);
-        for (int64_t row = r0 + wid; row < r1; row += waves)
-            drop_row_batch<SMAX, CH>(rs, chord, wepl, row, S, x, c, s, touched, cur);
-        if (!grid_barrier(bar)) return;
-        const uint32_t n = *cur;
-        for (int64_t i = gtid; i < (int64_t)n; i += gthreads) {
-            const int64_t j = touched[i];
-            const double inv = 1.0 / (double)s[j];
-            double *xp = x + j * S;
-            double *cp = c + j * S;
-            for (int k = 0; k < S; k++) {
-                xp[k] += lambda[k] * cp[k] * inv;
-                cp[k] = 0.0;
-            }
-            s[j] = 0u;
-        }
-        if (gtid == 0) cnt[(t + 1) & 1] = 0u;
-        if (!grid_barrier(bar)) return;
-    }
-    if (gtid == 0) {
-        cnt[0] = 0u;
-        cnt[1] = 0u;
-    }
-}
-
-// ------------------------------------------------------------- voxel-major form
-// Residuals r[q*S + s] of the rows [r0, r1) for every setting: one wavefront
-// per row, S float64 dot products over the row's entries.
-template <int SMAX, typename CH>
-__global__ void __launch_bounds__(kThreads)
-k_batch_resid(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1, int S,
-              const double *x, double *rbuf)
-{
-    const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 64;
-    if (row >= r1) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t lr = row - rs.first;
-    const float n2 = rs.norm2[lr];
-    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
-    double acc[SMAX];
-#pragma unroll
-    for (int k = 0; k < SMAX; k++) acc[k] = 0.0;
-    for (int64_t e = off + lane; e < end; e += 64) {
-        const double ch = (double)chord_at(chord, e);
-        const double *xp = x + (int64_t)rs.idx[e] * S;
-#pragma unroll
-        for (int k = 0; k < SMAX; k++)
-            if (k < S) acc[k] += ch * xp[k];
-    }
-    const double b = (double)wepl[row];
-    double *rp = rbuf + (row - r0) * S;
-#pragma unroll
-    for (int k = 0; k < SMAX; k++) {
-        if (k < S) {
-            const double d = group_sum<64>(acc[k]);
-            if (lane == k) rp[k] = (n2 > 0.0f) ? (b - d) / (double)n2 : 0.0;
-        }
-    }
-}
-
-// One thread per (distinct voxel, setting): the column sum in row order.
-template <typename CH>
-__global__ void __launch_bounds__(kThreads)
-k_batch_apply_csc(const int32_t *uvox, const uint32_t *ucol, int64_t U, int64_t ne,
-                  const uint16_t *cq, const CH *cch, const double *rbuf, int S,
-                  const double *lambda, double *x)
-{
-    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < U * S;
-         t += (int64_t)gridDim.x * kThreads) {
-        const int64_t u = t / S;
-        const int k = (int)(t - u * S);
-        const int64_t s0 = ucol[u];
-        const int64_t e0 = (u + 1 < U) ? (int64_t)ucol[u + 1] : ne;
-        double c = 0.0;
-        for (int64_t q = s0; q < e0; q++) c += rbuf[(int64_t)cq[q] * S + k] * (double)chord_at(cch, q);
-        x[(int64_t)uvox[u] * S + k] += lambda[k] * c / (double)(e0 - s0);
-    }
-}
-
 unsigned elem_grid(int64_t n)
 {
     int64_t wgs = (n + kThreads - 1) / kThreads;
-    if (wgs > 8192) wgs = 8192;
+    if (wgs > 4096) wgs = 4096;
     if (wgs < 1) wgs = 1;
     return (unsigned)wgs;
 }
 
-template <int SMAX>
-hipError_t drop_batch_launch(const RowSet &rs, const float *wepl, int64_t block_size,
-                             const BatchBuffers &b, int grid_wgs, hipStream_t stream)
-{
-    if (rs.chord16)
-        hipLaunchKernelGGL((k_drop_batch<SMAX, __half>), dim3(grid_wgs), dim3(kThreads), 0, stream,
-                           rs, rs.chord16, wepl, block_size, b.S, b.lambda, b.x, b.c, b.s,
-                           b.touched, b.ntouched, b.barrier);
-    else
-        hipLaunchKernelGGL((k_drop_batch<SMAX, float>), dim3(grid_wgs), dim3(kThreads), 0, stream,
-                           rs, rs.chord32, wepl, block_size, b.S, b.lambda, b.x, b.c, b.s,
-                           b.touched, b.ntouched, b.barrier);
-    return hipGetLastError();
-}
+// ------------------------------------------------------------- DROP, S images
+constexpr int kGroup = 8;   // settings per pass through LDS
 
-template <int SMAX>
-int occupancy_of()
-{
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(k_drop_batch<SMAX, float>), kThreads, 0) !=
-        hipSuccess)
-        return 0;
-    return per_cu;
-}
+struct BatchLds {
+    double x[kTileWords * kGroup];
+    long long cf[kTileWords * kGroup];
+    double cb[kTileWords * kGroup];
+    uint32_t hits[kTileWords];
+};
 
-template <int SMAX>
-hipError_t batch_csc_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
-                            const CscBlock &cb, const BatchBuffers &b, double *rbuf,
-                            hipStream_t stream)
+// One step of the tile-wise chain for S settings: finish block P and form
+// the dot products of block C (dot arrays row-major: dot[q * S + s]).
+template <typename CH>
+__global__ void __launch_bounds__(kThreads)
+k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
 {
-    const int64_t rows = r1 - r0;
-    if (rows <= 0) return hipSuccess;
-    dim3 grid((unsigned)((rows * 64 + kThreads - 1) / kThreads));
-    if (rs.chord16)
-        hipLaunchKernelGGL((k_batch_resid<SMAX, __half>), grid, dim3(kThreads), 0, stream, rs,
-                           rs.chord16, wepl, r0, r1, b.S, b.x, rbuf);
-    else
-        hipLaunchKernelGGL((k_batch_resid<SMAX, float>), grid, dim3(kThreads), 0, stream, rs,
-                           rs.chord32, wepl, r0, r1, b.S, b.x, rbuf);
-    if (cb.U <= 0) return hipGetLastError();
-    const unsigned wgs = elem_grid(cb.U * b.S);
-    if (cb.cch16)
-        hipLaunchKernelGGL((k_batch_apply_csc<__half>), dim3(wgs), dim3(kThreads), 0, stream,
-                           cb.uvox, cb.ucol, cb.U, cb.ne, cb.cq, cb.cch16, rbuf, b.S, b.lambda, b.x);
-    else
-        hipLaunchKernelGGL((k_batch_apply_csc<float>), dim3(wgs), dim3(kThreads), 0, stream,
-                           cb.uvox, cb.ucol, cb.U, cb.ne, cb.cq, cb.cch32, rbuf, b.S, b.lambda, b.x);
-    return hipGetLastError();
+    __shared__ BatchLds L;
+    const int t = threadIdx.x;
+    if (A.zero)
+        for (int64_t q = (int64_t)blockIdx.x * kThreads + t; q < A.B * S;
+             q += (int64_t)gridDim.x * kThreads)
+            A.zero[q] = 0;
+    const int64_t T = blockIdx.x;
+    int64_t p0 = 0, p1 = 0, c0 = 0, c1 = 0;
+    if (A.P.valid) {
+        p0 = A.P.toff[T];
+        p1 = A.P.toff[T + 1];
+    }
+    if (A.C.valid) {
+        c0 = A.C.toff[T];
+        c1 = A.C.toff[T + 1];
+    }
+    if (p0 == p1 && c0 == c1) return;
+    const CH *chp = nullptr, *chc = nullptr;
+    if constexpr (sizeof(CH) == 4) {
+        chp = A.P.ch32;
+        chc = A.C.ch32;
+    } else {
+        chp = A.P.ch16;
+        chc = A.C.ch16;
+    }
+    double *xt = A.x + (T << kTileShift) * S;
+    for (int g0 = 0; g0 < S; g0 += kGroup) {
+        const int G = (S - g0 < kGroup) ? S - g0 : kGroup;
+        for (int i = t; i < kTileWords * G; i += kThreads) {
+            const int w = i / G, s = i - w * G;
+            L.x[w * kGroup + s] = xt[(int64_t)w * S + g0 + s];
+        }
+        if (p1 > p0) {
+            for (int i = t; i < kTileWords * kGroup; i += kThreads) {
+                L.cf[i] = 0;
+                L.cb[i] = 0.0;
+            }
+            for (int w = t; w < kTileWords; w += kThreads) L.hits[w] = 0u;
+            __syncthreads();
+            for (int64_t e = p0 + t; e < p1; e += kThreads) {
+                const uint32_t m = A.P.meta[e - A.P.base];
+                const int w = (int)(m & (kTileWords - 1));
+                const uint32_t q = m >> kTileShift;
+                if (q >= A.P.rows) {
+                    atomicOr(A.err, 2u);
+                    continue;
+                }
+                const double a = (double)chord_at(chp, e - A.P.base);
+                const double wp = (double)A.P.wepl[q], n2 = (double)A.P.n2[q];
+                atomicAdd(&L.hits[w], 1u);
+                for (int s = 0; s < G; s++) {
+                    const double r = (wp - (double)A.P.dot[(int64_t)q * S + g0 + s] * kDotUnit) / n2;
+                    const double v = r * a;
+                    if (fabs(v) <= A.big)
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&L.cf[w * kGroup + s]),
+                                  (unsigned long long)__double2ll_rn(v * kCorrScale));
+                    else
+                        atomicAdd(&L.cb[w * kGroup + s], v);
+                }
+            }
+            __syncthreads();
+            for (int i = t; i < kTileWords * G; i += kThreads) {
+                const int w = i / G, s = i - w * G;
+                const uint32_t h = L.hits[w];
+                if (h) {
+                    const int k = w * kGroup + s;
+                    const double c = (double)L.cf[k] * kCorrUnit + L.cb[k];
+                    const double nx = L.x[k] + lambda[g0 + s] * c / (double)h;
+                    L.x[k] = nx;
+                    xt[(int64_t)w * S + g0 + s] = nx;
+                }
+            }
+        }
+        __syncthreads();
+        // every thread runs the same rounds and settings (the shuffles are uniform)
+        for (int64_t r0 = c0; r0 < c1; r0 += kThreads) {
+            const int64_t e = r0 + t;
+            uint32_t q = kNoRow;
+            int w = 0;
+            double a = 0.0;
+            if (e < c1) {
+                const uint32_t m = A.C.meta[e - A.C.base];
+                q = m >> kTileShift;
+                w = (int)(m & (kTileWords - 1));
+                a = (double)chord_at(chc, e - A.C.base);
+                if (q >= A.C.rows) {
+                    atomicOr(A.err, 2u);
+                    q = kNoRow;
+                }
+            }
+            const dev::Runs runs = dev::wave_runs(q);
+            for (int s = 0; s < G; s++) {
+                long long f = 0;
+                if (q != kNoRow) {
+                    const double p = a * L.x[w * kGroup + s];
+                    if (fabs(p) <= A.dot_max) f = __double2ll_rn(p * kDotScale);
+                    else atomicOr(A.err, 1u);
+                }
+                f = dev::run_sum(f, runs);
+                if (runs.tail && q != kNoRow)
+                    atomicAdd(reinterpret_cast<unsigned long long *>(A.C.dot + (int64_t)q * S + g0 + s),
+                              (unsigned long long)f);
+            }
+        }
+        __syncthreads();   // LDS is reused by the next group
+    }
 }
 
 }  // namespace
-
-hipError_t launch_batch_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
-                                  const CscBlock &cb, const BatchBuffers &b, double *rbuf,
-                                  hipStream_t stream)
-{
-    if (b.S <= 8) return batch_csc_launch<8>(rs, wepl, r0, r1, cb, b, rbuf, stream);
-    if (b.S <= 16) return batch_csc_launch<16>(rs, wepl, r0, r1, cb, b, rbuf, stream);
-    return batch_csc_launch<32>(rs, wepl, r0, r1, cb, b, rbuf, stream);
-}
 
 int batch_vox_per_wg(int S) { return kThreads / S; }
 
@@ -402,9 +321,6 @@ hipError_t launch_replicate(const double *x0, const BatchBuffers &b, hipStream_t
 {
     hipLaunchKernelGGL(k_replicate, dim3(elem_grid(b.nvox * b.S)), dim3(kThreads), 0, stream, x0,
                        b.x, b.S, b.nvox);
-    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-    hipLaunchKernelGGL(k_zero_d, dim3(elem_grid(b.nvox * b.S)), dim3(kThreads), 0, stream, b.c,
-                       b.nvox * b.S);
     return hipGetLastError();
 }
 
@@ -417,24 +333,18 @@ hipError_t launch_extract(const GridDev &g, const BatchBuffers &b, int s, float 
     return hipGetLastError();
 }
 
-hipError_t launch_drop_batch(const RowSet &rs, const float *wepl, int64_t block_size,
-                             const BatchBuffers &b, int grid_wgs, hipStream_t stream)
+hipError_t launch_drop_tiles_batch(const DropTileArgs &a, const BatchBuffers &b, int64_t ntiles,
+                                   hipStream_t stream)
 {
-    if (rs.n <= 0) return hipSuccess;
-    if (b.S <= 8) return drop_batch_launch<8>(rs, wepl, block_size, b, grid_wgs, stream);
-    if (b.S <= 16) return drop_batch_launch<16>(rs, wepl, block_size, b, grid_wgs, stream);
-    return drop_batch_launch<32>(rs, wepl, block_size, b, grid_wgs, stream);
-}
-
-int batch_grid_size(int device, int S)
-{
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
-        return 0;
-    int per_cu = (S <= 8) ? occupancy_of<8>() : (S <= 16) ? occupancy_of<16>() : occupancy_of<32>();
-    if (per_cu <= 0) return 0;
-    if (per_cu > 2) per_cu = 2;
-    return cus * per_cu;
+    if (ntiles <= 0 || (!a.P.valid && !a.C.valid)) return hipSuccess;
+    const bool half = a.P.valid ? (a.P.ch16 != nullptr) : (a.C.ch16 != nullptr);
+    if (half)
+        hipLaunchKernelGGL(k_drop_tile_batch<__half>, dim3((unsigned)ntiles), dim3(kThreads), 0,
+                           stream, a, b.S, (const double *)b.lambda);
+    else
+        hipLaunchKernelGGL(k_drop_tile_batch<float>, dim3((unsigned)ntiles), dim3(kThreads), 0,
+                           stream, a, b.S, (const double *)b.lambda);
+    return hipGetLastError();
 }
 
 }  // namespace tvs

@@ -2,24 +2,32 @@
 // DROP (diagonally relaxed orthogonal projections) over blocks of B
 // consecutive histories (arXiv 1803.01112, Section III-D; P_T in Appendix A).
 //
-// For block t, from one image x:
+// For block b, from one image x:
 //   r_i = (b_i - a_i . x) / ||a_i||^2          every row i of the block
-//   c_j = sum_i r_i a_ij,  s_j = #entries at j  (scatter)
-//   x_j += lambda c_j / s_j                     where s_j > 0 (apply)
+//   c_j = sum_i r_i a_ij,  s_j = #entries at j
+//   x_j += lambda c_j / s_j                     where s_j > 0
 // Blocks are applied one after another.
 //
-// Rows are read from a CSR row set (int32 voxel index + float32 or float16
-// chord).  A group of LPR lanes (a wavefront for LPR = 64) reads one row
-// coalesced, gathers x (float64), reduces the dot product in float64 with
-// cross-lane shuffles,
-// and scatters r a_ij / 1 with hardware float64 / integer atomics.  The first
-// hit of a voxel in a block appends it to a touched list (one atomic per
-// wavefront), so the apply phase visits only touched voxels and clears them.
-//
-// Two forms: one launch per phase (rows, apply), or one persistent launch
-// per sweep with a device-wide barrier between phases.  The barrier spins a
-// bounded number of times; on timeout it raises an error flag that makes
-// every workgroup leave, and the host reports a device error.
+// Tile-wise form.  The entries of a block are grouped by 16 x 16-voxel image
+// tile (tile lists, rows.hip).  One workgroup owns one tile:
+//   finish (block b - 1): every entry of the tile's list takes r_i from its
+//     row's dot product (complete after the previous launch), and the
+//     tile's c_j and s_j are summed in LDS; the tile's voxels are updated
+//     in LDS and written back once;
+//   dots (block b): every entry multiplies its chord by the updated voxel
+//     value in LDS; within a wavefront the products of one row (consecutive
+//     in the list) are summed over their run with shuffles, and one atomic
+//     per run adds the run's sum to the row's dot product.
+// Both halves of one step touch only the workgroup's own tile of x, so one
+// launch per block does both (the launch boundary is the only device-wide
+// synchronisation, and finishes every row's dot product before it is
+// used).  Row dot products are summed as 64-bit integers in units of
+// 2^-36, corrections in units of 2^-40: integer sums are exact, so the
+// results do not depend on the order in which workgroups or lanes add.  A
+// correction larger than `big` (outside the guaranteed integer range) is
+// summed in float64 instead; a product |a_ij x_j| above `dot_max` raises
+// an error flag (bit 0) that the host reports as a range error, and an
+// entry naming a row outside its block is skipped and raises bit 1.
 #include <hip/hip_ext.h>
 
 #include "device_common.hpp"
@@ -28,435 +36,226 @@
 namespace tvs {
 namespace {
 
-constexpr int kThreads = 256;
-using dev::append_touched;
 using dev::chord_at;
-using dev::grid_barrier;
-using dev::group_sum;
+using dev::kNoRow;
 
-// One row: dot, residual, scatter.  All LPR lanes of the group call it.
-template <int LPR, typename CH>
-__device__ inline void drop_row(const RowSet &rs, const CH *chord, const float *wepl, int64_t row,
-                                const double *x, double *c, uint32_t *s, int32_t *touched,
-                                uint32_t *cnt)
-{
-    const int lane = threadIdx.x & (LPR - 1);
-    const int64_t lr = row - rs.first;
-    const float n2 = rs.norm2[lr];
-    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
-    double acc = 0.0;
-    if (n2 > 0.0f)
-        for (int64_t e = off + lane; e < end; e += LPR)
-            acc += (double)chord_at(chord, e) * x[rs.idx[e]];
-    acc = group_sum<LPR>(acc);
-    const double r = (n2 > 0.0f) ? ((double)wepl[row] - acc) / (double)n2 : 0.0;
-    const int64_t trips = (n2 > 0.0f) ? (end - off + LPR - 1) / LPR : 0;
-    // Uniform trip count inside the group so the wavefront-wide ballot sees
-    // every lane of the group.
-    for (int64_t q = 0; q < trips; q++) {
-        int64_t e = off + q * LPR + lane;
-        bool first = false;
-        int32_t j = 0;
-        if (e < end) {
-            j = rs.idx[e];
-            unsafeAtomicAdd(c + j, r * (double)chord_at(chord, e));
-            first = (atomicAdd(s + j, 1u) == 0u);
-        }
-        append_touched(first, j, touched, cnt);
-    }
-}
+constexpr double kDotUnit = 1.0 / kDotScale;
+constexpr double kCorrUnit = 1.0 / kCorrScale;
 
-__device__ inline void apply_voxel(int32_t j, double lambda, double *x, double *c, uint32_t *s)
-{
-    double cj = c[j];
-    uint32_t sj = s[j];
-    x[j] += lambda * cj / (double)sj;
-    c[j] = 0.0;
-    s[j] = 0u;
-}
-
-__global__ void k_zero_counters(uint32_t *cnt)
-{
-    if (threadIdx.x < 2) cnt[threadIdx.x] = 0u;
-}
-
-template <int LPR, typename CH>
-__global__ void __launch_bounds__(kThreads)
-k_drop_persistent(RowSet rs, const CH *chord, const float *wepl, int64_t block_size, double lambda,
-                  double *x, double *c, uint32_t *s, int32_t *touched, uint32_t *cnt, uint32_t *bar)
-{
-    const int64_t groups = (int64_t)gridDim.x * (kThreads / LPR);
-    const int64_t gid = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
-    const int64_t gthreads = (int64_t)gridDim.x * kThreads;
-    const int64_t gtid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int64_t nblocks = (rs.n + block_size - 1) / block_size;
-    for (int64_t t = 0; t < nblocks; t++) {
-        const int64_t r0 = rs.first + t * block_size;
-        const int64_t r1 = (r0 + block_size < rs.first + rs.n) ? r0 + block_size : rs.first + rs.n;
-        uint32_t *cur = cnt + (t & 1);
-        for (int64_t row = r0 + gid; row < r1; row += groups)
-            drop_row<LPR, CH>(rs, chord, wepl, row, x, c, s, touched, cur);
-        if (!grid_barrier(bar)) return;
-        const uint32_t n = *cur;
-        for (int64_t i = gtid; i < (int64_t)n; i += gthreads) apply_voxel(touched[i], lambda, x, c, s);
-        if (gtid == 0) cnt[(t + 1) & 1] = 0u;
-        if (!grid_barrier(bar)) return;
-    }
-    if (gtid == 0) {
-        cnt[0] = 0u;
-        cnt[1] = 0u;
-    }
-}
-
-template <int LPR>
-hipError_t persistent_launch(const RowSet &rs, const float *wepl, int64_t block_size,
-                             double lambda, const DropBuffers &b, int grid_wgs, hipStream_t stream)
-{
-    if (rs.n <= 0) return hipSuccess;
-    if (rs.chord16)
-        hipLaunchKernelGGL((k_drop_persistent<LPR, __half>), dim3(grid_wgs), dim3(kThreads), 0,
-                           stream, rs, rs.chord16, wepl, block_size, lambda, b.x, b.c, b.s,
-                           b.touched, b.ntouched, b.barrier);
-    else
-        hipLaunchKernelGGL((k_drop_persistent<LPR, float>), dim3(grid_wgs), dim3(kThreads), 0,
-                           stream, rs, rs.chord32, wepl, block_size, lambda, b.x, b.c, b.s,
-                           b.touched, b.ntouched, b.barrier);
-    return hipGetLastError();
-}
-
-// Scatter-only row kernel of the per-block form: dot, residual, then
-// fire-and-forget float64 / uint32 atomics (no touched list: the apply
-// pass scans the hit counts densely).
-template <int LPR, typename CH>
-__global__ void __launch_bounds__(kThreads)
-k_drop_rows_dense(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1,
-                  const double *x, double *c, uint32_t *s)
-{
-    const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
-    if (row >= r1) return;
-    const int lane = threadIdx.x & (LPR - 1);
-    const int64_t lr = row - rs.first;
-    const float n2 = rs.norm2[lr];
-    if (!(n2 > 0.0f)) return;   // uniform over the group
-    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
-    double acc = 0.0;
-    for (int64_t e = off + lane; e < end; e += LPR)
-        acc += (double)chord_at(chord, e) * x[rs.idx[e]];
-    acc = group_sum<LPR>(acc);
-    const double r = ((double)wepl[row] - acc) / (double)n2;
-    for (int64_t e = off + lane; e < end; e += LPR) {
-        const int32_t j = rs.idx[e];
-        unsafeAtomicAdd(c + j, r * (double)chord_at(chord, e));
-        __hip_atomic_fetch_add(s + j, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Packed scatter: correction and hit count of an entry in one 64-bit integer
-// atomic.  Bits 48..63 count hits; bits 0..47 hold the correction in two's-
-// complement fixed point with kFrac fraction bits (exact, order-independent
-// integer sums).  A contribution larger than `big` (chosen by the host so
-// that no voxel's sum can leave the 48-bit field) goes to a float64 atomic
-// instead, with a count-only packed increment, and sets the voxel's bit in
-// the outlier mask so that the apply reads the float64 part only there.
-constexpr int kFrac = 30;
-constexpr double kScale = (double)(1ull << kFrac);
-constexpr uint64_t kHit = 1ull << 48;
-
-// The first kHeld chunks of LPR entries of a row are loaded once, all at
-// once (their gathers then overlap instead of forming a chain), and kept in
-// registers for the scatter; entries past them are streamed twice.  Every
-// lane sums its entries in ascending order either way.
-constexpr int kHeld = 4;
-
-template <int LPR, typename CH>
-__global__ void __launch_bounds__(kThreads)
-k_drop_rows_packed(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1,
-                   const double *x, unsigned long long *P, double *c64, uint32_t *omask,
-                   double big)
-{
-    const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
-    if (row >= r1) return;
-    const int lane = threadIdx.x & (LPR - 1);
-    const int64_t lr = row - rs.first;
-    const float n2 = rs.norm2[lr];
-    if (!(n2 > 0.0f)) return;
-    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
-    int32_t jh[kHeld];
-    float ch[kHeld];
-#pragma unroll
-    for (int u = 0; u < kHeld; u++) {
-        const int64_t e = off + lane + (int64_t)u * LPR;
-        jh[u] = (e < end) ? rs.idx[e] : -1;
-        ch[u] = (e < end) ? chord_at(chord, e) : 0.0f;
-    }
-    double xh[kHeld];
-#pragma unroll
-    for (int u = 0; u < kHeld; u++) xh[u] = (jh[u] >= 0) ? x[jh[u]] : 0.0;
-    double acc = 0.0;
-#pragma unroll
-    for (int u = 0; u < kHeld; u++)
-        if (jh[u] >= 0) acc += (double)ch[u] * xh[u];
-    for (int64_t e = off + lane + (int64_t)kHeld * LPR; e < end; e += LPR)
-        acc += (double)chord_at(chord, e) * x[rs.idx[e]];
-    acc = group_sum<LPR>(acc);
-    const double r = ((double)wepl[row] - acc) / (double)n2;
-    auto scatter = [&](int32_t j, float a) {
-        const double v = r * (double)a;
-        if (fabs(v) <= big) {
-            const long long f = __double2ll_rn(v * kScale);
-            atomicAdd(P + j, (unsigned long long)kHit + (unsigned long long)f);
-        } else {
-            unsafeAtomicAdd(c64 + j, v);
-            atomicAdd(P + j, (unsigned long long)kHit);
-            atomicOr(omask + (j >> 5), 1u << (j & 31));
-        }
-    };
-#pragma unroll
-    for (int u = 0; u < kHeld; u++)
-        if (jh[u] >= 0) scatter(jh[u], ch[u]);
-    for (int64_t e = off + lane + (int64_t)kHeld * LPR; e < end; e += LPR)
-        scatter(rs.idx[e], chord_at(chord, e));
-}
-
-// Voxel j is handled by a lane of the same wavefront instruction as the 31
-// other voxels of its mask word (the stride is a multiple of 32), so the
-// word's first lane may clear it right after the wavefront has read it.
-__global__ void __launch_bounds__(kThreads)
-k_drop_apply_packed(double lambda, double *x, unsigned long long *P, double *c64,
-                    uint32_t *omask, int64_t nvox)
-{
-    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < nvox;
-         j += (int64_t)gridDim.x * kThreads) {
-        // x is read with P (not after testing P) so the two loads overlap
-        const unsigned long long p = P[j];
-        const uint32_t m = omask[j >> 5];
-        const double xj = x[j];
-        if (m != 0u && (j & 31) == 0) omask[j >> 5] = 0u;
-        if (p == 0ull) continue;
-        const unsigned long long hits = (p + (1ull << 47)) >> 48;
-        const long long fixed = (long long)(p - (hits << 48));
-        double c = (double)fixed * (1.0 / kScale);
-        if ((m >> (j & 31)) & 1u) {
-            c += c64[j];
-            c64[j] = 0.0;
-        }
-        x[j] = xj + lambda * c / (double)hits;
-        P[j] = 0ull;
-    }
-}
-
-// Dense apply: every voxel with hits in the block takes its correction and
-// clears its accumulators (a coalesced pass over the hit counts).
-__global__ void __launch_bounds__(kThreads)
-k_drop_apply_dense(double lambda, double *x, double *c, uint32_t *s, int64_t nvox)
-{
-    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < nvox;
-         j += (int64_t)gridDim.x * kThreads) {
-        const uint32_t sj = s[j];
-        if (sj == 0u) continue;
-        x[j] += lambda * c[j] / (double)sj;
-        c[j] = 0.0;
-        s[j] = 0u;
-    }
-}
-
-// Residuals of the rows [r0, r1) into rbuf[row - r0] (voxel-major apply).
-template <int LPR, typename CH>
-__global__ void __launch_bounds__(kThreads)
-k_drop_resid(RowSet rs, const CH *chord, const float *wepl, int64_t r0, int64_t r1,
-             const double *x, double *rbuf)
-{
-    const int64_t row = r0 + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LPR;
-    if (row >= r1) return;
-    const int lane = threadIdx.x & (LPR - 1);
-    const int64_t lr = row - rs.first;
-    const float n2 = rs.norm2[lr];
-    const int64_t off = rs.row_off[lr] - rs.base, end = rs.row_off[lr + 1] - rs.base;
-    int32_t jh[kHeld];
-    float ch[kHeld];
-#pragma unroll
-    for (int u = 0; u < kHeld; u++) {
-        const int64_t e = off + lane + (int64_t)u * LPR;
-        jh[u] = (e < end) ? rs.idx[e] : -1;
-        ch[u] = (e < end) ? chord_at(chord, e) : 0.0f;
-    }
-    double xh[kHeld];
-#pragma unroll
-    for (int u = 0; u < kHeld; u++) xh[u] = (jh[u] >= 0) ? x[jh[u]] : 0.0;
-    double acc = 0.0;
-#pragma unroll
-    for (int u = 0; u < kHeld; u++)
-        if (jh[u] >= 0) acc += (double)ch[u] * xh[u];
-    for (int64_t e = off + lane + (int64_t)kHeld * LPR; e < end; e += LPR)
-        acc += (double)chord_at(chord, e) * x[rs.idx[e]];
-    acc = group_sum<LPR>(acc);
-    if (lane == 0) rbuf[row - r0] = (n2 > 0.0f) ? ((double)wepl[row] - acc) / (double)n2 : 0.0;
-}
-
-// x_j += lambda * (sum over column j of r_q a_qj) / (column length), one
-// thread per distinct voxel of the block; columns are summed in row order.
 template <typename CH>
-__global__ void __launch_bounds__(kThreads)
-k_drop_apply_csc(const int32_t *uvox, const uint32_t *ucol, int64_t U, int64_t ne,
-                 const uint16_t *cq, const CH *cch, const double *rbuf, double lambda, double *x)
+__device__ inline const CH *chords(const TileBlock &t);
+template <>
+__device__ inline const float *chords<float>(const TileBlock &t) { return t.ch32; }
+template <>
+__device__ inline const __half *chords<__half>(const TileBlock &t) { return t.ch16; }
+
+// LDS of one tile workgroup.
+struct TileLds {
+    double x[kTileWords];
+    long long cf[kTileWords];    // fixed-point correction sums
+    double cb[kTileWords];       // float64 part (large contributions)
+    uint32_t hits[kTileWords];
+};
+
+// Finishes block P on this tile: x (LDS and global) updated in place.
+template <int NT, typename CH>
+__device__ void tile_finish(const TileBlock &P, int64_t p0, int64_t p1, TileLds &L, double *xt,
+                            double lambda, double big, uint32_t *err)
 {
-    for (int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x; u < U;
-         u += (int64_t)gridDim.x * kThreads) {
-        const int64_t s = ucol[u];
-        const int64_t e = (u + 1 < U) ? (int64_t)ucol[u + 1] : ne;
-        const int32_t vj = uvox[u];
-        const double xj = x[vj];          // issued before the column's loads
-        double c = 0.0;
-        int64_t k = s;
-        for (; k + 2 <= e; k += 2) {      // two entries' loads in flight at once
-            const uint16_t q0 = cq[k], q1 = cq[k + 1];
-            const float a0 = chord_at(cch, k), a1 = chord_at(cch, k + 1);
-            const double b0 = rbuf[q0], b1 = rbuf[q1];
-            c += b0 * (double)a0;
-            c += b1 * (double)a1;
-        }
-        if (k < e) c += rbuf[cq[k]] * (double)chord_at(cch, k);
-        x[vj] = xj + lambda * c / (double)(e - s);
+    const CH *ch = chords<CH>(P);
+    for (int w = threadIdx.x; w < kTileWords; w += NT) {
+        L.hits[w] = 0u;
+        L.cf[w] = 0;
+        L.cb[w] = 0.0;
     }
+    __syncthreads();
+    for (int64_t e = p0 + threadIdx.x; e < p1; e += NT) {
+        const uint32_t m = P.meta[e - P.base];
+        const int w = (int)(m & (kTileWords - 1));
+        const uint32_t q = m >> kTileShift;
+        if (q >= P.rows) {
+            atomicOr(err, 2u);
+            continue;
+        }
+        const double r = ((double)P.wepl[q] - (double)P.dot[q] * kDotUnit) / (double)P.n2[q];
+        const double v = r * (double)chord_at(ch, e - P.base);
+        atomicAdd(&L.hits[w], 1u);
+        if (fabs(v) <= big)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&L.cf[w]),
+                      (unsigned long long)__double2ll_rn(v * kCorrScale));
+        else
+            atomicAdd(&L.cb[w], v);
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < kTileWords; w += NT) {
+        const uint32_t h = L.hits[w];
+        if (h) {
+            const double c = (double)L.cf[w] * kCorrUnit + L.cb[w];
+            const double nx = L.x[w] + lambda * c / (double)h;
+            L.x[w] = nx;
+            xt[w] = nx;
+        }
+    }
+    __syncthreads();
+}
+
+// Partial dot products of block C's rows on this tile, from x in LDS.
+template <int NT, typename CH>
+__device__ void tile_dots(const TileBlock &C, int64_t c0, int64_t c1, const TileLds &L,
+                          double dot_max, uint32_t *err)
+{
+    const CH *ch = chords<CH>(C);
+    // every thread runs the same number of rounds (the shuffles are uniform)
+    for (int64_t r0 = c0; r0 < c1; r0 += NT) {
+        const int64_t e = r0 + threadIdx.x;
+        uint32_t q = kNoRow;
+        long long f = 0;
+        if (e < c1) {
+            const uint32_t m = C.meta[e - C.base];
+            q = m >> kTileShift;
+            const double p = (double)chord_at(ch, e - C.base) * L.x[m & (kTileWords - 1)];
+            if (q >= C.rows) {
+                atomicOr(err, 2u);
+                q = kNoRow;
+            } else if (fabs(p) <= dot_max) {
+                f = __double2ll_rn(p * kDotScale);
+            } else {
+                atomicOr(err, 1u);
+            }
+        }
+        const dev::Runs runs = dev::wave_runs(q);
+        f = dev::run_sum(f, runs);
+        if (runs.tail && q != kNoRow)
+            atomicAdd(reinterpret_cast<unsigned long long *>(C.dot + q), (unsigned long long)f);
+    }
+}
+
+__device__ inline void clear_next(const DropTileArgs &A, int nt)
+{
+    if (!A.zero) return;
+    for (int64_t q = (int64_t)blockIdx.x * nt + threadIdx.x; q < A.B; q += (int64_t)gridDim.x * nt)
+        A.zero[q] = 0;
+}
+
+__device__ inline void list_range(const TileBlock &t, int64_t T, int64_t &a, int64_t &b)
+{
+    a = b = 0;
+    if (t.valid) {
+        a = t.toff[T];
+        b = t.toff[T + 1];
+    }
+}
+
+// Fused step: finish block P, then the dot products of block C.
+template <int NT, typename CH>
+__global__ void __launch_bounds__(NT) k_drop_tile(DropTileArgs A)
+{
+    __shared__ TileLds L;
+    clear_next(A, NT);
+    const int64_t T = blockIdx.x;
+    int64_t p0, p1, c0, c1;
+    list_range(A.P, T, p0, p1);
+    list_range(A.C, T, c0, c1);
+    if (p0 == p1 && c0 == c1) return;
+    double *xt = A.x + (T << kTileShift);
+    for (int w = threadIdx.x; w < kTileWords; w += NT) L.x[w] = xt[w];
+    __syncthreads();
+    if (p1 > p0) tile_finish<NT, CH>(A.P, p0, p1, L, xt, A.lambda, A.big, A.err);
+    if (c1 > c0) tile_dots<NT, CH>(A.C, c0, c1, L, A.dot_max, A.err);
+}
+
+// Split form, first launch: finish block P only.
+template <int NT, typename CH>
+__global__ void __launch_bounds__(NT) k_drop_tile_finish(DropTileArgs A)
+{
+    __shared__ TileLds L;
+    const int64_t T = blockIdx.x;
+    int64_t p0, p1;
+    list_range(A.P, T, p0, p1);
+    if (p0 == p1) return;
+    double *xt = A.x + (T << kTileShift);
+    for (int w = threadIdx.x; w < kTileWords; w += NT) L.x[w] = xt[w];
+    __syncthreads();
+    tile_finish<NT, CH>(A.P, p0, p1, L, xt, A.lambda, A.big, A.err);
+}
+
+// Split form, second launch: dot products of block C only.
+template <int NT, typename CH>
+__global__ void __launch_bounds__(NT) k_drop_tile_dots(DropTileArgs A)
+{
+    __shared__ TileLds L;
+    clear_next(A, NT);
+    const int64_t T = blockIdx.x;
+    int64_t c0, c1;
+    list_range(A.C, T, c0, c1);
+    if (c0 == c1) return;
+    const double *xt = A.x + (T << kTileShift);
+    for (int w = threadIdx.x; w < kTileWords; w += NT) L.x[w] = xt[w];
+    __syncthreads();
+    tile_dots<NT, CH>(A.C, c0, c1, L, A.dot_max, A.err);
+}
+
+__global__ void __launch_bounds__(256) k_zero_i64(long long *p, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * 256)
+        p[q] = 0;
 }
 
 // Launches one kernel; with a timer pair the launch carries its own start and
 // stop events, which take the dispatch's timestamps (no gap around it).
 template <typename F, typename... Args>
-void launch(F kernel, dim3 grid, hipStream_t stream, hipEvent_t t0, hipEvent_t t1,
+void launch(F kernel, dim3 grid, dim3 block, hipStream_t stream, hipEvent_t t0, hipEvent_t t1,
             Args... args)
 {
-    hipExtLaunchKernelGGL(kernel, grid, dim3(kThreads), 0, stream, t0, t1, 0u, args...);
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, t0, t1, 0u, args...);
 }
 
-template <int LPR>
-hipError_t block_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1, double lambda,
-                        const DropBuffers &b, hipStream_t stream, const KTimer *kt)
+template <int NT, typename CH>
+hipError_t drop_tiles(const DropTileArgs &a, int64_t ntiles, int split, hipStream_t stream,
+                      const KTimer &t)
 {
-    const int64_t rows = r1 - r0;
-    if (rows <= 0) return hipSuccess;
-    const KTimer none{};
-    const KTimer &t = kt ? *kt : none;
-    dim3 grid((unsigned)((rows * LPR + kThreads - 1) / kThreads));
-    int64_t wgs = (b.nvox + kThreads - 1) / kThreads;
-    if (wgs > 8192) wgs = 8192;
-    if (b.c64) {
-        unsigned long long *P = reinterpret_cast<unsigned long long *>(b.c);
-        if (rs.chord16)
-            launch(k_drop_rows_packed<LPR, __half>, grid, stream, t.e[0], t.e[1], rs, rs.chord16,
-                   wepl, r0, r1, (const double *)b.x, P, b.c64, b.omask, b.big);
-        else
-            launch(k_drop_rows_packed<LPR, float>, grid, stream, t.e[0], t.e[1], rs, rs.chord32,
-                   wepl, r0, r1, (const double *)b.x, P, b.c64, b.omask, b.big);
-        launch(k_drop_apply_packed, dim3((unsigned)wgs), stream, t.e[2], t.e[3], lambda, b.x, P,
-               b.c64, b.omask, b.nvox);
+    const dim3 grid((unsigned)ntiles), block(NT);
+    if (!split) {
+        launch(k_drop_tile<NT, CH>, grid, block, stream, t.e[0], t.e[1], a);
         return hipGetLastError();
     }
-    if (rs.chord16)
-        launch(k_drop_rows_dense<LPR, __half>, grid, stream, t.e[0], t.e[1], rs, rs.chord16, wepl,
-               r0, r1, (const double *)b.x, b.c, b.s);
-    else
-        launch(k_drop_rows_dense<LPR, float>, grid, stream, t.e[0], t.e[1], rs, rs.chord32, wepl,
-               r0, r1, (const double *)b.x, b.c, b.s);
-    launch(k_drop_apply_dense, dim3((unsigned)wgs), stream, t.e[2], t.e[3], lambda, b.x, b.c, b.s,
-           b.nvox);
+    if (a.P.valid) launch(k_drop_tile_finish<NT, CH>, grid, block, stream, t.e[0], t.e[1], a);
+    launch(k_drop_tile_dots<NT, CH>, grid, block, stream, t.e[2], t.e[3], a);
     return hipGetLastError();
 }
 
-template <int LPR>
-hipError_t csc_block_launch(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
-                            double lambda, const CscBlock &cb, double *x, double *rbuf,
-                            hipStream_t stream, const KTimer *kt)
+template <typename CH>
+hipError_t drop_tiles_nt(const DropTileArgs &a, int64_t ntiles, int threads, int split,
+                         hipStream_t stream, const KTimer &t)
 {
-    const int64_t rows = r1 - r0;
-    if (rows <= 0) return hipSuccess;
-    const KTimer none{};
-    const KTimer &t = kt ? *kt : none;
-    dim3 grid((unsigned)((rows * LPR + kThreads - 1) / kThreads));
-    if (rs.chord16)
-        launch(k_drop_resid<LPR, __half>, grid, stream, t.e[0], t.e[1], rs, rs.chord16, wepl, r0,
-               r1, (const double *)x, rbuf);
-    else
-        launch(k_drop_resid<LPR, float>, grid, stream, t.e[0], t.e[1], rs, rs.chord32, wepl, r0,
-               r1, (const double *)x, rbuf);
-    if (cb.U <= 0) return hipGetLastError();
-    int64_t wgs = (cb.U + kThreads - 1) / kThreads;
-    if (wgs > 4096) wgs = 4096;
-    if (cb.cch16)
-        launch(k_drop_apply_csc<__half>, dim3((unsigned)wgs), stream, t.e[2], t.e[3], cb.uvox,
-               cb.ucol, cb.U, cb.ne, cb.cq, cb.cch16, (const double *)rbuf, lambda, x);
-    else
-        launch(k_drop_apply_csc<float>, dim3((unsigned)wgs), stream, t.e[2], t.e[3], cb.uvox,
-               cb.ucol, cb.U, cb.ne, cb.cq, cb.cch32, (const double *)rbuf, lambda, x);
-    return hipGetLastError();
+    switch (threads) {
+    case 64: return drop_tiles<64, CH>(a, ntiles, split, stream, t);
+    case 128: return drop_tiles<128, CH>(a, ntiles, split, stream, t);
+    default: return drop_tiles<256, CH>(a, ntiles, split, stream, t);
+    }
 }
 
 }  // namespace
 
-hipError_t launch_drop_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
-                                 double lambda, const CscBlock &cb, double *x, double *rbuf,
-                                 int lanes_per_row, hipStream_t stream, const KTimer *kt)
-{
-    switch (lanes_per_row) {
-    case 16: return csc_block_launch<16>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, kt);
-    case 32: return csc_block_launch<32>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, kt);
-    default: return csc_block_launch<64>(rs, wepl, r0, r1, lambda, cb, x, rbuf, stream, kt);
-    }
-}
-
-hipError_t launch_drop_block(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
-                             double lambda, const DropBuffers &b, int parity, int lanes_per_row,
+hipError_t launch_drop_tiles(const DropTileArgs &a, int64_t ntiles, int threads, int split,
                              hipStream_t stream, const KTimer *kt)
 {
-    (void)parity;
-    switch (lanes_per_row) {
-    case 16: return block_launch<16>(rs, wepl, r0, r1, lambda, b, stream, kt);
-    case 32: return block_launch<32>(rs, wepl, r0, r1, lambda, b, stream, kt);
-    default: return block_launch<64>(rs, wepl, r0, r1, lambda, b, stream, kt);
-    }
+    if (ntiles <= 0 || (!a.P.valid && !a.C.valid)) return hipSuccess;
+    const KTimer none{};
+    const KTimer &t = kt ? *kt : none;
+    const bool half = a.P.valid ? (a.P.ch16 != nullptr) : (a.C.ch16 != nullptr);
+    return half ? drop_tiles_nt<__half>(a, ntiles, threads, split, stream, t)
+                : drop_tiles_nt<float>(a, ntiles, threads, split, stream, t);
 }
 
-hipError_t launch_zero_counters(uint32_t *cnt, hipStream_t stream)
+hipError_t launch_zero_i64(long long *p, int64_t n, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, cnt);
+    if (n <= 0) return hipSuccess;
+    int64_t wgs = (n + 255) / 256;
+    if (wgs > 1024) wgs = 1024;
+    hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)wgs), dim3(256), 0, stream, p, n);
     return hipGetLastError();
-}
-
-hipError_t launch_drop_persistent(const RowSet &rs, const float *wepl, int64_t block_size,
-                                  double lambda, const DropBuffers &b, int lanes_per_row,
-                                  int grid_wgs, hipStream_t stream)
-{
-    switch (lanes_per_row) {
-    case 16: return persistent_launch<16>(rs, wepl, block_size, lambda, b, grid_wgs, stream);
-    case 32: return persistent_launch<32>(rs, wepl, block_size, lambda, b, grid_wgs, stream);
-    default: return persistent_launch<64>(rs, wepl, block_size, lambda, b, grid_wgs, stream);
-    }
-}
-
-int persistent_grid_size(int device, int lanes_per_row)
-{
-    int cus = 0, per_cu = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
-        return 0;
-    hipError_t e;
-    switch (lanes_per_row) {
-    case 16:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(k_drop_persistent<16, float>), kThreads, 0);
-        break;
-    case 32:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(k_drop_persistent<32, float>), kThreads, 0);
-        break;
-    default:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(k_drop_persistent<64, float>), kThreads, 0);
-        break;
-    }
-    if (e != hipSuccess || per_cu <= 0) return 0;
-    // Stay well inside co-residency: at most 2 workgroups per CU.
-    if (per_cu > 2) per_cu = 2;
-    return cus * per_cu;
 }
 
 }  // namespace tvs

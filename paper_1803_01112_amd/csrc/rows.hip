@@ -22,6 +22,9 @@ namespace {
 constexpr double kE0 = 13.6;     // MeV, Highland constant
 constexpr double kX0 = 360.8;    // mm, radiation length of water
 constexpr int kThreads = 256;
+// Row kernels: hold the register budget to 3 wavefronts per SIMD (168
+// VGPRs), enough to overlap the float64 latency of one lane's walk.
+constexpr int kRowWaves = 3;
 
 __device__ inline double ipow(double base, int e)
 {
@@ -72,43 +75,116 @@ __device__ inline void mvec(const M2 &A, double x0, double x1, double &y0, doubl
 }
 
 // Row emission state: consecutive pieces in one voxel merge into one entry.
-template <bool FILL, typename CH>
+// Entries also group into segments: maximal runs of consecutive entries in
+// one image tile.  Modes:
+//   kCount    counts entries and segments;
+//   kSeg      reserves each segment's place in its (block, tile) list;
+//   kRowMajor writes the entries in walk order (tvs_debug_rows);
+//   kTiled    writes every entry into its tile list at the reserved place.
+enum EmitMode { kCount = 0, kSeg = 1, kRowMajor = 2, kTiled = 3 };
+
+template <int MODE, typename CH>
 struct Emit {
     int32_t cur = -1;
     double cur_len = 0.0;
     double norm2 = 0.0;
-    int64_t n = 0;
-    int32_t *idx = nullptr;
-    CH *chord = nullptr;
+    int64_t n = 0;               // entries emitted
+    int64_t nseg = 0;            // segments opened
+    int32_t tile = -1;           // tile of the open segment
+    uint32_t seg_len = 0;        // kSeg: entries of the open segment
+    int32_t *idx = nullptr;      // kRowMajor
+    CH *chord = nullptr;         // kRowMajor, kTiled
+    uint32_t *btc = nullptr;     // kSeg: list lengths of this row's block
+    uint64_t *segtab = nullptr;  // kSeg: (tile, place) of this row's segments
+    const int64_t *segdst = nullptr;  // kTiled: first entry of this row's segments
+    uint32_t *meta = nullptr;    // kTiled
+    int64_t base = 0, dst = 0;   // kTiled
+    uint32_t q = 0;              // kTiled: row within its block
+    // kSeg, kTiled: guards against a walk that disagrees with the load-time
+    // count (segments of this row, entries of the buffer); a disagreement
+    // writes nothing and raises *err
+    int64_t seg_cap = 0, cap = 0;
+    uint32_t *err = nullptr;
+    bool ok = true;
+
+    __device__ inline void close_seg()
+    {
+        if constexpr (MODE == kSeg) {
+            if (seg_len && ok) {
+                const uint32_t pos = atomicAdd(btc + tile, seg_len);
+                segtab[nseg - 1] = ((uint64_t)(uint32_t)tile << 32) | pos;
+            }
+            seg_len = 0;
+        }
+    }
+
+    __device__ inline void bad()
+    {
+        if (ok) atomicOr(err, 1u);
+        ok = false;
+    }
 
     __device__ inline void flush()
     {
         if (cur < 0) return;
-        if (FILL) {
+        const int32_t t = cur >> kTileShift;
+        if (t != tile) {
+            close_seg();
+            tile = t;
+            if constexpr (MODE == kSeg || MODE == kTiled) {
+                if (nseg >= seg_cap) bad();
+            }
+            if constexpr (MODE == kTiled) {
+                if (ok) dst = segdst[nseg] - base;
+            }
+            nseg++;
+        }
+        if constexpr (MODE == kRowMajor) {
             idx[n] = cur;
             if constexpr (sizeof(CH) == 4) chord[n] = (float)cur_len;
             else chord[n] = __float2half((float)cur_len);
         }
+        if constexpr (MODE == kTiled) {
+            if (ok && (dst < 0 || dst >= cap)) bad();
+            if (ok) {
+                meta[dst] = (uint32_t)(cur & (kTileWords - 1)) | (q << kTileShift);
+                if constexpr (sizeof(CH) == 4) chord[dst] = (float)cur_len;
+                else chord[dst] = __float2half((float)cur_len);
+                dst++;
+            }
+        }
+        if constexpr (MODE == kSeg) seg_len++;
         norm2 += cur_len * cur_len;
         n++;
         cur = -1;
         cur_len = 0.0;
     }
+
+    __device__ inline void finish()
+    {
+        flush();
+        close_seg();
+    }
 };
 
-template <bool FILL, typename CH>
+// Grid coordinates (p - o) / v of a point.
+__device__ inline void to_grid(const GridDev &g, const double p[3], double gp[3])
+{
+    gp[0] = (p[0] - g.ox) / g.vx;
+    gp[1] = (p[1] - g.oy) / g.vy;
+    gp[2] = (p[2] - g.oz) / g.vz;
+}
+
+// Walks segment q0 -> q1 given both end points and their grid coordinates
+// g0, g1 (each point's coordinates are computed once and shared by the two
+// segments that meet there).
+template <int MODE, typename CH>
 __device__ void walk_segment(const GridDev &g, const double q0[3], const double q1[3],
-                             Emit<FILL, CH> &e)
+                             const double g0[3], const double g1[3], Emit<MODE, CH> &e)
 {
     const int32_t n[3] = {g.nx, g.ny, g.nz};
-    const double vs[3] = {g.vx, g.vy, g.vz};
-    const double o[3] = {g.ox, g.oy, g.oz};
-    double g0[3], g1[3], dg[3];
-    for (int a = 0; a < 3; a++) {
-        g0[a] = (q0[a] - o[a]) / vs[a];
-        g1[a] = (q1[a] - o[a]) / vs[a];
-        dg[a] = g1[a] - g0[a];
-    }
+    double dg[3];
+    for (int a = 0; a < 3; a++) dg[a] = g1[a] - g0[a];
     double dx = q1[0] - q0[0], dy = q1[1] - q0[1], dz = q1[2] - q0[2];
     double len = sqrt(dx * dx + dy * dy + dz * dz);
     if (!(len > 0.0)) return;
@@ -172,10 +248,35 @@ __device__ void walk_segment(const GridDev &g, const double q0[3], const double 
     }
 }
 
+// Inverse covariance of the entry-side slab at depth d1, (Sigma_1(d1))^-1,
+// as {a, b, d} of the symmetric 2x2 matrix [[a, b], [b, d]].  It depends on
+// the depth only, so a context computes it once per vertex depth j * step
+// (k_mlp_table) and every row reads it from that table.
+__device__ inline void entry_sigma_inv(double d1, const MlpCfg &m, double s[3])
+{
+    double b[6];
+    power_coefs(m.const_power, b);
+    double i1[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int mm = 0; mm < 3; mm++) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const double beta = fact(mm) * fact(k) / fact(mm + k + 1);
+            i1[mm] += b[k] * ipow(d1, mm + k + 1) * beta;
+        }
+    }
+    double A1 = highland(d1, m.log_term);
+    M2 S1 = {A1 * i1[2], A1 * i1[1], A1 * i1[1], A1 * i1[0]};
+    M2 S1i = inv(S1);
+    s[0] = S1i.a;
+    s[1] = S1i.b;   // equals S1i.c: S1 is symmetric
+    s[2] = S1i.d;
+}
+
 // MLP of history i and the Siddon walk of its polyline.
-template <bool FILL, typename CH>
+template <int MODE, typename CH>
 __device__ void form_row(const GridDev &g, const HistDev &H, const MlpCfg &m, int64_t i,
-                         Emit<FILL, CH> &e)
+                         Emit<MODE, CH> &e)
 {
     double ex = H.ex[i], ey = H.ey[i], ez = H.ez[i];
     double qx = H.qx[i], qy = H.qy[i], qz = H.qz[i];
@@ -208,30 +309,37 @@ __device__ void form_row(const GridDev &g, const HistDev &H, const MlpCfg &m, in
     }
 
     double prevp[3] = {ex, ey, ez};
+    double prevg[3];
+    to_grid(g, prevp, prevg);
     for (int64_t j = 1; j < J; j++) {
         double d1 = (double)j * m.step;
         double d2 = L - d1;
-        double i1[3] = {0.0, 0.0, 0.0}, j2[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int mm = 0; mm < 3; mm++) {
-#pragma unroll
-            for (int k = 0; k < 6; k++) {
-                const double beta = fact(mm) * fact(k) / fact(mm + k + 1);
-                i1[mm] += b[k] * ipow(d1, mm + k + 1) * beta;
-            }
+        // the table covers every depth of the loaded histories (their vertex
+        // counts bound it); a depth past it raises the consistency flag
+        double s1[3] = {0.0, 0.0, 0.0};
+        if (j < m.nj) {
+            s1[0] = m.s1i[3 * j];
+            s1[1] = m.s1i[3 * j + 1];
+            s1[2] = m.s1i[3 * j + 2];
+        } else if (m.err) {
+            atomicOr(m.err, 1u);
         }
+        // powers d2^e as the running product 1 * d2 * d2 ... (as ipow forms them)
+        double pw[9];
+        pw[0] = 1.0;
+#pragma unroll
+        for (int q = 1; q <= 8; q++) pw[q] = pw[q - 1] * d2;
+        double j2[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int mm = 0; mm < 3; mm++)
 #pragma unroll
             for (int k = 0; k < 6; k++)
-                j2[mm] += c[k] * ipow(d2, mm + k + 1) / (double)(mm + k + 1);
-        double A1 = highland(d1, m.log_term);
+                j2[mm] += c[k] * pw[mm + k + 1] / (double)(mm + k + 1);
         double A2 = highland(d2, m.log_term);
-        M2 S1 = {A1 * i1[2], A1 * i1[1], A1 * i1[1], A1 * i1[0]};
         M2 S2 = {A2 * j2[2], A2 * j2[1], A2 * j2[1], A2 * j2[0]};
         M2 R0 = {1.0, d1, 0.0, 1.0};
         M2 R1 = {1.0, d2, 0.0, 1.0};
-        M2 S1i = inv(S1);
+        M2 S1i = {s1[0], s1[1], s1[1], s1[2]};
         M2 S2i = inv(S2);
         M2 R1t = {R1.a, R1.c, R1.b, R1.d};
         M2 T = mul(R1t, S2i);
@@ -261,44 +369,115 @@ __device__ void form_row(const GridDev &g, const HistDev &H, const MlpCfg &m, in
         }
         double u = u0 + d1;
         double p[3] = {u * ux - y1t * uy, u * uy + y1t * ux, y1v};
-        walk_segment<FILL, CH>(g, prevp, p, e);
-        prevp[0] = p[0];
-        prevp[1] = p[1];
-        prevp[2] = p[2];
+        double pg[3];
+        to_grid(g, p, pg);
+        walk_segment<MODE, CH>(g, prevp, p, prevg, pg, e);
+        for (int a = 0; a < 3; a++) {
+            prevp[a] = p[a];
+            prevg[a] = pg[a];
+        }
     }
     double last[3] = {qx, qy, qz};
-    walk_segment<FILL, CH>(g, prevp, last, e);
+    double lastg[3];
+    to_grid(g, last, lastg);
+    walk_segment<MODE, CH>(g, prevp, last, prevg, lastg, e);
 }
 
-__global__ void __launch_bounds__(kThreads)
-k_rows_count(GridDev g, HistDev H, MlpCfg m, int64_t first, int64_t n, int32_t *nnz)
+__global__ void __launch_bounds__(kThreads) k_mlp_table(MlpCfg m, int64_t nj, double *tab)
+{
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j >= nj) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    if (j > 0) entry_sigma_inv((double)j * m.step, m, s);
+    tab[3 * j] = s[0];
+    tab[3 * j + 1] = s[1];
+    tab[3 * j + 2] = s[2];
+}
+
+__global__ void __launch_bounds__(kThreads, kRowWaves)
+k_rows_count(GridDev g, HistDev H, MlpCfg m, int64_t first, int64_t n, int32_t *nnz, int32_t *nseg)
 {
     int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (q >= n) return;
-    Emit<false, float> e;
-    form_row<false, float>(g, H, m, first + q, e);
-    e.flush();
+    Emit<kCount, float> e;
+    form_row<kCount, float>(g, H, m, first + q, e);
+    e.finish();
     nnz[q] = (int32_t)e.n;
+    if (nseg) nseg[q] = (int32_t)e.nseg;
+}
+
+__global__ void __launch_bounds__(kThreads, kRowWaves)
+k_rows_seg(GridDev g, HistDev H, MlpCfg m, int64_t n, int64_t B, int64_t ntiles,
+           const int64_t *seg_off, uint32_t *btc, uint64_t *segtab, uint32_t *err)
+{
+    int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    Emit<kSeg, float> e;
+    e.btc = btc + (i / B) * ntiles;
+    e.segtab = segtab + seg_off[i];
+    e.seg_cap = seg_off[i + 1] - seg_off[i];
+    e.err = err;
+    form_row<kSeg, float>(g, H, m, i, e);
+    e.finish();
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_seg_dest(int64_t n, int64_t B, int64_t ntiles, const int64_t *seg_off, const int64_t *bt_off,
+           uint64_t *segtab, uint32_t *err)
+{
+    int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const int64_t *bto = bt_off + (i / B) * ntiles;
+    for (int64_t s = seg_off[i]; s < seg_off[i + 1]; s++) {
+        const uint64_t v = segtab[s];
+        const int64_t T = (int64_t)(v >> 32);
+        if (T >= ntiles) {
+            atomicOr(err, 1u);
+            segtab[s] = 0;
+            continue;
+        }
+        segtab[s] = (uint64_t)(bto[T] + (int64_t)(v & 0xffffffffull));
+    }
 }
 
 template <typename CH>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, kRowWaves)
+k_rows_fill_tiled(GridDev g, HistDev H, MlpCfg m, TileFill f, CH *chord)
+{
+    int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= f.n) return;
+    const int64_t i = f.first + q;
+    Emit<kTiled, CH> e;
+    e.segdst = f.segdst + f.seg_off[i];
+    e.seg_cap = f.seg_off[i + 1] - f.seg_off[i];
+    e.cap = f.cap;
+    e.err = f.err;
+    e.meta = f.meta;
+    e.chord = chord;
+    e.base = f.base;
+    e.q = (uint32_t)(i % f.B);
+    form_row<kTiled, CH>(g, H, m, i, e);
+    e.finish();
+    f.norm2[i] = (float)e.norm2;
+}
+
+__global__ void __launch_bounds__(kThreads, kRowWaves)
 k_rows_fill(GridDev g, HistDev H, MlpCfg m, int64_t first, int64_t n, const int64_t *row_off,
-            int64_t base, int32_t *idx, CH *chord, float *norm2)
+            int64_t base, int32_t *idx, float *chord, float *norm2)
 {
     int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (q >= n) return;
-    Emit<true, CH> e;
+    Emit<kRowMajor, float> e;
     int64_t off = row_off[q] - base;
     e.idx = idx + off;
     e.chord = chord + off;
-    form_row<true, CH>(g, H, m, first + q, e);
-    e.flush();
+    form_row<kRowMajor, float>(g, H, m, first + q, e);
+    e.finish();
     norm2[q] = (float)e.norm2;
 }
 
 __global__ void __launch_bounds__(kThreads)
-k_validate(HistDev H, int64_t n, double step, uint32_t *bad)
+k_validate(HistDev H, int64_t n, double step, uint32_t *bad, uint32_t *jmax)
 {
     int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
@@ -319,6 +498,7 @@ k_validate(HistDev H, int64_t n, double step, uint32_t *bad)
             double L = ((double)H.qx[i] - (double)H.ex[i]) * (ux / nrm) +
                        ((double)H.qy[i] - (double)H.ey[i]) * (uy / nrm);
             if (L / step > 1048576.0) ok = false;
+            else if (L > 0.0) atomicMax(jmax, (uint32_t)ceil(L / step) + 2u);
         }
     }
     if (!ok) atomicAdd(bad, 1u);
@@ -405,11 +585,47 @@ k_scan_write(const int32_t *cnt, int64_t n, const int64_t *tile_off, int64_t nti
 }  // namespace
 
 hipError_t launch_rows_count(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t first,
-                             int64_t n, int32_t *nnz, hipStream_t stream)
+                             int64_t n, int32_t *nnz, int32_t *nseg, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
     dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
-    hipLaunchKernelGGL(k_rows_count, grid, dim3(kThreads), 0, stream, g, h, m, first, n, nnz);
+    hipLaunchKernelGGL(k_rows_count, grid, dim3(kThreads), 0, stream, g, h, m, first, n, nnz, nseg);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_seg(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t n,
+                           int64_t B, const int64_t *seg_off, uint32_t *btc, uint64_t *segtab,
+                           uint32_t *err, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(k_rows_seg, grid, dim3(kThreads), 0, stream, g, h, m, n, B, num_tiles(g),
+                       seg_off, btc, segtab, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_dest(const GridDev &g, int64_t n, int64_t B, const int64_t *seg_off,
+                           const int64_t *bt_off, uint64_t *segtab, uint32_t *err,
+                           hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(k_seg_dest, grid, dim3(kThreads), 0, stream, n, B, num_tiles(g), seg_off,
+                       bt_off, segtab, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_fill_tiled(const GridDev &g, const HistDev &h, const MlpCfg &m,
+                                  const TileFill &f, hipStream_t stream)
+{
+    if (f.n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((f.n + kThreads - 1) / kThreads));
+    if (f.ch16)
+        hipLaunchKernelGGL(k_rows_fill_tiled<__half>, grid, dim3(kThreads), 0, stream, g, h, m, f,
+                           f.ch16);
+    else
+        hipLaunchKernelGGL(k_rows_fill_tiled<float>, grid, dim3(kThreads), 0, stream, g, h, m, f,
+                           f.ch32);
     return hipGetLastError();
 }
 
@@ -418,23 +634,27 @@ hipError_t launch_rows_fill(const GridDev &g, const HistDev &h, const MlpCfg &m,
 {
     if (rs.n <= 0) return hipSuccess;
     dim3 grid((unsigned)((rs.n + kThreads - 1) / kThreads));
-    if (rs.chord16)
-        hipLaunchKernelGGL(k_rows_fill<__half>, grid, dim3(kThreads), 0, stream, g, h, m, rs.first,
-                           rs.n, rs.row_off, rs.base, rs.idx, rs.chord16, rs.norm2);
-    else
-        hipLaunchKernelGGL(k_rows_fill<float>, grid, dim3(kThreads), 0, stream, g, h, m, rs.first,
-                           rs.n, rs.row_off, rs.base, rs.idx, rs.chord32, rs.norm2);
+    hipLaunchKernelGGL(k_rows_fill, grid, dim3(kThreads), 0, stream, g, h, m, rs.first, rs.n,
+                       rs.row_off, rs.base, rs.idx, rs.chord32, rs.norm2);
     return hipGetLastError();
 }
 
 int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
 hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *bad,
-                           hipStream_t stream)
+                           uint32_t *jmax, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_validate, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
-                       0, stream, h, n, step, bad);
+                       0, stream, h, n, step, bad, jmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_table(const MlpCfg &m, int64_t nj, double *tab, hipStream_t stream)
+{
+    if (nj <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_table, dim3((unsigned)((nj + kThreads - 1) / kThreads)), dim3(kThreads),
+                       0, stream, m, nj, tab);
     return hipGetLastError();
 }
 

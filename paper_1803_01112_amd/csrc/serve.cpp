@@ -46,24 +46,27 @@ struct Req {
 uint64_t footprint(const tvs_request &r, int64_t chunk)
 {
     // conservative device bytes of one context (see tvs_server_footprint)
-    // image words in the device's brick layout (padding included)
-    const uint64_t nvox = (uint64_t)(((r.grid.nx + 3) / 4) * 4) * (((r.grid.ny + 1) / 2) * 2) *
-                          (uint64_t)r.grid.nz;
+    // image words in the device's tiled layout (16 x 16 tiles, padding included)
+    const uint64_t nvox = (uint64_t)(((r.grid.nx + 15) / 16) * 16) *
+                          (uint64_t)(((r.grid.ny + 15) / 16) * 16) * (uint64_t)r.grid.nz;
+    const uint64_t ntiles = nvox / 256;
     const double vmin = std::min(r.grid.vx, r.grid.vy);
     const double span = (r.grid.nx * r.grid.vx + r.grid.ny * r.grid.vy) / vmin;
     const uint64_t row_est = (uint64_t)(0.8 * span) + (uint64_t)r.grid.nz + 8;
+    const uint64_t seg_est = row_est / 4 + 2;
     const uint64_t n = (uint64_t)std::max<int64_t>(r.n, 0);
+    const uint64_t B = (uint64_t)(r.block_size > 0 ? r.block_size : 3200);
+    const uint64_t nblocks = (n + B - 1) / B;
     uint64_t rows_held;
-    if (r.path_mode == TVS_PATH_ON_THE_FLY) rows_held = std::min<uint64_t>(n, (uint64_t)chunk);
+    if (r.path_mode == TVS_PATH_ON_THE_FLY) rows_held = 2 * std::min<uint64_t>(n, (uint64_t)chunk);
     else rows_held = n;
-    // on the fly: two chunk buffers of int32 index + float32 chord; stores:
-    // row entries, their voxel-major copy (row id + chord) and at most one
-    // distinct-voxel record per entry, plus the build's scratch
-    uint64_t entry = 2 * 8, scratch = 0;
-    if (r.path_mode == TVS_PATH_STORE_F32) entry = 8 + 6 + 8, scratch = 256ull << 20;
-    if (r.path_mode == TVS_PATH_STORE_F16) entry = 6 + 4 + 8, scratch = 256ull << 20;
-    return 52 * n + 12 * n + 8 * n /* load-time count + scan */ + rows_held * row_est * entry +
-           56 * nvox + scratch + (64ull << 20);
+    // entries: 32-bit tag + chord (float32, or float16 for the f16 store)
+    const uint64_t entry = (r.path_mode == TVS_PATH_STORE_F16) ? 6 : 8;
+    const uint64_t per_hist = 52 /* streams */ + 8 + 4 + 8 /* row_off, norm2, seg_off */ +
+                              8 /* load-time counts */ + 8 * seg_est /* segment places */;
+    const uint64_t lists = 12 * (nblocks * ntiles + 1) /* list starts + load-time counts */;
+    return per_hist * n + lists + rows_held * row_est * entry + 40 * nvox + 24 * B +
+           (64ull << 20);
 }
 
 }  // namespace

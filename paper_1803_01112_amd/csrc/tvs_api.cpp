@@ -1,8 +1,9 @@
 // tvs_api.cpp -- the C ABI (include/tvs.h) and the host runtime around the
 // gfx950 kernels: argument validation, device memory ownership and HBM
-// budget, history ingest, row formation (once for a path store, per chunk
-// for on-the-fly rows), the cycle driver (schedule of ell and beta, TV
-// steps with or without the TV-reduction check, the DROP sweep) and the
+// budget, history ingest and the tile lists of every DROP block (their
+// layout fixed at load; rows formed once for a path store, per chunk and
+// sweep for on-the-fly rows), the cycle driver (schedule of ell and beta,
+// TV steps with or without the TV-reduction check, the DROP sweep) and the
 // step log.
 //
 // Cycle structure (arXiv 1803.01112, Appendix C): ell_k = rand(k, ell_{k-1})
@@ -23,10 +24,15 @@
 using tvs::GridDev;
 using tvs::HistDev;
 using tvs::RowSet;
+using tvs::TileBlock;
 
 namespace {
 
 constexpr int kNumStreams = 13;
+
+// Flags on the device: DROP fixed-point range, tile-list consistency,
+// history validation.
+enum { kFlagRange = 0, kFlagLists = 1, kFlagInvalid = 2, kFlagJmax = 3, kNumFlags = 4 };
 
 // SplitMix64 (Steele, Lea, Flood 2014): golden-gamma Weyl state, variant-13
 // output mixer.
@@ -58,52 +64,50 @@ struct tvs_ctx {
     GridDev gd{};
     tvs::MlpCfg mlp{};
     hipStream_t stream = nullptr;
-    int64_t nvox = 0;               // words of a device image (brick layout, padding included)
+    int64_t nvox = 0;               // words of a device image (tiled layout, padding included)
     int64_t nimg = 0;               // voxels of an image at the ABI (nx * ny * nz)
+    int64_t ntiles = 0;
     uint64_t budget = 0;
     uint64_t bytes = 0;
     std::string err;
 
-    // image-side buffers (image, subgradient and corrections float64)
-    double *x = nullptr, *g = nullptr, *c = nullptr;
-    double *c64 = nullptr;          // float64 part of large packed contributions
-    uint32_t *omask = nullptr;      // bit per voxel: c64 holds a contribution
+    // image side (float64, tiled layout)
+    double *x = nullptr, *g = nullptr;
+    double *x0 = nullptr;           // initial iterate, the starting image of batches
     float *xio = nullptr;           // float32 staging of the image at the ABI
-    uint32_t *s = nullptr;
-    int32_t *touched = nullptr;
-    uint32_t *ntouched = nullptr;   // [2] touched counters, [2..4] barrier, [5] scratch flag
     double *part = nullptr, *scal = nullptr;
     uint32_t *ticket = nullptr;
     int64_t nparts = 0;
+    uint32_t *flags = nullptr;      // kNumFlags device flags
+    long long *dot = nullptr;       // 3 x B fixed-point row dot products
 
-    // histories
+    // histories and the tile lists of their DROP blocks
     bool loaded = false;
     int64_t nh = 0;
     float *hist = nullptr;          // 13 * nh floats
-    int64_t *row_off = nullptr;     // nh + 1
+    int64_t *row_off = nullptr;     // nh + 1, entry offsets in walk order
     float *norm2 = nullptr;         // nh
-    int32_t *idx = nullptr;         // store, or the first chunk buffer
-    float *chord32 = nullptr;
-    __half *chord16 = nullptr;
-    int32_t *idx2 = nullptr;        // second chunk buffer (on-the-fly rows)
-    float *chord32b = nullptr;
+    double *s1i = nullptr;          // entry-side MLP table (3 per vertex depth)
+    int64_t nj = 0;
+    int64_t *seg_off = nullptr;     // nh + 1
+    uint64_t *segtab = nullptr;     // nseg: global entry index of each segment's first entry
+    int64_t nseg = 0;
+    int64_t *bt_off = nullptr;      // nblocks * ntiles + 1 list starts
+    int64_t nblocks = 0;
+    uint32_t *meta[2] = {nullptr, nullptr};   // entries: the store, or two chunk buffers
+    float *ch32[2] = {nullptr, nullptr};
+    __half *ch16 = nullptr;
+    int64_t cap = 0;                // entries per buffer
+    int nbuf = 0;
     hipStream_t fill_stream = nullptr;          // row formation of the next chunk
     hipEvent_t ev_filled[2] = {nullptr, nullptr};
-    hipEvent_t ev_dropped[2] = {nullptr, nullptr};
+    hipEvent_t ev_free[2] = {nullptr, nullptr};
     int64_t nnz = 0, max_row = 0, skipped = 0;
-    int64_t chunk = 0;              // histories per chunk (on-the-fly)
-    std::vector<int64_t> chunk_base; // row_off at each chunk start (and the end)
-
-    // voxel-major form of every block of a path store (csc.hip)
-    bool csc = false;
-    int32_t *uvox = nullptr;
-    uint32_t *ucol = nullptr;
-    uint16_t *cq = nullptr;
-    float *cch32 = nullptr;
-    __half *cch16 = nullptr;
-    double *rbuf = nullptr;         // residuals of one block
-    int64_t n_unique = 0;
-    std::vector<int64_t> blk_u, blk_ubase, blk_ebase, blk_ne;
+    int64_t chunk = 0;              // histories per chunk (a multiple of B)
+    std::vector<int64_t> chunk_base;  // entry offset of each chunk start (and the end)
+    double big = 0.0, dot_max = 0.0;  // fixed-point ranges of the DROP kernels
+    int threads = 256;              // threads per tile workgroup
+    int split = 0;                  // 1: two launches per block
 
     // cycle state
     int64_t k = 0, ell = 0;
@@ -123,11 +127,6 @@ struct tvs_ctx {
     double last_sweep_ms = 0, last_tv_ms = 0, last_rows_ms = 0;
     double tot_ms[6] = {0, 0, 0, 0, 0, 0};
     int64_t tot_n[6] = {0, 0, 0, 0, 0, 0};
-    int lpr = 64;
-    int pgrid = 0;
-
-    // initial iterate (float64), the starting image of batches
-    double *x0 = nullptr;
 
     // batched reconstructions
     struct Batch {
@@ -135,14 +134,13 @@ struct tvs_ctx {
         bool valid = false;
         std::vector<tvs_params> p;
         tvs::BatchBuffers b;
+        long long *dot = nullptr;   // 3 x B x S
         int64_t k = 0;
         std::vector<int64_t> ell;
         std::vector<uint64_t> rng;
         int64_t beta_cap = 0;
-        int grid = 0;
         double ms_total = 0;
         int64_t cycles = 0;
-        double *rbuf = nullptr;     // B * S residuals (voxel-major form)
     } batch;
 };
 
@@ -193,41 +191,31 @@ void dfree(tvs_ctx *ctx, T **p, size_t count)
     }
 }
 
-int64_t nnz_cap_of(tvs_ctx *ctx)
-{
-    // entries held by the idx/chord buffers: the whole store, or the largest chunk
-    if (ctx->cfg.path_mode != TVS_PATH_ON_THE_FLY) return ctx->nnz;
-    int64_t m = 0;
-    for (size_t q = 0; q + 1 < ctx->chunk_base.size(); q++)
-        m = std::max(m, ctx->chunk_base[q + 1] - ctx->chunk_base[q]);
-    return m;
-}
+int64_t bt_len(const tvs_ctx *ctx) { return ctx->nblocks * ctx->ntiles + 1; }
 
 void free_histories(tvs_ctx *ctx)
 {
-    int64_t cap = nnz_cap_of(ctx);
     dfree(ctx, &ctx->hist, (size_t)(kNumStreams * ctx->nh));
     dfree(ctx, &ctx->row_off, (size_t)(ctx->nh + 1));
     dfree(ctx, &ctx->norm2, (size_t)ctx->nh);
-    dfree(ctx, &ctx->idx, (size_t)cap);
-    dfree(ctx, &ctx->chord32, (size_t)cap);
-    dfree(ctx, &ctx->chord16, (size_t)cap);
-    dfree(ctx, &ctx->idx2, (size_t)cap);
-    dfree(ctx, &ctx->chord32b, (size_t)cap);
-    dfree(ctx, &ctx->uvox, (size_t)ctx->n_unique);
-    dfree(ctx, &ctx->ucol, (size_t)ctx->n_unique);
-    dfree(ctx, &ctx->cq, (size_t)(ctx->csc ? ctx->nnz : 0));
-    dfree(ctx, &ctx->cch32, (size_t)(ctx->csc ? ctx->nnz : 0));
-    dfree(ctx, &ctx->cch16, (size_t)(ctx->csc ? ctx->nnz : 0));
-    dfree(ctx, &ctx->rbuf, (size_t)ctx->cfg.block_size);
-    ctx->csc = false;
-    ctx->n_unique = 0;
-    ctx->blk_u.clear();
-    ctx->blk_ubase.clear();
-    ctx->blk_ebase.clear();
-    ctx->blk_ne.clear();
+    dfree(ctx, &ctx->seg_off, (size_t)(ctx->nh + 1));
+    dfree(ctx, &ctx->s1i, (size_t)(3 * ctx->nj));
+    ctx->nj = 0;
+    ctx->mlp.s1i = nullptr;
+    ctx->mlp.nj = 0;
+    dfree(ctx, &ctx->segtab, (size_t)ctx->nseg);
+    dfree(ctx, &ctx->bt_off, (size_t)bt_len(ctx));
+    for (int q = 0; q < 2; q++) {
+        dfree(ctx, &ctx->meta[q], (size_t)ctx->cap);
+        dfree(ctx, &ctx->ch32[q], (size_t)ctx->cap);
+    }
+    dfree(ctx, &ctx->ch16, (size_t)ctx->cap);
     ctx->loaded = false;
     ctx->nh = 0;
+    ctx->nseg = 0;
+    ctx->nblocks = 0;
+    ctx->cap = 0;
+    ctx->nbuf = 0;
     ctx->nnz = ctx->max_row = ctx->skipped = 0;
     ctx->chunk_base.clear();
 }
@@ -238,7 +226,6 @@ void free_batch(tvs_ctx *ctx)
     const size_t n = (size_t)(ctx->nvox * B.S);
     dfree(ctx, &B.b.x, n);
     dfree(ctx, &B.b.g, n);
-    dfree(ctx, &B.b.c, n);
     dfree(ctx, &B.b.part, (size_t)(tvs::batch_num_parts(ctx->gd, std::max(B.S, 1)) * B.S));
     dfree(ctx, &B.b.ticket, (size_t)4);
     dfree(ctx, &B.b.norm2, (size_t)B.S);
@@ -246,7 +233,7 @@ void free_batch(tvs_ctx *ctx)
     dfree(ctx, &B.b.eps, (size_t)B.S);
     dfree(ctx, &B.b.beta_tab, (size_t)B.beta_cap);
     dfree(ctx, &B.b.cyc, (size_t)4);
-    dfree(ctx, &B.rbuf, (size_t)(ctx->cfg.block_size * B.S));
+    dfree(ctx, &B.dot, (size_t)(3 * (int64_t)ctx->cfg.block_size * B.S));
     B = tvs_ctx::Batch();
 }
 
@@ -256,21 +243,6 @@ HistDev hist_dev(const tvs_ctx *ctx)
     const int64_t n = ctx->nh;
     return HistDev{b + 0 * n, b + 1 * n, b + 2 * n,  b + 3 * n,  b + 4 * n,  b + 5 * n, b + 6 * n,
                    b + 7 * n, b + 8 * n, b + 9 * n, b + 10 * n, b + 11 * n, b + 12 * n};
-}
-
-tvs::DropBuffers drop_bufs(tvs_ctx *ctx)
-{
-    tvs::DropBuffers b{ctx->x, ctx->c, ctx->s, ctx->touched, ctx->ntouched, ctx->ntouched + 2,
-                       ctx->nvox};
-    // Packed scatter (one 64-bit atomic per entry) when the hit count of a
-    // voxel in a block stays below 2^16: at most 8 entries per row and voxel.
-    const int64_t B = ctx->cfg.block_size;
-    if (B <= 8191) {
-        b.c64 = ctx->c64;
-        b.omask = ctx->omask;
-        b.big = 65536.0 / (8.0 * (double)B);    // 2^(47-30) / (16 B): a factor 2 to spare
-    }
-    return b;
 }
 
 tvs::TvBuffers tv_bufs(tvs_ctx *ctx)
@@ -307,7 +279,7 @@ long mark(tvs_ctx *ctx, hipStream_t st)
     return (long)ctx->tev_used++;
 }
 
-// Reserves an event of the pool without recording it (recorded by a launcher).
+// Reserves an event of the pool without recording it (recorded by a launch).
 long slot(tvs_ctx *ctx)
 {
     if (ctx->tev_used == ctx->tev.size()) {
@@ -323,116 +295,138 @@ void span(tvs_ctx *ctx, int kind, long a, long b)
     if (a >= 0 && b >= 0) ctx->spans.push_back({kind, (size_t)a, (size_t)b});
 }
 
-// Four pool events for the kernels of one sampled block: the rows kernel's
-// start/stop (kind 4) and the apply kernel's (kind 5), stamped by the
-// launches themselves.
-bool ktimer(tvs_ctx *ctx, tvs::KTimer &kt)
+// Pool events for the kernels of one sampled block, stamped by the launches
+// themselves: the first launch (kind 4) and, when the step is split in two
+// launches, the second (kind 5).
+bool ktimer(tvs_ctx *ctx, tvs::KTimer &kt, bool two)
 {
-    long q[4];
-    for (int i = 0; i < 4; i++)
+    const int n = two ? 4 : 2;
+    long q[4] = {-1, -1, -1, -1};
+    for (int i = 0; i < n; i++)
         if ((q[i] = slot(ctx)) < 0) return false;
-    for (int i = 0; i < 4; i++) kt.e[i] = ctx->tev[(size_t)q[i]];
+    for (int i = 0; i < n; i++) kt.e[i] = ctx->tev[(size_t)q[i]];
     span(ctx, 4, q[0], q[1]);
-    span(ctx, 5, q[2], q[3]);
+    if (two) span(ctx, 5, q[2], q[3]);
     return true;
 }
 
-// Row set covering histories [first, first + n) of the loaded data, with
-// the idx/chord buffers (store: global entries; chunk: entries from base).
-RowSet rowset(tvs_ctx *ctx, int64_t first, int64_t n, int64_t base)
+// Checks the device flags raised by the DROP and row kernels (waits for the
+// work queued on st).
+int check_flags(tvs_ctx *ctx, hipStream_t st)
 {
-    RowSet rs;
-    rs.first = first;
-    rs.n = n;
-    rs.base = base;
-    rs.row_off = ctx->row_off + first;
-    rs.norm2 = ctx->norm2 + first;
-    rs.idx = ctx->idx;
-    rs.chord32 = ctx->chord32;
-    rs.chord16 = ctx->chord16;
-    return rs;
+    uint32_t f[kNumFlags] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(f, ctx->flags, sizeof(f), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (f[kFlagLists] || (f[kFlagRange] & 2u))
+        return fail(ctx, TVS_EDEVICE, "a row walk disagreed with its load-time tile lists");
+    if (f[kFlagRange])
+        return fail(ctx, TVS_ERANGE,
+                    "a DROP product |a_ij x_j| left the fixed-point range (image values too "
+                    "large); set a new image to clear");
+    return TVS_OK;
+}
+
+// One block's tile lists as the DROP kernels see them.
+TileBlock block_view(tvs_ctx *ctx, int64_t b, long long *dot_base, int64_t dot_stride)
+{
+    const int64_t B = ctx->cfg.block_size;
+    const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
+    const int64_t c = otf ? (b * B) / ctx->chunk : 0;
+    const int buf = otf ? (int)(c & 1) : 0;
+    TileBlock t;
+    t.meta = ctx->meta[buf];
+    t.ch32 = ctx->ch32[buf];
+    t.ch16 = ctx->ch16;
+    t.toff = ctx->bt_off + b * ctx->ntiles;
+    t.base = otf ? ctx->chunk_base[(size_t)c] : 0;
+    t.wepl = ctx->hist + 12 * ctx->nh + b * B;
+    t.n2 = ctx->norm2 + b * B;
+    t.dot = dot_base + (b % 3) * dot_stride;
+    t.rows = (uint32_t)std::min<int64_t>(B, ctx->nh - b * B);
+    t.valid = 1;
+    return t;
+}
+
+// Forms the rows of chunk c (histories [c*chunk, c*chunk + n)) into its buffer.
+tvs::TileFill chunk_fill(tvs_ctx *ctx, int64_t c, int64_t n)
+{
+    tvs::TileFill f;
+    f.first = c * ctx->chunk;
+    f.n = n;
+    f.B = ctx->cfg.block_size;
+    f.seg_off = ctx->seg_off;
+    f.segdst = reinterpret_cast<const int64_t *>(ctx->segtab);
+    f.base = ctx->chunk_base[(size_t)c];
+    f.meta = ctx->meta[c & 1];
+    f.ch32 = ctx->ch32[c & 1];
+    f.ch16 = ctx->ch16;
+    f.cap = ctx->cap;
+    f.norm2 = ctx->norm2;
+    f.err = ctx->flags + kFlagLists;
+    return f;
 }
 
 // One P_T sweep over the loaded histories (the first `limit` of them when
-// limit >= 0: used to time launch shapes).
+// limit >= 0, a multiple of B: used to time launch shapes).
 int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st, int64_t limit = -1)
 {
     const int64_t B = ctx->cfg.block_size;
     const int64_t nh_run = (limit >= 0) ? std::min(limit, ctx->nh) : ctx->nh;
-    const float *wepl = ctx->hist + 12 * ctx->nh;
-    tvs::DropBuffers db = drop_bufs(ctx);
-    const bool persistent = ctx->pgrid > 0;
+    if (nh_run <= 0) return TVS_OK;
+    const int64_t nb = (nh_run + B - 1) / B;
     const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
     const int64_t step = otf ? ctx->chunk : ctx->nh;
-    const int64_t nchunks = (nh_run + step - 1) / std::max<int64_t>(step, 1);
-    const bool two = otf && ctx->idx2 != nullptr;
-    hipStream_t fs = two ? ctx->fill_stream : st;
-    // forms the rows of chunk q into buffer q & 1 on the fill stream
-    auto fill = [&](int64_t q) -> int {
-        const int64_t f0 = q * step, n0 = std::min(step, nh_run - f0);
-        RowSet rq = rowset(ctx, f0, n0, ctx->chunk_base[q]);
-        if (two && (q & 1)) {
-            rq.idx = ctx->idx2;
-            rq.chord32 = ctx->chord32b;
-        }
-        if (two) HIPCHK(hipStreamWaitEvent(fs, ctx->ev_dropped[q & 1], 0));
+    const int64_t nchunks = (nh_run + step - 1) / step;
+    hipStream_t fs = ctx->fill_stream;
+    HIPCHK(tvs::launch_zero_i64(ctx->dot, 3 * B, st));
+    auto fill = [&](int64_t c) -> int {
+        const int64_t n = std::min(step, nh_run - c * step);
+        tvs::TileFill f = chunk_fill(ctx, c, n);
+        HIPCHK(hipStreamWaitEvent(fs, ctx->ev_free[c & 1], 0));
         long a = mark(ctx, fs);
-        HIPCHK(tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rq, fs));
+        HIPCHK(tvs::launch_rows_fill_tiled(ctx->gd, hist_dev(ctx), ctx->mlp, f, fs));
         span(ctx, 2, a, mark(ctx, fs));
-        if (two) HIPCHK(hipEventRecord(ctx->ev_filled[q & 1], fs));
+        HIPCHK(hipEventRecord(ctx->ev_filled[c & 1], fs));
         return TVS_OK;
     };
-    if (otf && nchunks > 0) {
+    if (otf) {
         int rc = fill(0);
+        if (!rc && nchunks > 1) rc = fill(1);
         if (rc) return rc;
     }
-    for (int64_t first = 0, q = 0; first < nh_run; first += step, q++) {
-        const int64_t n = std::min(step, nh_run - first);
-        RowSet rs = rowset(ctx, first, n, otf ? ctx->chunk_base[q] : 0);
-        if (two && (q & 1)) {
-            rs.idx = ctx->idx2;
-            rs.chord32 = ctx->chord32b;
-        }
-        if (otf && q + 1 < nchunks) {
-            int rc = fill(q + 1);   // overlaps the DROP chain of chunk q
-            if (rc) return rc;
-        }
-        if (two) HIPCHK(hipStreamWaitEvent(st, ctx->ev_filled[q & 1], 0));
-        long e0 = mark(ctx, st);
-        if (ctx->csc) {
-            for (int64_t r0 = first, t = first / B; r0 < first + n; r0 += B, t++) {
-                const int64_t r1 = std::min(r0 + B, first + n);
-                tvs::CscBlock cb;
-                cb.uvox = ctx->uvox + ctx->blk_ubase[t];
-                cb.ucol = ctx->ucol + ctx->blk_ubase[t];
-                cb.U = ctx->blk_u[t];
-                cb.ne = ctx->blk_ne[t];
-                cb.cq = ctx->cq + ctx->blk_ebase[t];
-                if (ctx->cch16) cb.cch16 = ctx->cch16 + ctx->blk_ebase[t];
-                else cb.cch32 = ctx->cch32 + ctx->blk_ebase[t];
-                const bool samp = ctx->cfg.time_sample > 0 && t % ctx->cfg.time_sample == 0;
-                tvs::KTimer kt;
-                const bool timed = samp && ktimer(ctx, kt);
-                HIPCHK(tvs::launch_drop_block_csc(rs, wepl, r0, r1, lambda, cb, ctx->x, ctx->rbuf,
-                                                  ctx->lpr, st, timed ? &kt : nullptr));
+    long e0 = mark(ctx, st);
+    for (int64_t b = 0; b <= nb; b++) {
+        const bool has_c = b < nb;
+        const int64_t c = has_c ? (b * B) / step : -1;
+        const bool first_of_chunk = has_c && (b * B) % step == 0;
+        if (otf && first_of_chunk) HIPCHK(hipStreamWaitEvent(st, ctx->ev_filled[c & 1], 0));
+        tvs::DropTileArgs A;
+        if (b > 0) A.P = block_view(ctx, b - 1, ctx->dot, B);
+        if (has_c) A.C = block_view(ctx, b, ctx->dot, B);
+        A.x = ctx->x;
+        A.lambda = lambda;
+        A.big = ctx->big;
+        A.dot_max = ctx->dot_max;
+        A.zero = ctx->dot + ((b + 1) % 3) * B;
+        A.B = B;
+        A.err = ctx->flags + kFlagRange;
+        const bool samp = ctx->cfg.time_sample > 0 && has_c && b > 0 &&
+                          b % ctx->cfg.time_sample == 0;
+        tvs::KTimer kt;
+        const bool timed = samp && ktimer(ctx, kt, ctx->split != 0);
+        HIPCHK(tvs::launch_drop_tiles(A, ctx->ntiles, ctx->threads, ctx->split, st,
+                                      timed ? &kt : nullptr));
+        if (otf && first_of_chunk && c >= 1) {
+            // the launch above was the last to read chunk c - 1's buffer
+            HIPCHK(hipEventRecord(ctx->ev_free[(c - 1) & 1], st));
+            if (c + 1 < nchunks) {
+                int rc = fill(c + 1);
+                if (rc) return rc;
             }
-        } else if (persistent) {
-            HIPCHK(tvs::launch_drop_persistent(rs, wepl, B, lambda, db, ctx->lpr, ctx->pgrid, st));
-        } else {
-            int parity = 0;
-            for (int64_t r0 = first, t = first / B; r0 < first + n; r0 += B, parity ^= 1, t++) {
-                int64_t r1 = std::min(r0 + B, first + n);
-                const bool samp = ctx->cfg.time_sample > 0 && t % ctx->cfg.time_sample == 0;
-                tvs::KTimer kt;
-                const bool timed = samp && ktimer(ctx, kt);
-                HIPCHK(tvs::launch_drop_block(rs, wepl, r0, r1, lambda, db, parity, ctx->lpr, st,
-                                              timed ? &kt : nullptr));
-            }
-            HIPCHK(tvs::launch_zero_counters(ctx->ntouched, st));
         }
-        span(ctx, 3, e0, mark(ctx, st));
-        if (two) HIPCHK(hipEventRecord(ctx->ev_dropped[q & 1], st));
     }
+    span(ctx, 3, e0, mark(ctx, st));
+    if (otf) HIPCHK(hipEventRecord(ctx->ev_free[(nchunks - 1) & 1], st));
     return TVS_OK;
 }
 
@@ -458,7 +452,7 @@ int read_scalars(tvs_ctx *ctx, hipStream_t st, double out[2])
     return TVS_OK;
 }
 
-// Forms rows [first, first+n) with temporary buffers (used by load and debug).
+// Row lengths of histories [first, first + n) into row_off_dev (n + 1).
 int count_rows(tvs_ctx *ctx, int64_t first, int64_t n, int64_t *row_off_dev, hipStream_t st)
 {
     int32_t *cnt = nullptr;
@@ -470,7 +464,8 @@ int count_rows(tvs_ctx *ctx, int64_t first, int64_t n, int64_t *row_off_dev, hip
         dfree(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
         return rc;
     }
-    hipError_t e = tvs::launch_rows_count(ctx->gd, hist_dev(ctx), ctx->mlp, first, n, cnt, st);
+    hipError_t e =
+        tvs::launch_rows_count(ctx->gd, hist_dev(ctx), ctx->mlp, first, n, cnt, nullptr, st);
     if (e == hipSuccess) e = tvs::launch_scan(cnt, n, row_off_dev, tmp, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     dfree(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
@@ -479,127 +474,156 @@ int count_rows(tvs_ctx *ctx, int64_t first, int64_t n, int64_t *row_off_dev, hip
     return TVS_OK;
 }
 
-// Builds the voxel-major form of every block of the path store.
-int build_csc(tvs_ctx *ctx, hipStream_t st)
+// Lays out the tile lists of every block: row and segment counts, each
+// segment's place in its (block, tile) list, the list starts.  Sets nnz,
+// max_row, skipped, nseg, nblocks and the chunking.
+int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
 {
-    const int64_t B = ctx->cfg.block_size, nh = ctx->nh, nvox = ctx->nvox;
-    const int64_t T = (nh + B - 1) / B;
-    if (T == 0) return TVS_OK;
-    std::vector<int64_t> off((size_t)nh + 1);
-    HIPCHK(hipMemcpy(off.data(), ctx->row_off, sizeof(int64_t) * (nh + 1), hipMemcpyDeviceToHost));
-    ctx->blk_ebase.resize((size_t)T);
-    ctx->blk_ne.resize((size_t)T);
-    ctx->blk_u.assign((size_t)T, 0);
-    ctx->blk_ubase.assign((size_t)T, 0);
-    for (int64_t t = 0; t < T; t++) {
-        const int64_t r0 = t * B, r1 = std::min(r0 + B, nh);
-        ctx->blk_ebase[t] = off[(size_t)r0];
-        ctx->blk_ne[t] = off[(size_t)r1] - off[(size_t)r0];
-    }
-    int64_t NB = (int64_t)((256ll << 20) / (24 * std::max<int64_t>(nvox, 1)));
-    NB = std::max<int64_t>(1, std::min<int64_t>(NB, 64));
-    NB = std::min(NB, T);
-    const int64_t n = NB * nvox;
-    uint32_t *cnt = nullptr;
-    int32_t *flag = nullptr;
-    int64_t *urank = nullptr, *cstart = nullptr, *tmp = nullptr, *meta = nullptr;
+    const int64_t n = ctx->nh, B = ctx->cfg.block_size;
+    const int64_t nbt = ((n + B - 1) / B) * ctx->ntiles;
+    int32_t *cnt = nullptr, *cseg = nullptr;
+    uint32_t *btc = nullptr;
+    int64_t *tmp = nullptr;
+    const int64_t ntmp = tvs::scan_tmp_elems(std::max(n, nbt)) + 1;
     auto cleanup = [&]() {
-        dfree(ctx, &cnt, (size_t)n);
-        dfree(ctx, &flag, (size_t)n);
-        dfree(ctx, &urank, (size_t)n + 1);
-        dfree(ctx, &cstart, (size_t)n + 1);
-        dfree(ctx, &tmp, (size_t)tvs::scan_tmp_elems(n) + 1);
-        dfree(ctx, &meta, (size_t)(5 * (NB + 1)));
+        dfree(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
+        dfree(ctx, &cseg, (size_t)std::max<int64_t>(n, 1));
+        dfree(ctx, &btc, (size_t)std::max<int64_t>(nbt, 1));
+        dfree(ctx, &tmp, (size_t)ntmp);
     };
-    int rc = dalloc(ctx, &cnt, (size_t)n);
-    if (!rc) rc = dalloc(ctx, &flag, (size_t)n);
-    if (!rc) rc = dalloc(ctx, &urank, (size_t)n + 1);
-    if (!rc) rc = dalloc(ctx, &cstart, (size_t)n + 1);
-    if (!rc) rc = dalloc(ctx, &tmp, (size_t)tvs::scan_tmp_elems(n) + 1);
-    if (!rc) rc = dalloc(ctx, &meta, (size_t)(5 * (NB + 1)));
+    int rc = dalloc(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
+    if (!rc) rc = dalloc(ctx, &cseg, (size_t)std::max<int64_t>(n, 1));
+    if (!rc) rc = dalloc(ctx, &tmp, (size_t)ntmp);
     if (rc) {
         cleanup();
         return rc;
     }
-    RowSet rs = rowset(ctx, 0, nh, 0);
-    std::vector<int64_t> picks((size_t)NB + 1);
-    hipError_t e = hipSuccess;
-    // pass 1: distinct voxels per block
-    for (int64_t b0 = 0; b0 < T && e == hipSuccess; b0 += NB) {
-        const int64_t nb = std::min(NB, T - b0);
-        const int64_t r0 = b0 * B, r1 = std::min((b0 + nb) * B, nh);
-        e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb * nvox, st);
-        if (e == hipSuccess) e = tvs::csc_count(rs, r0, r1, B, b0, nvox, cnt, st);
-        if (e == hipSuccess) e = tvs::csc_flags(cnt, nb * nvox, flag, st);
-        if (e == hipSuccess) e = tvs::launch_scan(flag, nb * nvox, urank, tmp, st);
-        if (e == hipSuccess) e = tvs::csc_pick(urank, nvox, nb, meta, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(picks.data(), meta, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        for (int64_t b = 0; b < nb && e == hipSuccess; b++) ctx->blk_u[b0 + b] = picks[b + 1] - picks[b];
-    }
+    HistDev hd = hist_dev(ctx);
+    hipError_t e = tvs::launch_rows_count(ctx->gd, hd, ctx->mlp, 0, n, cnt, cseg, st);
+    if (e == hipSuccess) e = tvs::launch_scan(cnt, n, ctx->row_off, tmp, st);
+    if (e == hipSuccess) e = tvs::launch_scan(cseg, n, ctx->seg_off, tmp, st);
+    std::vector<int64_t> off((size_t)n + 1);
+    int64_t nseg = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(off.data(), ctx->row_off, sizeof(int64_t) * (n + 1),
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&nseg, ctx->seg_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         cleanup();
-        return fail(ctx, TVS_EDEVICE, std::string("voxel-major build: ") + hipGetErrorString(e));
+        return fail(ctx, TVS_EDEVICE, std::string("row count: ") + hipGetErrorString(e));
     }
-    int64_t tot = 0;
-    for (int64_t t = 0; t < T; t++) {
-        ctx->blk_ubase[t] = tot;
-        tot += ctx->blk_u[t];
+    dfree(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
+    dfree(ctx, &cseg, (size_t)std::max<int64_t>(n, 1));
+    const int64_t total = off[(size_t)n];
+    int64_t mx = 0, sk = 0;
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t len = off[(size_t)i + 1] - off[(size_t)i];
+        mx = std::max(mx, len);
+        sk += (len == 0);
     }
-    ctx->n_unique = tot;
-    rc = dalloc(ctx, &ctx->uvox, (size_t)tot);
-    if (!rc) rc = dalloc(ctx, &ctx->ucol, (size_t)tot);
-    if (!rc) rc = dalloc(ctx, &ctx->cq, (size_t)ctx->nnz);
-    if (!rc) {
-        if (ctx->chord16) rc = dalloc(ctx, &ctx->cch16, (size_t)ctx->nnz);
-        else rc = dalloc(ctx, &ctx->cch32, (size_t)ctx->nnz);
-    }
-    if (!rc) rc = dalloc(ctx, &ctx->rbuf, (size_t)B);
-    ctx->csc = true;   // so that a failure frees the column arrays with the right sizes
+    ctx->nnz = total;
+    ctx->max_row = mx;
+    ctx->skipped = sk;
+    ctx->nseg = nseg;
+    ctx->nblocks = (n + B - 1) / B;
+    int64_t chunk = ctx->cfg.chunk_histories;
+    if (chunk <= 0) chunk = std::max<int64_t>(B, ((int64_t)1 << 20) / B * B);
+    else chunk = (chunk + B - 1) / B * B;
+    ctx->chunk = std::max<int64_t>(chunk, 1);
+    for (int64_t f = 0; f < n; f += ctx->chunk) ctx->chunk_base.push_back(off[(size_t)f]);
+    ctx->chunk_base.push_back(total);
+    // integer ranges of the DROP sums: no voxel takes more than 2B entries of
+    // one block, no row more than max_row entries
+    ctx->big = 2097152.0 / (double)B;                              // 2^21 / B
+    ctx->dot_max = 67108864.0 / (double)std::max<int64_t>(mx, 1);  // 2^26 / max_row
+
+    rc = dalloc(ctx, &ctx->segtab, (size_t)nseg);
+    if (!rc) rc = dalloc(ctx, &ctx->bt_off, (size_t)bt_len(ctx));
+    if (!rc) rc = dalloc(ctx, &btc, (size_t)std::max<int64_t>(nbt, 1));
     if (rc) {
         cleanup();
         return rc;
     }
-    // pass 2: distinct-voxel records, column placement, column sort
-    std::vector<int64_t> hm((size_t)(4 * NB));
-    for (int64_t b0 = 0; b0 < T && e == hipSuccess; b0 += NB) {
-        const int64_t nb = std::min(NB, T - b0);
-        const int64_t r0 = b0 * B, r1 = std::min((b0 + nb) * B, nh);
-        int64_t maxu = 0;
-        for (int64_t b = 0; b < nb; b++) {
-            hm[(size_t)b] = ctx->blk_ubase[b0 + b];
-            hm[(size_t)(NB + b)] = ctx->blk_ebase[b0 + b];
-            hm[(size_t)(2 * NB + b)] = ctx->blk_u[b0 + b];
-            hm[(size_t)(3 * NB + b)] = ctx->blk_ne[b0 + b];
-            maxu = std::max(maxu, ctx->blk_u[b0 + b]);
-        }
-        int64_t *d_ubase = meta, *d_ebase = meta + NB, *d_ucnt = meta + 2 * NB, *d_ecnt = meta + 3 * NB;
-        e = hipMemcpyAsync(meta, hm.data(), sizeof(int64_t) * 4 * NB, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb * nvox, st);
-        if (e == hipSuccess) e = tvs::csc_count(rs, r0, r1, B, b0, nvox, cnt, st);
-        if (e == hipSuccess) e = tvs::csc_flags(cnt, nb * nvox, flag, st);
-        if (e == hipSuccess) e = tvs::launch_scan(flag, nb * nvox, urank, tmp, st);
-        if (e == hipSuccess) e = tvs::csc_as_int(cnt, nb * nvox, flag, st);
-        if (e == hipSuccess) e = tvs::launch_scan(flag, nb * nvox, cstart, tmp, st);
-        if (e == hipSuccess)
-            e = tvs::csc_emit(cnt, urank, cstart, nb, nvox, d_ubase, d_ebase, ctx->uvox, ctx->ucol, st);
-        if (e == hipSuccess)
-            e = tvs::csc_place(rs, r0, r1, B, b0, nvox, cnt, d_ebase, ctx->cq, ctx->cch32, ctx->cch16, st);
-        if (e == hipSuccess)
-            e = tvs::csc_sort(ctx->ucol, d_ubase, d_ucnt, d_ebase, d_ecnt, nb, maxu, ctx->cq,
-                              ctx->cch32, ctx->cch16, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);   // meta is reused by the next batch
-    }
+    e = hipMemsetAsync(btc, 0, sizeof(uint32_t) * std::max<int64_t>(nbt, 1), st);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->flags, 0, sizeof(uint32_t) * kNumFlags, st);
+    if (e == hipSuccess)
+        e = tvs::launch_rows_seg(ctx->gd, hd, ctx->mlp, n, B, ctx->seg_off, btc, ctx->segtab,
+                                 ctx->flags + kFlagLists, st);
+    if (e == hipSuccess)
+        e = tvs::launch_scan(reinterpret_cast<const int32_t *>(btc), nbt, ctx->bt_off, tmp, st);
+    if (e == hipSuccess)
+        e = tvs::launch_seg_dest(ctx->gd, n, B, ctx->seg_off, ctx->bt_off, ctx->segtab,
+                                 ctx->flags + kFlagLists, st);
+    // every block's lists must add up to the block's entries
+    std::vector<int64_t> starts((size_t)ctx->nblocks + 1);
+    if (e == hipSuccess && ctx->nblocks > 0)
+        e = hipMemcpy2DAsync(starts.data(), sizeof(int64_t), ctx->bt_off,
+                             sizeof(int64_t) * ctx->ntiles, sizeof(int64_t),
+                             (size_t)ctx->nblocks + 1, hipMemcpyDeviceToHost, st);
+    uint32_t fl[kNumFlags] = {0, 0, 0, 0};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(fl, ctx->flags, sizeof(fl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     cleanup();
-    if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("voxel-major build: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("tile lists: ") + hipGetErrorString(e));
+    bool same = !fl[kFlagLists];
+    for (int64_t b = 0; same && b < ctx->nblocks; b++)
+        same = starts[(size_t)b] == off[(size_t)(b * B)];
+    if (same && ctx->nblocks > 0) same = starts[(size_t)ctx->nblocks] == total;
+    if (!same) return fail(ctx, TVS_EDEVICE, "tile lists disagree with the row lengths");
     return TVS_OK;
+}
+
+// Allocates the entry buffers and, for a path store, forms every row now.
+int form_entries(tvs_ctx *ctx, hipStream_t st)
+{
+    const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
+    int64_t cap = ctx->nnz;
+    if (otf) {
+        cap = 0;
+        for (size_t q = 0; q + 1 < ctx->chunk_base.size(); q++)
+            cap = std::max(cap, ctx->chunk_base[q + 1] - ctx->chunk_base[q]);
+    }
+    ctx->cap = std::max<int64_t>(cap, 1);
+    ctx->nbuf = (otf && ctx->chunk_base.size() > 2) ? 2 : 1;
+    int rc = TVS_OK;
+    for (int q = 0; q < ctx->nbuf && !rc; q++) {
+        rc = dalloc(ctx, &ctx->meta[q], (size_t)ctx->cap);
+        if (!rc) {
+            if (ctx->cfg.path_mode == TVS_PATH_STORE_F16) rc = dalloc(ctx, &ctx->ch16, (size_t)ctx->cap);
+            else rc = dalloc(ctx, &ctx->ch32[q], (size_t)ctx->cap);
+        }
+        // entries start as (row 0, word 0, chord 0): never an index out of range
+        if (!rc) HIPCHK(hipMemsetAsync(ctx->meta[q], 0, sizeof(uint32_t) * ctx->cap, st));
+        if (!rc && ctx->ch32[q]) HIPCHK(hipMemsetAsync(ctx->ch32[q], 0, sizeof(float) * ctx->cap, st));
+    }
+    if (!rc && ctx->ch16) HIPCHK(hipMemsetAsync(ctx->ch16, 0, sizeof(__half) * ctx->cap, st));
+    if (rc) return rc;
+    if (otf || ctx->nh == 0) return TVS_OK;
+    tvs::TileFill f;
+    f.first = 0;
+    f.n = ctx->nh;
+    f.B = ctx->cfg.block_size;
+    f.seg_off = ctx->seg_off;
+    f.segdst = reinterpret_cast<const int64_t *>(ctx->segtab);
+    f.base = 0;
+    f.meta = ctx->meta[0];
+    f.ch32 = ctx->ch32[0];
+    f.ch16 = ctx->ch16;
+    f.cap = ctx->cap;
+    f.norm2 = ctx->norm2;
+    f.err = ctx->flags + kFlagLists;
+    hipError_t e = tvs::launch_rows_fill_tiled(ctx->gd, hist_dev(ctx), ctx->mlp, f, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("row fill: ") + hipGetErrorString(e));
+    return check_flags(ctx, st);
 }
 
 }  // namespace
 
 extern "C" {
-
 
 void tvs_config_default(tvs_config *cfg)
 {
@@ -615,7 +639,7 @@ void tvs_config_default(tvs_config *cfg)
     cfg->device = 0;
     cfg->max_tries = 0;
     cfg->sweep_kernel = 0;
-    cfg->wave_rows = 0;
+    cfg->tile_threads = 0;
     cfg->time_sample = 0;
 }
 
@@ -627,7 +651,7 @@ const char *tvs_strerror(int status)
     case TVS_ENOMEM: return "out of device memory or HBM budget";
     case TVS_EDEVICE: return "HIP device error";
     case TVS_ESTATE: return "call out of order";
-    case TVS_ERANGE: return "index or size out of range";
+    case TVS_ERANGE: return "index, size or value out of range";
     default: return "unknown status";
     }
 }
@@ -645,13 +669,9 @@ void tvs_destroy(tvs_ctx *ctx)
     dfree(ctx, &ctx->x0, (size_t)ctx->nvox);
     dfree(ctx, &ctx->x, (size_t)ctx->nvox);
     dfree(ctx, &ctx->xio, (size_t)ctx->nvox);
-    dfree(ctx, &ctx->c, (size_t)ctx->nvox);
-    dfree(ctx, &ctx->c64, (size_t)ctx->nvox);
-    dfree(ctx, &ctx->omask, (size_t)(ctx->nvox + 31) / 32);
     dfree(ctx, &ctx->g, (size_t)ctx->nvox);
-    dfree(ctx, &ctx->s, (size_t)ctx->nvox);
-    dfree(ctx, &ctx->touched, (size_t)ctx->nvox);
-    dfree(ctx, &ctx->ntouched, (size_t)8);
+    dfree(ctx, &ctx->flags, (size_t)kNumFlags);
+    dfree(ctx, &ctx->dot, (size_t)(3 * (int64_t)ctx->cfg.block_size));
     dfree(ctx, &ctx->part, (size_t)ctx->nparts);
     dfree(ctx, &ctx->scal, (size_t)4);
     dfree(ctx, &ctx->ticket, (size_t)4);
@@ -659,7 +679,7 @@ void tvs_destroy(tvs_ctx *ctx)
         if (e) (void)hipEventDestroy(e);
     for (int q = 0; q < 2; q++) {
         if (ctx->ev_filled[q]) (void)hipEventDestroy(ctx->ev_filled[q]);
-        if (ctx->ev_dropped[q]) (void)hipEventDestroy(ctx->ev_dropped[q]);
+        if (ctx->ev_free[q]) (void)hipEventDestroy(ctx->ev_free[q]);
     }
     if (ctx->fill_stream) (void)hipStreamDestroy(ctx->fill_stream);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -679,16 +699,18 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (!finite_pos(grid->vx) || !finite_pos(grid->vy) || !finite_pos(grid->vz)) return TVS_EINVAL;
     if (!std::isfinite(grid->ox) || !std::isfinite(grid->oy) || !std::isfinite(grid->oz))
         return TVS_EINVAL;
+    if (grid->nx >= (1 << 20) || grid->ny >= (1 << 20) || grid->nz >= (1 << 20)) return TVS_EINVAL;
     const tvs::GridDev gdev = tvs::make_grid_dev(*grid);
     const int64_t nimg = (int64_t)grid->nx * grid->ny * grid->nz;
-    const int64_t nvox = tvs::padded_voxels(gdev);     // device image words (brick layout)
+    const int64_t nvox = tvs::padded_voxels(gdev);     // device image words (tiled layout)
     if (nvox >= ((int64_t)1 << 31)) return TVS_EINVAL;
-    if (cfg.block_size < 1) return TVS_EINVAL;
+    if (cfg.block_size < 1 || cfg.block_size > (1 << 24)) return TVS_EINVAL;
     if (cfg.path_mode < 0 || cfg.path_mode > 2) return TVS_EINVAL;
     if (!std::isfinite(cfg.mlp_step_mm)) return TVS_EINVAL;
     if (cfg.chunk_histories < 0 || cfg.max_tries < 0) return TVS_EINVAL;
     if (cfg.sweep_kernel < 0 || cfg.sweep_kernel > 2) return TVS_EINVAL;
-    if (cfg.wave_rows != 0 && cfg.wave_rows != 16 && cfg.wave_rows != 32 && cfg.wave_rows != 64)
+    if (cfg.tile_threads != 0 && cfg.tile_threads != 64 && cfg.tile_threads != 128 &&
+        cfg.tile_threads != 256)
         return TVS_EINVAL;
     if (cfg.time_sample < 0) return TVS_EINVAL;
     int ndev = 0;
@@ -701,11 +723,13 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     ctx->cfg = cfg;
     ctx->gd = gdev;
     ctx->nimg = nimg;
+    ctx->nvox = nvox;
+    ctx->ntiles = tvs::num_tiles(gdev);
     double step = cfg.mlp_step_mm > 0.0 ? cfg.mlp_step_mm : std::min(grid->vx, grid->vy);
     ctx->mlp = tvs::MlpCfg{step, cfg.mlp_log_term ? 1 : 0, cfg.mlp_const_power ? 1 : 0};
     if (ctx->cfg.max_tries == 0) ctx->cfg.max_tries = 100000;
-    ctx->nvox = nvox;
-    ctx->lpr = cfg.wave_rows ? cfg.wave_rows : 64;
+    ctx->threads = cfg.tile_threads ? cfg.tile_threads : 256;
+    ctx->split = (cfg.sweep_kernel == 2) ? 1 : 0;
 
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
@@ -719,13 +743,9 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (!rc) rc = dalloc(ctx, &ctx->x, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->x0, (size_t)nvox);
     if (!rc) rc = dalloc(ctx, &ctx->xio, (size_t)nvox);
-    if (!rc) rc = dalloc(ctx, &ctx->c, (size_t)nvox);
-    if (!rc) rc = dalloc(ctx, &ctx->c64, (size_t)nvox);
-    if (!rc) rc = dalloc(ctx, &ctx->omask, (size_t)(nvox + 31) / 32);
     if (!rc) rc = dalloc(ctx, &ctx->g, (size_t)nvox);
-    if (!rc) rc = dalloc(ctx, &ctx->s, (size_t)nvox);
-    if (!rc) rc = dalloc(ctx, &ctx->touched, (size_t)nvox);
-    if (!rc) rc = dalloc(ctx, &ctx->ntouched, (size_t)8);
+    if (!rc) rc = dalloc(ctx, &ctx->flags, (size_t)kNumFlags);
+    if (!rc) rc = dalloc(ctx, &ctx->dot, (size_t)(3 * (int64_t)cfg.block_size));
     if (!rc) rc = dalloc(ctx, &ctx->part, (size_t)ctx->nparts);
     if (!rc) rc = dalloc(ctx, &ctx->scal, (size_t)4);
     if (!rc) rc = dalloc(ctx, &ctx->ticket, (size_t)4);
@@ -740,8 +760,8 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     }
     for (int q = 0; q < 2; q++) {
         if (hipEventCreateWithFlags(&ctx->ev_filled[q], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&ctx->ev_dropped[q], hipEventDisableTiming) != hipSuccess ||
-            hipEventRecord(ctx->ev_dropped[q], ctx->stream) != hipSuccess) {
+            hipEventCreateWithFlags(&ctx->ev_free[q], hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ctx->ev_free[q], ctx->stream) != hipSuccess) {
             tvs_destroy(ctx);
             return TVS_EDEVICE;
         }
@@ -749,12 +769,8 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemsetAsync(ctx->x, 0, sizeof(double) * nvox, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->x0, 0, sizeof(double) * nvox, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->c, 0, sizeof(double) * nvox, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->c64, 0, sizeof(double) * nvox, ctx->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(ctx->omask, 0, sizeof(uint32_t) * ((nvox + 31) / 32), ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->s, 0, sizeof(uint32_t) * nvox, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->ntouched, 0, sizeof(uint32_t) * 8, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->g, 0, sizeof(double) * nvox, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->flags, 0, sizeof(uint32_t) * kNumFlags, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->ticket, 0, sizeof(uint32_t) * 4, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->scal, 0, sizeof(double) * 4, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -762,10 +778,6 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
         tvs_destroy(ctx);
         return TVS_EDEVICE;
     }
-    // launches are far cheaper than device-wide barriers on gfx950, so the
-    // default sweep is one launch per block phase; 2 keeps the persistent form
-    int sk = cfg.sweep_kernel ? cfg.sweep_kernel : 1;
-    ctx->pgrid = (sk == 2) ? tvs::persistent_grid_size(cfg.device, ctx->lpr) : 0;
     *out = ctx;
     return TVS_OK;
 }
@@ -789,16 +801,20 @@ int tvs_load_histories(tvs_ctx *ctx, int64_t n, const tvs_histories *h, int on_d
     HIPCHK(hipSetDevice(ctx->cfg.device));
     hipStream_t st = pick(ctx, stream);
     HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->fill_stream));
     free_histories(ctx);
     reset_state(ctx);
     HIPCHK(hipMemsetAsync(ctx->x, 0, sizeof(double) * ctx->nvox, st));
     HIPCHK(hipMemsetAsync(ctx->x0, 0, sizeof(double) * ctx->nvox, st));
+    HIPCHK(hipMemsetAsync(ctx->flags, 0, sizeof(uint32_t) * kNumFlags, st));
     ctx->batch.valid = false;
     ctx->nh = n;
 
     int rc = dalloc(ctx, &ctx->hist, (size_t)(kNumStreams * n));
     if (!rc) rc = dalloc(ctx, &ctx->row_off, (size_t)(n + 1));
     if (!rc) rc = dalloc(ctx, &ctx->norm2, (size_t)n);
+    if (!rc) rc = dalloc(ctx, &ctx->seg_off, (size_t)(n + 1));
     if (rc) {
         free_histories(ctx);
         return rc;
@@ -812,12 +828,16 @@ int tvs_load_histories(tvs_ctx *ctx, int64_t n, const tvs_histories *h, int on_d
         }
     }
     // validation on the device (the inputs may live there already)
-    uint32_t bad = 0;
+    uint32_t bad = 0, jmax = 0;
     {
-        hipError_t e = hipMemsetAsync(ctx->ntouched + 5, 0, sizeof(uint32_t), st);
-        if (e == hipSuccess) e = tvs::launch_validate(hist_dev(ctx), n, ctx->mlp.step, ctx->ntouched + 5, st);
+        hipError_t e = tvs::launch_validate(hist_dev(ctx), n, ctx->mlp.step,
+                                            ctx->flags + kFlagInvalid, ctx->flags + kFlagJmax, st);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(&bad, ctx->ntouched + 5, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+            e = hipMemcpyAsync(&bad, ctx->flags + kFlagInvalid, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&jmax, ctx->flags + kFlagJmax, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
             free_histories(ctx);
@@ -826,75 +846,36 @@ int tvs_load_histories(tvs_ctx *ctx, int64_t n, const tvs_histories *h, int on_d
     }
     if (bad) {
         free_histories(ctx);
+        (void)hipMemsetAsync(ctx->flags, 0, sizeof(uint32_t) * kNumFlags, st);
         return fail(ctx, TVS_EINVAL,
                     std::to_string(bad) + " histories hold NaN/inf, |value| > 1e6, a zero beam "
                                           "axis or more than 2^20 MLP vertices");
     }
-    // row lengths of every history (one MLP pass); rows themselves are
-    // formed now for a path store, per chunk and sweep otherwise
-    rc = count_rows(ctx, 0, n, ctx->row_off, st);
-    if (rc) {
-        free_histories(ctx);
-        return rc;
-    }
-    std::vector<int64_t> off_h;
-    int64_t total = 0;
-    {
-        std::vector<int64_t> all((size_t)n + 1);
-        hipError_t e = hipMemcpy(all.data(), ctx->row_off, sizeof(int64_t) * (n + 1),
-                                 hipMemcpyDeviceToHost);
-        if (e != hipSuccess) {
+    // entry-side MLP table for every vertex depth of these histories
+    if (jmax > 0) {
+        rc = dalloc(ctx, &ctx->s1i, (size_t)(3 * (int64_t)jmax));
+        if (!rc) {
+            ctx->nj = jmax;
+            hipError_t e = tvs::launch_mlp_table(ctx->mlp, ctx->nj, ctx->s1i, st);
+            if (e != hipSuccess) rc = fail(ctx, TVS_EDEVICE, std::string("MLP table: ") + hipGetErrorString(e));
+            ctx->mlp.s1i = ctx->s1i;
+            ctx->mlp.nj = ctx->nj;
+            ctx->mlp.err = ctx->flags + kFlagLists;
+        }
+        if (rc) {
+            std::string msg = ctx->err;
             free_histories(ctx);
-            return fail(ctx, TVS_EDEVICE, std::string("row offsets: ") + hipGetErrorString(e));
+            return fail(ctx, rc, msg);
         }
-        total = all[(size_t)n];
-        int64_t mx = 0, sk = 0;
-        for (int64_t i = 0; i < n; i++) {
-            int64_t len = all[(size_t)i + 1] - all[(size_t)i];
-            mx = std::max(mx, len);
-            sk += (len == 0);
-        }
-        ctx->max_row = mx;
-        ctx->skipped = sk;
-        const int64_t B = ctx->cfg.block_size;
-        int64_t chunk = ctx->cfg.chunk_histories;
-        if (chunk <= 0) chunk = std::max<int64_t>(B, ((int64_t)1 << 20) / B * B);
-        else chunk = (chunk + B - 1) / B * B;
-        ctx->chunk = std::max<int64_t>(chunk, 1);
-        for (int64_t f = 0; f < n; f += ctx->chunk) ctx->chunk_base.push_back(all[(size_t)f]);
-        ctx->chunk_base.push_back(total);
     }
-    ctx->nnz = total;
-    int64_t cap = nnz_cap_of(ctx);
-    rc = dalloc(ctx, &ctx->idx, (size_t)cap);
-    if (!rc) {
-        if (ctx->cfg.path_mode == TVS_PATH_STORE_F16) rc = dalloc(ctx, &ctx->chord16, (size_t)cap);
-        else rc = dalloc(ctx, &ctx->chord32, (size_t)cap);
-    }
-    if (!rc && ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY && ctx->chunk_base.size() > 2) {
-        rc = dalloc(ctx, &ctx->idx2, (size_t)cap);
-        if (!rc) rc = dalloc(ctx, &ctx->chord32b, (size_t)cap);
-    }
+    // the tile lists of every block (their layout; rows themselves are
+    // formed now for a path store, per chunk and sweep otherwise)
+    rc = build_tile_lists(ctx, st);
+    if (!rc) rc = form_entries(ctx, st);
     if (rc) {
+        std::string msg = ctx->err;
         free_histories(ctx);
-        return rc;
-    }
-    if (ctx->cfg.path_mode != TVS_PATH_ON_THE_FLY && n > 0) {
-        RowSet rs = rowset(ctx, 0, n, 0);
-        hipError_t e = tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rs, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) {
-            free_histories(ctx);
-            return fail(ctx, TVS_EDEVICE, std::string("row fill: ") + hipGetErrorString(e));
-        }
-        if (ctx->cfg.block_size <= 65536 && ctx->cfg.sweep_kernel != 2) {
-            rc = build_csc(ctx, st);
-            if (rc) {
-                std::string msg = ctx->err;
-                free_histories(ctx);
-                return fail(ctx, rc, msg);
-            }
-        }
+        return fail(ctx, rc, msg);
     }
     ctx->loaded = true;
     ctx->timed = false;
@@ -917,6 +898,7 @@ int tvs_set_image(tvs_ctx *ctx, const float *x0, int on_device, void *stream)
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     HIPCHK(tvs::launch_widen(ctx->gd, ctx->xio, ctx->x, st));
     HIPCHK(hipMemcpyAsync(ctx->x0, ctx->x, sizeof(double) * ctx->nvox, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(ctx->flags + kFlagRange, 0, sizeof(uint32_t), st));
     if (!on_device) HIPCHK(hipStreamSynchronize(st));
     reset_state(ctx);
     ctx->batch.valid = false;
@@ -1002,16 +984,6 @@ int tvs_iterate(tvs_ctx *ctx, const tvs_params *p, int32_t K, void *stream)
         span(ctx, 1, c1, mark(ctx, st));
         ctx->k += 1;
     }
-    if (K > 0 && ctx->pgrid > 0) {
-        uint32_t flag = 0;
-        HIPCHK(hipMemcpyAsync(&flag, ctx->ntouched + 4, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (flag) {
-            HIPCHK(hipMemsetAsync(ctx->ntouched, 0, sizeof(uint32_t) * 5, st));
-            HIPCHK(hipStreamSynchronize(st));
-            return fail(ctx, TVS_EDEVICE, "sweep grid barrier timed out");
-        }
-    }
     return TVS_OK;
 }
 
@@ -1022,6 +994,8 @@ int tvs_get_image(tvs_ctx *ctx, float *out, int on_device, void *stream)
     if (!out) return fail(ctx, TVS_EINVAL, "output is NULL");
     HIPCHK(hipSetDevice(ctx->cfg.device));
     hipStream_t st = pick(ctx, stream);
+    int rc = check_flags(ctx, st);
+    if (rc) return rc;
     HIPCHK(tvs::launch_narrow(ctx->gd, ctx->x, ctx->xio, st));
     HIPCHK(hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nimg,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
@@ -1036,6 +1010,7 @@ int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out)
     HIPCHK(hipSetDevice(ctx->cfg.device));
     if (ctx->timed && !ctx->spans.empty()) {
         HIPCHK(hipEventSynchronize(ctx->tev[ctx->spans.back().b]));
+        HIPCHK(hipStreamSynchronize(ctx->fill_stream));
         for (int q = 0; q < 6; q++) {
             ctx->tot_ms[q] = 0.0;
             ctx->tot_n[q] = 0;
@@ -1062,6 +1037,8 @@ int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out)
         ctx->last_rows_ms = last[2];
         ctx->timed = false;
     }
+    int rc = check_flags(ctx, ctx->stream);
+    if (rc) return rc;
     out->k = ctx->k;
     out->ell = ctx->ell;
     out->n_hist = ctx->nh;
@@ -1149,7 +1126,7 @@ int tvs_debug_rows(tvs_ctx *ctx, int64_t first, int64_t count, int64_t *row_nnz,
             e = hipMemcpyAsync(idx, di, sizeof(int32_t) * tot, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e == hipSuccess) {
-            // brick-layout words to x-fastest voxel indices (the ABI's order)
+            // tiled-layout words to x-fastest voxel indices (the ABI's order)
             const GridDev &g = ctx->gd;
             for (int64_t q = 0; q < tot; q++) {
                 int64_t i, j, k;
@@ -1191,31 +1168,22 @@ int batch_init(tvs_ctx *ctx, const tvs_params *p, int S, hipStream_t st)
         const size_t n = (size_t)(ctx->nvox * S);
         int rc = dalloc(ctx, &B.b.x, n);
         if (!rc) rc = dalloc(ctx, &B.b.g, n);
-        if (!rc) rc = dalloc(ctx, &B.b.c, n);
         if (!rc) rc = dalloc(ctx, &B.b.part, (size_t)(tvs::batch_num_parts(ctx->gd, S) * S));
         if (!rc) rc = dalloc(ctx, &B.b.ticket, (size_t)4);
         if (!rc) rc = dalloc(ctx, &B.b.norm2, (size_t)S);
         if (!rc) rc = dalloc(ctx, &B.b.lambda, (size_t)S);
         if (!rc) rc = dalloc(ctx, &B.b.eps, (size_t)S);
         if (!rc) rc = dalloc(ctx, &B.b.cyc, (size_t)4);
-        if (!rc) rc = dalloc(ctx, &B.rbuf, (size_t)(ctx->cfg.block_size * S));
+        if (!rc) rc = dalloc(ctx, &B.dot, (size_t)(3 * (int64_t)ctx->cfg.block_size * S));
         if (rc) {
             free_batch(ctx);
             return rc;
         }
         B.b.S = S;
         B.b.nvox = ctx->nvox;
-        B.grid = tvs::batch_grid_size(ctx->cfg.device, S);
-        if (B.grid <= 0) {
-            free_batch(ctx);
-            return fail(ctx, TVS_EDEVICE, "no occupancy for the batched sweep");
-        }
         HIPCHK(hipMemsetAsync(B.b.ticket, 0, sizeof(uint32_t) * 4, st));
+        HIPCHK(hipMemsetAsync(B.b.g, 0, sizeof(double) * n, st));
     }
-    B.b.s = ctx->s;
-    B.b.touched = ctx->touched;
-    B.b.ntouched = ctx->ntouched;
-    B.b.barrier = ctx->ntouched + 2;
     B.p.assign(p, p + S);
     std::vector<double> lam(S), eps(S);
     for (int q = 0; q < S; q++) {
@@ -1234,43 +1202,48 @@ int batch_init(tvs_ctx *ctx, const tvs_params *p, int S, hipStream_t st)
     return TVS_OK;
 }
 
-// Enqueues the launches of one batched cycle (captured into a graph).
+// Enqueues the launches of one batched cycle (captured into a graph): the
+// TV steps of every setting, then the tile-wise DROP chain for all S
+// images; on-the-fly rows are formed chunk by chunk on the same stream
+// into alternating buffers.
 int batch_cycle(tvs_ctx *ctx, int nmax, hipStream_t st)
 {
-    auto &B = ctx->batch;
+    auto &Bt = ctx->batch;
+    const int S = Bt.S;
     for (int n = 0; n < nmax; n++) {
         uint32_t active = 0;
-        for (int q = 0; q < B.S; q++)
-            if (B.p[q].N > n) active |= 1u << q;
-        HIPCHK(tvs::launch_tvb_grad(ctx->gd, B.b, active, st));
-        HIPCHK(tvs::launch_tvb_step(B.b, active, n, nmax, st));
+        for (int q = 0; q < S; q++)
+            if (Bt.p[q].N > n) active |= 1u << q;
+        HIPCHK(tvs::launch_tvb_grad(ctx->gd, Bt.b, active, st));
+        HIPCHK(tvs::launch_tvb_step(Bt.b, active, n, nmax, st));
+    }
+    const int64_t B = ctx->cfg.block_size, nb = ctx->nblocks;
+    if (nb == 0) {
+        HIPCHK(tvs::launch_tick(Bt.b.cyc, st));
+        return TVS_OK;
     }
     const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
     const int64_t step = otf ? ctx->chunk : ctx->nh;
-    const float *wepl = ctx->hist + 12 * ctx->nh;
-    for (int64_t first = 0, q = 0; first < ctx->nh; first += step, q++) {
-        const int64_t n = std::min(step, ctx->nh - first);
-        RowSet rs = rowset(ctx, first, n, otf ? ctx->chunk_base[q] : 0);
-        if (otf) HIPCHK(tvs::launch_rows_fill(ctx->gd, hist_dev(ctx), ctx->mlp, rs, st));
-        if (ctx->csc) {
-            const int64_t Bs = ctx->cfg.block_size;
-            for (int64_t r0 = first, t = first / Bs; r0 < first + n; r0 += Bs, t++) {
-                const int64_t r1 = std::min(r0 + Bs, first + n);
-                tvs::CscBlock cb;
-                cb.uvox = ctx->uvox + ctx->blk_ubase[t];
-                cb.ucol = ctx->ucol + ctx->blk_ubase[t];
-                cb.U = ctx->blk_u[t];
-                cb.ne = ctx->blk_ne[t];
-                cb.cq = ctx->cq + ctx->blk_ebase[t];
-                if (ctx->cch16) cb.cch16 = ctx->cch16 + ctx->blk_ebase[t];
-                else cb.cch32 = ctx->cch32 + ctx->blk_ebase[t];
-                HIPCHK(tvs::launch_batch_block_csc(rs, wepl, r0, r1, cb, B.b, B.rbuf, st));
-            }
-        } else {
-            HIPCHK(tvs::launch_drop_batch(rs, wepl, ctx->cfg.block_size, B.b, B.grid, st));
+    HIPCHK(tvs::launch_zero_i64(Bt.dot, 3 * B * S, st));
+    for (int64_t b = 0; b <= nb; b++) {
+        const bool has_c = b < nb;
+        if (otf && has_c && (b * B) % step == 0) {
+            const int64_t c = (b * B) / step;
+            tvs::TileFill f = chunk_fill(ctx, c, std::min(step, ctx->nh - c * step));
+            HIPCHK(tvs::launch_rows_fill_tiled(ctx->gd, hist_dev(ctx), ctx->mlp, f, st));
         }
+        tvs::DropTileArgs A;
+        if (b > 0) A.P = block_view(ctx, b - 1, Bt.dot, B * S);
+        if (has_c) A.C = block_view(ctx, b, Bt.dot, B * S);
+        A.x = Bt.b.x;
+        A.big = ctx->big;
+        A.dot_max = ctx->dot_max;
+        A.zero = Bt.dot + ((b + 1) % 3) * B * S;
+        A.B = B;
+        A.err = ctx->flags + kFlagRange;
+        HIPCHK(tvs::launch_drop_tiles_batch(A, Bt.b, ctx->ntiles, st));
     }
-    HIPCHK(tvs::launch_tick(B.b.cyc, st));
+    HIPCHK(tvs::launch_tick(Bt.b.cyc, st));
     return TVS_OK;
 }
 
@@ -1294,6 +1267,9 @@ int tvs_iterate_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, int32_t K, v
     if (!ctx->loaded) return fail(ctx, TVS_ESTATE, "tvs_iterate_batch before tvs_load_histories");
     HIPCHK(hipSetDevice(ctx->cfg.device));
     hipStream_t st = pick(ctx, stream);
+    // the chunk buffers must be free of the single-image sweep's work
+    HIPCHK(hipStreamSynchronize(ctx->fill_stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     auto &B = ctx->batch;
     bool same = B.valid && B.S == S;
     for (int q = 0; same && q < S; q++) same = same_params(B.p[q], p[q]);
@@ -1350,6 +1326,9 @@ int tvs_iterate_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, int32_t K, v
         (void)hipGraphDestroy(graph);
         return fail(ctx, TVS_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ce));
     }
+    ctx->tev_used = 0;
+    ctx->spans.clear();
+    ctx->timed = false;
     std::vector<long> ev;
     ev.push_back(mark(ctx, st));
     for (int32_t kk = 0; kk < K && ce == hipSuccess; kk++) {
@@ -1369,15 +1348,6 @@ int tvs_iterate_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, int32_t K, v
     }
     B.cycles = K;
     ctx->tev_used = 0;
-    ctx->spans.clear();
-    ctx->timed = false;
-    uint32_t flag = 0;
-    HIPCHK(hipMemcpy(&flag, ctx->ntouched + 4, sizeof(uint32_t), hipMemcpyDeviceToHost));
-    if (flag) {
-        HIPCHK(hipMemset(ctx->ntouched, 0, sizeof(uint32_t) * 5));
-        B.valid = false;
-        return fail(ctx, TVS_EDEVICE, "batched sweep grid barrier timed out");
-    }
     return TVS_OK;
 }
 
@@ -1390,6 +1360,8 @@ int tvs_get_batch_image(tvs_ctx *ctx, int32_t s, float *out, int on_device, void
     if (s < 0 || s >= ctx->batch.S) return fail(ctx, TVS_ERANGE, "setting outside the batch");
     HIPCHK(hipSetDevice(ctx->cfg.device));
     hipStream_t st = pick(ctx, stream);
+    int rc = check_flags(ctx, st);
+    if (rc) return rc;
     HIPCHK(tvs::launch_extract(ctx->gd, ctx->batch.b, s, ctx->xio, st));
     HIPCHK(hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nimg,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
@@ -1418,12 +1390,12 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
             char line[1024];
             while (std::fgets(line, sizeof(line), f)) {
                 char k[512];
-                int l = 0, sw = 0;
+                int th = 0, sw = 0;
                 double ms = 0;
-                if (std::sscanf(line, "%511s %d %d %lf", k, &l, &sw, &ms) == 4 &&
-                    std::strcmp(k, key) == 0 && (l == 16 || l == 32 || l == 64) &&
+                if (std::sscanf(line, "%511s %d %d %lf", k, &th, &sw, &ms) == 4 &&
+                    std::strcmp(k, key) == 0 && (th == 64 || th == 128 || th == 256) &&
                     (sw == 1 || sw == 2)) {
-                    out->lanes_per_row = l;
+                    out->tile_threads = th;
                     out->sweep_kernel = sw;
                     out->ms_per_block = ms;
                     out->from_cache = 1;
@@ -1432,45 +1404,43 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
             std::fclose(f);
         }
         if (out->from_cache) {
-            ctx->lpr = out->lanes_per_row;
-            ctx->pgrid = (out->sweep_kernel == 2 && !ctx->csc)
-                             ? tvs::persistent_grid_size(ctx->cfg.device, ctx->lpr) : 0;
+            ctx->threads = out->tile_threads;
+            ctx->split = out->sweep_kernel == 2 ? 1 : 0;
             return TVS_OK;
         }
     }
     const int64_t B = ctx->cfg.block_size;
-    const int64_t T = (ctx->nh + B - 1) / B;
-    const int64_t nb = std::min<int64_t>(T, 48);
+    const int64_t nb = std::min<int64_t>(ctx->nblocks, 48);
     if (nb == 0) {
-        out->lanes_per_row = ctx->lpr;
-        out->sweep_kernel = ctx->pgrid > 0 ? 2 : 1;
+        out->tile_threads = ctx->threads;
+        out->sweep_kernel = ctx->split ? 2 : 1;
         return TVS_OK;
     }
+    HIPCHK(hipStreamSynchronize(ctx->fill_stream));
     double *saved = nullptr;
     int rc = dalloc(ctx, &saved, (size_t)ctx->nvox);
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(saved, ctx->x, sizeof(double) * ctx->nvox, hipMemcpyDeviceToDevice, st));
-    const int lprs[3] = {16, 32, 64};
-    const int old_lpr = ctx->lpr, old_pgrid = ctx->pgrid;
+    const int ths[3] = {64, 128, 256};
+    const int old_threads = ctx->threads, old_split = ctx->split;
     double best = 1e300;
     int nc = 0;
     for (int sw = 1; sw <= 2 && rc == TVS_OK; sw++) {
-        if (sw == 2 && ctx->csc) break;   // path stores use the voxel-major launches
-        for (int li = 0; li < 3 && rc == TVS_OK; li++) {
-            ctx->lpr = lprs[li];
-            ctx->pgrid = (sw == 2) ? tvs::persistent_grid_size(ctx->cfg.device, ctx->lpr) : 0;
-            if (sw == 2 && ctx->pgrid <= 0) continue;
+        for (int ti = 0; ti < 3 && rc == TVS_OK; ti++) {
+            ctx->threads = ths[ti];
+            ctx->split = sw == 2 ? 1 : 0;
             double tbest = 1e300;
             for (int rep = 0; rep < 3 && rc == TVS_OK; rep++) {
                 ctx->tev_used = 0;
                 ctx->spans.clear();
                 long a = mark(ctx, st);
-                rc = run_sweep(ctx, lambda, st, nb * B);
+                rc = run_sweep(ctx, lambda, st, std::min(nb * B, ctx->nh));
                 long b = mark(ctx, st);
                 if (rc) break;
                 hipError_t e = hipMemcpyAsync(ctx->x, saved, sizeof(double) * ctx->nvox,
                                               hipMemcpyDeviceToDevice, st);
                 if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (e == hipSuccess) e = hipStreamSynchronize(ctx->fill_stream);
                 float ms = 0;
                 if (e == hipSuccess && a >= 0 && b >= 0)
                     e = hipEventElapsedTime(&ms, ctx->tev[(size_t)a], ctx->tev[(size_t)b]);
@@ -1482,14 +1452,14 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
             }
             if (rc) break;
             if (nc < 8) {
-                out->cand_lanes[nc] = lprs[li];
+                out->cand_threads[nc] = ths[ti];
                 out->cand_sweep[nc] = sw;
                 out->cand_ms[nc] = tbest;
                 nc++;
             }
             if (tbest < best) {
                 best = tbest;
-                out->lanes_per_row = lprs[li];
+                out->tile_threads = ths[ti];
                 out->sweep_kernel = sw;
                 out->ms_per_block = tbest;
             }
@@ -1501,15 +1471,15 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
     ctx->timed = false;
     out->n_candidates = nc;
     if (rc || best == 1e300) {
-        ctx->lpr = old_lpr;
-        ctx->pgrid = old_pgrid;
+        ctx->threads = old_threads;
+        ctx->split = old_split;
         return rc ? rc : fail(ctx, TVS_EDEVICE, "autotune: no candidate ran");
     }
-    ctx->lpr = out->lanes_per_row;
-    ctx->pgrid = (out->sweep_kernel == 2) ? tvs::persistent_grid_size(ctx->cfg.device, ctx->lpr) : 0;
+    ctx->threads = out->tile_threads;
+    ctx->split = out->sweep_kernel == 2 ? 1 : 0;
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %.6f\n", key, out->lanes_per_row, out->sweep_kernel,
+            std::fprintf(f, "%s %d %d %.6f\n", key, out->tile_threads, out->sweep_kernel,
                          out->ms_per_block);
             std::fclose(f);
         }

@@ -1,6 +1,6 @@
 // tvs_internal.hpp -- internal declarations of the MI355X TVS library: the
-// context, device-side parameter blocks and the kernel launchers.  Nothing
-// here is part of the public ABI (include/tvs.h).
+// device-side parameter blocks and the kernel launchers.  Nothing here is
+// part of the public ABI (include/tvs.h).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,50 +15,60 @@
 namespace tvs {
 
 // Voxel grid as the kernels see it.  Every device image (and every voxel
-// index a row holds) uses the brick layout below; images cross the ABI in
+// index a row holds) uses the tiled layout below; images cross the ABI in
 // plain x-fastest order and are converted on the way in and out.
 struct GridDev {
     int32_t nx, ny, nz;
     double vx, vy, vz;
     double ox, oy, oz;
-    int32_t nbx, nby;         // bricks per slice along x and y
+    int32_t ntx, nty;         // tiles per slice along x and y
 };
 
-// Brick layout: each slice is tiled by 4 x 2 (x, y) bricks of 8 float64
-// words, one 64-byte line, bricks x-fastest, slices outermost.  A proton
-// path crosses a brick in a few consecutive entries, so the entries a
-// wavefront gathers or scatters at once touch about a third fewer lines
-// than in x-fastest order (atomics are priced per line).  Voxels past nx / ny
-// in the last brick column / row are padding: never indexed by a row, zero
-// in every image and subgradient.
-constexpr int kBrickX = 4, kBrickY = 2, kBrick = kBrickX * kBrickY;
+// Tiled layout.  Each slice is cut into 16 x 16 voxel tiles of 256
+// consecutive float64 words (tiles x-fastest, then y, slices outermost);
+// inside a tile, 4 x 2 (x, y) bricks of 8 words (one 64-byte line), bricks
+// x-fastest.  A DROP block is processed tile by tile: one workgroup holds a
+// tile's 256 voxels in LDS, so the block's corrections never leave the CU.
+// Voxels past nx / ny in the last tile column / row are padding: never
+// indexed by a row, zero in every image and subgradient.
+constexpr int kTileShift = 8, kTileWords = 1 << kTileShift, kTileSide = 16;
 
 __host__ __device__ inline int64_t vaddr(const GridDev &g, int64_t i, int64_t j, int64_t k)
 {
-    return (((k * g.nby + (j >> 1)) * g.nbx + (i >> 2)) << 3) + ((j & 1) << 2) + (i & 3);
+    const int64_t tile = (k * g.nty + (j >> 4)) * g.ntx + (i >> 4);
+    const int64_t in = ((((j & 15) >> 1) << 2 | ((i & 15) >> 2)) << 3) | ((j & 1) << 2) | (i & 3);
+    return (tile << kTileShift) | in;
 }
 
-// Inverse of vaddr: voxel coordinates of brick-layout word a.
+// Inverse of vaddr: voxel coordinates of tiled-layout word a.
 __host__ __device__ inline void vcoord(const GridDev &g, int64_t a, int64_t &i, int64_t &j,
                                        int64_t &k)
 {
-    const int64_t b = a >> 3, w = a & 7;
-    const int64_t t = b / g.nbx;
-    i = (b - t * g.nbx) * kBrickX + (w & 3);
-    k = t / g.nby;
-    j = (t - k * g.nby) * kBrickY + (w >> 2);
+    const int64_t tile = a >> kTileShift, in = a & (kTileWords - 1);
+    const int64_t brick = in >> 3, w = in & 7;
+    const int64_t t2 = tile / g.ntx;
+    const int64_t tx = tile - t2 * g.ntx;
+    k = t2 / g.nty;
+    const int64_t ty = t2 - k * g.nty;
+    i = tx * kTileSide + (brick & 3) * 4 + (w & 3);
+    j = ty * kTileSide + (brick >> 2) * 2 + (w >> 2);
+}
+
+__host__ __device__ inline int64_t num_tiles(const GridDev &g)
+{
+    return (int64_t)g.ntx * g.nty * g.nz;
 }
 
 // Words of a device image (padding included).
 __host__ __device__ inline int64_t padded_voxels(const GridDev &g)
 {
-    return (int64_t)g.nbx * g.nby * kBrick * g.nz;
+    return num_tiles(g) << kTileShift;
 }
 
 inline GridDev make_grid_dev(const tvs_grid &g)
 {
     return GridDev{g.nx, g.ny, g.nz, g.vx, g.vy, g.vz, g.ox, g.oy, g.oz,
-                   (g.nx + kBrickX - 1) / kBrickX, (g.ny + kBrickY - 1) / kBrickY};
+                   (g.nx + kTileSide - 1) / kTileSide, (g.ny + kTileSide - 1) / kTileSide};
 }
 
 // SoA history streams on the device (13 float32 arrays of length n_hist).
@@ -70,106 +80,125 @@ struct MlpCfg {
     double step;
     int32_t log_term;
     int32_t const_power;
+    const double *s1i = nullptr;   // entry-side table: (Sigma_1(j * step))^-1 as {a, b, d}
+    int64_t nj = 0;                // depths j < nj in the table
+    uint32_t *err = nullptr;       // raised by a depth past the table
 };
 
-// Rows of a contiguous range of histories [first, first + n): CSR with
-// offsets relative to the start of this row set.
+// Row-major rows of histories [first, first + n) (debug copies of rows):
+// CSR with offsets relative to the start of this row set.
 struct RowSet {
     int64_t first = 0;        // global index of the first history
     int64_t n = 0;            // histories in the set
-    int64_t nnz = 0;          // entries
     int64_t base = 0;         // entries of row q start at row_off[q] - base
     int64_t *row_off = nullptr;   // n + 1 offsets
-    int32_t *idx = nullptr;       // voxel indices
-    float *chord32 = nullptr;     // chords (float32) or
-    __half *chord16 = nullptr;    // chords (float16)
+    int32_t *idx = nullptr;       // voxel indices (x-fastest order after the copy-out)
+    float *chord32 = nullptr;     // chords (float32)
     float *norm2 = nullptr;       // ||a_i||^2 per history (0: the history forms no row)
 };
 
-// ----------------------------------------------------------------- rows.hip
-// Forms the rows of histories [first, first + n) in two passes.  Pass 1
-// writes nnz[i] (int32); after an exclusive scan into row_off, pass 2 fills
-// idx / chord / norm2.  All launches are asynchronous on `stream`.
-hipError_t launch_rows_count(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t first,
-                             int64_t n, int32_t *nnz, hipStream_t stream);
-hipError_t launch_rows_fill(const GridDev &g, const HistDev &h, const MlpCfg &m, const RowSet &rs,
-                            hipStream_t stream);
-// Exclusive scan of n int32 counts into n+1 int64 offsets (off[n] = total).
-// `tmp` needs scan_tmp_elems(n) int64 elements.
-int64_t scan_tmp_elems(int64_t n);
-// Counts histories with non-finite values, a degenerate beam axis,
-// coordinates beyond 1e6 mm or more than 2^20 MLP vertices into *bad.
-hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *bad,
-                           hipStream_t stream);
-hipError_t launch_scan(const int32_t *cnt, int64_t n, int64_t *off, int64_t *tmp,
-                       hipStream_t stream);
-
-// ----------------------------------------------------------------- drop.hip
-struct DropBuffers {
-    double *x;           // image (float64: keeps the small DROP increments exact
-                         // enough for the scale-free TV subgradient)
-    double *c;           // correction sums (float64, like the image)
-    uint32_t *s;         // hit counts
-    int32_t *touched;    // voxels touched by the current block (capacity nvox)
-    uint32_t *ntouched;  // two counters used alternately by consecutive blocks
-    uint32_t *barrier;   // persistent sweep: grid barrier counter + error flag
-    int64_t nvox;
-    double *c64 = nullptr;   // non-null: packed per-block scatter (c holds the packed words,
-                             // c64 the float64 part of large contributions)
-    uint32_t *omask = nullptr;  // one bit per voxel: the float64 part is non-zero
-    double big = 0.0;        // largest contribution taken in fixed point
+// Tile lists.  The entries of DROP block b (rows bB .. bB+B-1) are kept
+// grouped by image tile: list (b, T) holds, for every row of the block that
+// crosses tile T, its entries inside T, each as
+//   meta  = (word within the tile) | (row within the block) << 8,
+//   chord = float32 or float16.
+// A row's entries inside one tile form a segment (a run of consecutive
+// entries of its walk); the place of every segment in its list is fixed
+// once, when the histories are loaded, so rows formed again on every sweep
+// land where the sweep expects them.
+struct TileFill {
+    int64_t first = 0, n = 0;       // histories [first, first + n)
+    int64_t B = 1;                  // block size
+    const int64_t *seg_off = nullptr;   // per history: first segment (global)
+    const int64_t *segdst = nullptr;    // per segment: global entry index of its first entry
+    int64_t base = 0;               // global entry index of meta[0] / chord[0]
+    uint32_t *meta = nullptr;
+    float *ch32 = nullptr;
+    __half *ch16 = nullptr;
+    int64_t cap = 0;                // entries meta / chord can hold
+    float *norm2 = nullptr;         // per history (global index)
+    uint32_t *err = nullptr;        // raised if a walk disagrees with the load-time lists
 };
 
-// Start/stop events of the two kernels of one block (the rows kernel, then
-// the apply kernel); null events are not recorded.
+// ----------------------------------------------------------------- rows.hip
+// Load-time passes over every history (all asynchronous on `stream`):
+//   count : nnz[i] entries and nseg[i] segments of row i;
+//   seg   : reserves each segment's place in its (block, tile) list with an
+//           atomic on btc[b * ntiles + T] and records (T, place) in segtab;
+//   dest  : turns (T, place) into the segment's global entry index, given
+//           the exclusive scan bt_off of btc.
+// A walk that disagrees with the count pass writes nothing and raises *err.
+hipError_t launch_rows_count(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t first,
+                             int64_t n, int32_t *nnz, int32_t *nseg, hipStream_t stream);
+hipError_t launch_rows_seg(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t n,
+                           int64_t B, const int64_t *seg_off, uint32_t *btc, uint64_t *segtab,
+                           uint32_t *err, hipStream_t stream);
+hipError_t launch_seg_dest(const GridDev &g, int64_t n, int64_t B, const int64_t *seg_off,
+                           const int64_t *bt_off, uint64_t *segtab, uint32_t *err,
+                           hipStream_t stream);
+// Forms the rows of f.first .. f.first + f.n - 1 into their tile lists.
+hipError_t launch_rows_fill_tiled(const GridDev &g, const HistDev &h, const MlpCfg &m,
+                                  const TileFill &f, hipStream_t stream);
+// Forms rows in row-major order (for tvs_debug_rows).
+hipError_t launch_rows_fill(const GridDev &g, const HistDev &h, const MlpCfg &m, const RowSet &rs,
+                            hipStream_t stream);
+// Exclusive scan of n int32 (or uint32) counts into n+1 int64 offsets
+// (off[n] = total).  `tmp` needs scan_tmp_elems(n) int64 elements.
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_scan(const int32_t *cnt, int64_t n, int64_t *off, int64_t *tmp,
+                       hipStream_t stream);
+// Counts histories with non-finite values, a degenerate beam axis,
+// coordinates beyond 1e6 mm or more than 2^20 MLP vertices into *bad, and
+// raises *jmax to at least every valid history's vertex count + 2.
+hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *bad,
+                           uint32_t *jmax, hipStream_t stream);
+// Fills the entry-side table of m for depths j = 0 .. nj - 1 (3 doubles each).
+hipError_t launch_mlp_table(const MlpCfg &m, int64_t nj, double *tab, hipStream_t stream);
+
+// ----------------------------------------------------------------- drop.hip
+// One DROP block's tile lists as a kernel sees them.
+struct TileBlock {
+    const uint32_t *meta = nullptr;   // entry e (global index) at meta[e - base]
+    const float *ch32 = nullptr;
+    const __half *ch16 = nullptr;
+    const int64_t *toff = nullptr;    // ntiles + 1 list starts (global entry index)
+    int64_t base = 0;
+    const float *wepl = nullptr;      // per row of the block
+    const float *n2 = nullptr;        // ||a_i||^2 per row of the block
+    long long *dot = nullptr;         // fixed-point row dot products (x S for batches)
+    uint32_t rows = 0;                // rows of the block; an entry naming another raises err
+    int valid = 0;
+};
+
+// Fixed-point units: row dot products are summed as integers in units of
+// 2^-36 (exact and order-free), block corrections in units of 2^-40.
+constexpr double kDotScale = 68719476736.0;          // 2^36
+constexpr double kCorrScale = 1099511627776.0;       // 2^40
+
+struct DropTileArgs {
+    TileBlock P;            // block b - 1: its update is finished on every tile
+    TileBlock C;            // block b: partial dot products of its rows per tile
+    double *x = nullptr;    // image (tiled layout, float64)
+    double lambda = 0.0;
+    double big = 0.0;       // |r a| above this is summed in float64 (keeps the fixed sum in range)
+    double dot_max = 0.0;   // |a x| above this cannot be summed in fixed point: error flag
+    long long *zero = nullptr;  // dot accumulators to clear for block b + 1
+    int64_t B = 0;
+    uint32_t *err = nullptr;
+};
+
+// Start/stop events of the kernels of one block (first and second launch);
+// null events are not recorded.
 struct KTimer {
     hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
-// One DROP block [r0, r1) (global history indices inside rs) with the
-// one-launch-per-phase kernels; `parity` selects the touched counter.
-// `kt` (may be null) times the block's two kernels.
-hipError_t launch_drop_block(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
-                             double lambda, const DropBuffers &b, int parity, int lanes_per_row,
+// One step of the tile-wise DROP chain: finish block b - 1 and form the dot
+// products of block b (either may be absent) on every tile.  threads: 64,
+// 128 or 256 per tile workgroup; split: 0 one fused launch, 1 two launches.
+hipError_t launch_drop_tiles(const DropTileArgs &a, int64_t ntiles, int threads, int split,
                              hipStream_t stream, const KTimer *kt = nullptr);
-// All blocks of rs in one persistent launch with grid barriers.
-hipError_t launch_drop_persistent(const RowSet &rs, const float *wepl, int64_t block_size,
-                                  double lambda, const DropBuffers &b, int lanes_per_row,
-                                  int grid_wgs, hipStream_t stream);
-int persistent_grid_size(int device, int lanes_per_row);
-// Clears both touched-list counters.
-hipError_t launch_zero_counters(uint32_t *cnt, hipStream_t stream);
-
-// Voxel-major form of one DROP block (csc.hip): distinct voxels uvox[0..U),
-// their column starts ucol (relative to the block's first entry), and the
-// block's ne column entries (row within the block, chord).
-struct CscBlock {
-    const int32_t *uvox = nullptr;
-    const uint32_t *ucol = nullptr;
-    int64_t U = 0, ne = 0;
-    const uint16_t *cq = nullptr;
-    const float *cch32 = nullptr;
-    const __half *cch16 = nullptr;
-};
-// Residual launch + voxel-major apply launch of one block (no atomics).
-hipError_t launch_drop_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
-                                 double lambda, const CscBlock &cb, double *x, double *rbuf,
-                                 int lanes_per_row, hipStream_t stream, const KTimer *kt = nullptr);
-// Build steps of the voxel-major form for a batch of nb blocks from b0.
-hipError_t csc_count(const RowSet &rs, int64_t r0, int64_t r1, int64_t block_size, int64_t b0,
-                     int64_t nvox, uint32_t *cnt, hipStream_t st);
-hipError_t csc_pick(const int64_t *src, int64_t stride, int64_t n, int64_t *dst, hipStream_t st);
-hipError_t csc_flags(const uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t st);
-hipError_t csc_as_int(const uint32_t *cnt, int64_t n, int32_t *out, hipStream_t st);
-hipError_t csc_emit(uint32_t *cnt, const int64_t *urank, const int64_t *cstart, int64_t nb,
-                    int64_t nvox, const int64_t *ubase, const int64_t *ebase, int32_t *uvox,
-                    uint32_t *ucol, hipStream_t st);
-hipError_t csc_place(const RowSet &rs, int64_t r0, int64_t r1, int64_t block_size, int64_t b0,
-                     int64_t nvox, uint32_t *cursor, const int64_t *ebase, uint16_t *cq,
-                     float *cch32, __half *cch16, hipStream_t st);
-hipError_t csc_sort(const uint32_t *ucol, const int64_t *ubase, const int64_t *ucount,
-                    const int64_t *ebase, const int64_t *ecount, int64_t nb, int64_t max_u,
-                    uint16_t *cq, float *cch32, __half *cch16, hipStream_t st);
+hipError_t launch_zero_i64(long long *p, int64_t n, hipStream_t stream);
 
 // ----------------------------------------------------------------- tv.hip
 struct TvBuffers {
@@ -191,25 +220,18 @@ hipError_t launch_tv_step(const GridDev &g, double *x, double beta, const TvBuff
 // (beta = 0: TV(x)).
 hipError_t launch_tv_phi(const GridDev &g, const double *x, double beta, double eps,
                          const TvBuffers &t, hipStream_t stream);
-// Image conversions between the float32 ABI and the float64 device image.
 // Image conversion between the ABI's x-fastest float32 and the device's
-// float64 brick layout (the padding of dst is left untouched by widen).
+// float64 tiled layout (the padding of dst is left untouched by widen).
 hipError_t launch_widen(const GridDev &g, const float *src, double *dst, hipStream_t stream);
 hipError_t launch_narrow(const GridDev &g, const double *src, float *dst, hipStream_t stream);
-hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream);
 
 // ----------------------------------------------------------------- batch.hip
-// S images interleaved by voxel (x[p*S + s]); hit counts and the touched list
-// are shared by all settings.
+// S images interleaved by voxel (x[p*S + s]).
 struct BatchBuffers {
     int S = 0;
     int64_t nvox = 0;
     double *x = nullptr;        // nvox * S
     double *g = nullptr;        // nvox * S
-    double *c = nullptr;        // nvox * S
-    uint32_t *s = nullptr;      // nvox (shared)
-    int32_t *touched = nullptr; // nvox (shared)
-    uint32_t *ntouched = nullptr, *barrier = nullptr;
     double *part = nullptr;     // batch_num_parts * S
     uint32_t *ticket = nullptr;
     double *norm2 = nullptr;    // S
@@ -220,7 +242,6 @@ struct BatchBuffers {
 };
 int batch_vox_per_wg(int S);
 int64_t batch_num_parts(const GridDev &g, int S);
-int batch_grid_size(int device, int S);
 hipError_t launch_tvb_grad(const GridDev &g, const BatchBuffers &b, uint32_t active,
                            hipStream_t stream);
 hipError_t launch_tvb_step(const BatchBuffers &b, uint32_t active, int n, int nmax,
@@ -230,12 +251,10 @@ hipError_t launch_tick(int32_t *cyc, hipStream_t stream);
 hipError_t launch_replicate(const double *x0, const BatchBuffers &b, hipStream_t stream);
 hipError_t launch_extract(const GridDev &g, const BatchBuffers &b, int s, float *out,
                           hipStream_t stream);
-hipError_t launch_drop_batch(const RowSet &rs, const float *wepl, int64_t block_size,
-                             const BatchBuffers &b, int grid_wgs, hipStream_t stream);
-// Voxel-major block of a batch: S residuals per row into rbuf (B*S), then S
-// corrections per distinct voxel.
-hipError_t launch_batch_block_csc(const RowSet &rs, const float *wepl, int64_t r0, int64_t r1,
-                                  const CscBlock &cb, const BatchBuffers &b, double *rbuf,
-                                  hipStream_t stream);
+// The tile-wise DROP step for S settings at once (dot arrays hold B x S
+// values, row-major by row; a.lambda is unused, the per-setting relaxations
+// come from b.lambda).
+hipError_t launch_drop_tiles_batch(const DropTileArgs &a, const BatchBuffers &b, int64_t ntiles,
+                                   hipStream_t stream);
 
 }  // namespace tvs

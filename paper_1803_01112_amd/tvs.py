@@ -46,7 +46,7 @@ class Config(C.Structure):
                 ("mlp_log_term", C.c_int32), ("mlp_const_power", C.c_int32),
                 ("chunk_histories", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
                 ("device", C.c_int32), ("max_tries", C.c_int32), ("sweep_kernel", C.c_int32),
-                ("wave_rows", C.c_int32), ("time_sample", C.c_int32)]
+                ("tile_threads", C.c_int32), ("time_sample", C.c_int32)]
 
 
 _FP = C.POINTER(C.c_float)
@@ -83,9 +83,9 @@ class StepLog(C.Structure):
 
 
 class TuneResult(C.Structure):
-    _fields_ = [("lanes_per_row", C.c_int32), ("sweep_kernel", C.c_int32),
+    _fields_ = [("tile_threads", C.c_int32), ("sweep_kernel", C.c_int32),
                 ("ms_per_block", C.c_double), ("from_cache", C.c_int32),
-                ("n_candidates", C.c_int32), ("cand_lanes", C.c_int32 * 8),
+                ("n_candidates", C.c_int32), ("cand_threads", C.c_int32 * 8),
                 ("cand_sweep", C.c_int32 * 8), ("cand_ms", C.c_double * 8)]
 
 
@@ -209,7 +209,7 @@ class Context:
 
     def __init__(self, grid, *, block_size=3200, path_mode="otf", mlp_step_mm=0.0,
                  mlp_log_term=True, mlp_const_power=False, chunk_histories=0,
-                 hbm_budget_bytes=0, device=0, max_tries=0, sweep_kernel=0, wave_rows=0,
+                 hbm_budget_bytes=0, device=0, max_tries=0, sweep_kernel=0, tile_threads=0,
                  time_sample=0):
         self._L = load_library()
         self.grid = grid
@@ -225,7 +225,7 @@ class Context:
         cfg.device = int(device)
         cfg.max_tries = int(max_tries)
         cfg.sweep_kernel = int(sweep_kernel)
-        cfg.wave_rows = int(wave_rows)
+        cfg.tile_threads = int(tile_threads)
         cfg.time_sample = int(time_sample)
         self.cfg = cfg
         h = C.c_void_p()
@@ -312,9 +312,9 @@ class Context:
         self._check(self._L.tvs_autotune(self._h, float(lam), cp, C.byref(r),
                                          _stream_handle(stream)), "tvs_autotune")
         n = r.n_candidates
-        return dict(lanes_per_row=r.lanes_per_row, sweep_kernel=r.sweep_kernel,
+        return dict(tile_threads=r.tile_threads, sweep_kernel=r.sweep_kernel,
                     ms_per_block=r.ms_per_block, from_cache=bool(r.from_cache),
-                    candidates=[dict(lanes=r.cand_lanes[q], sweep=r.cand_sweep[q],
+                    candidates=[dict(threads=r.cand_threads[q], sweep=r.cand_sweep[q],
                                      ms=r.cand_ms[q]) for q in range(n)])
 
     def get_batch_image(self, s, out=None, stream=None):

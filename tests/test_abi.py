@@ -69,7 +69,7 @@ def test_create_rejects_bad_arguments_before_touching_the_device(lib):
     bad.path_mode = 7
     assert lib.tvs_create(C.byref(g), C.byref(bad), C.byref(out)) == tvs.TVS_EINVAL
     bad = tvs.default_config()
-    bad.wave_rows = 48
+    bad.tile_threads = 48
     assert lib.tvs_create(C.byref(g), C.byref(bad), C.byref(out)) == tvs.TVS_EINVAL
     assert out.value is None
     assert lib.tvs_create(C.byref(g), C.byref(cfg), None) == tvs.TVS_EINVAL

@@ -28,11 +28,11 @@ def test_autotune_keeps_image_and_parity(tmp_path, path_mode):
         ctx.set_image(x0)
         r = ctx.autotune(0.05, cache)
         assert not r["from_cache"] and r["candidates"]
-        assert (r["lanes_per_row"], r["sweep_kernel"]) in {(c["lanes"], c["sweep"])
+        assert (r["tile_threads"], r["sweep_kernel"]) in {(c["threads"], c["sweep"])
                                                            for c in r["candidates"]}
         np.testing.assert_array_equal(ctx.get_image(), x0)
         r2 = ctx.autotune(0.05, cache)
-        assert r2["from_cache"] and r2["lanes_per_row"] == r["lanes_per_row"]
+        assert r2["from_cache"] and r2["tile_threads"] == r["tile_threads"]
         ctx.iterate(2, 0.05, 3, 0.75, seed=5)
         x = ctx.get_image()
     rows = oracle.build_rows(w.grid, h, 2.0)
