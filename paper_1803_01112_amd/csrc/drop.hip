@@ -57,34 +57,77 @@ struct TileLds {
     uint32_t hits[kTileWords];
 };
 
-// Finishes block P on this tile: x (LDS and global) updated in place.
-template <int NT, typename CH>
-__device__ void tile_finish(const TileBlock &P, int64_t p0, int64_t p1, TileLds &L, double *xt,
-                            double lambda, double big, uint32_t *err)
+// One list entry as loaded: tag (word | row << 8), chord, and whether the
+// index lay inside the list.
+struct Ent {
+    uint32_t m = 0u;
+    float a = 0.0f;
+    bool ok = false;
+};
+
+template <typename CH>
+__device__ inline Ent load_ent(const TileBlock &B, int64_t e, int64_t end)
 {
-    const CH *ch = chords<CH>(P);
-    for (int w = threadIdx.x; w < kTileWords; w += NT) {
-        L.hits[w] = 0u;
-        L.cf[w] = 0;
-        L.cb[w] = 0.0;
+    Ent r;
+    if (e < end) {
+        r.m = B.meta[e - B.base];
+        r.a = chord_at(chords<CH>(B), e - B.base);
+        r.ok = true;
     }
-    __syncthreads();
-    for (int64_t e = p0 + threadIdx.x; e < p1; e += NT) {
-        const uint32_t m = P.meta[e - P.base];
-        const int w = (int)(m & (kTileWords - 1));
-        const uint32_t q = m >> kTileShift;
-        if (q >= P.rows) {
-            atomicOr(err, 2u);
-            continue;
-        }
-        const double r = ((double)P.wepl[q] - (double)P.dot[q] * kDotUnit) / (double)P.n2[q];
-        const double v = r * (double)chord_at(ch, e - P.base);
-        atomicAdd(&L.hits[w], 1u);
-        if (fabs(v) <= big)
-            atomicAdd(reinterpret_cast<unsigned long long *>(&L.cf[w]),
-                      (unsigned long long)__double2ll_rn(v * kCorrScale));
-        else
-            atomicAdd(&L.cb[w], v);
+    return r;
+}
+
+// Row data an entry of the finished block needs: its row's WEPL, ||a||^2
+// and dot product (complete since the previous launch).
+struct RowData {
+    double wepl = 0.0, n2 = 1.0, dot = 0.0;
+};
+
+__device__ inline RowData load_row(const TileBlock &P, const Ent &en)
+{
+    RowData d;
+    const uint32_t q = en.m >> kTileShift;
+    if (en.ok && q < P.rows) {
+        d.wepl = (double)P.wepl[q];
+        d.n2 = (double)P.n2[q];
+        d.dot = (double)P.dot[q] * kDotUnit;
+    }
+    return d;
+}
+
+// Adds one entry of the finished block to the tile's LDS sums.
+__device__ inline void finish_one(const TileBlock &P, const Ent &en, const RowData &d, TileLds &L,
+                                  double big, uint32_t *err)
+{
+    if (!en.ok) return;
+    const uint32_t q = en.m >> kTileShift;
+    if (q >= P.rows) {
+        atomicOr(err, 2u);
+        return;
+    }
+    const int w = (int)(en.m & (kTileWords - 1));
+    const double r = (d.wepl - d.dot) / d.n2;
+    const double v = r * (double)en.a;
+    atomicAdd(&L.hits[w], 1u);
+    if (fabs(v) <= big)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&L.cf[w]),
+                  (unsigned long long)__double2ll_rn(v * kCorrScale));
+    else
+        atomicAdd(&L.cb[w], v);
+}
+
+// Finishes block P on this tile (x in LDS and global updated in place).  The
+// first round of entries (e0, with its row data d0) was loaded by the caller
+// together with the tile; the LDS sums are already cleared.
+template <int NT, typename CH>
+__device__ void tile_finish(const TileBlock &P, int64_t p0, int64_t p1, const Ent &e0,
+                            const RowData &d0, TileLds &L, double *xt, double lambda, double big,
+                            uint32_t *err)
+{
+    finish_one(P, e0, d0, L, big, err);
+    for (int64_t e = p0 + NT + threadIdx.x; e < p1; e += NT) {
+        const Ent en = load_ent<CH>(P, e, p1);
+        finish_one(P, en, load_row(P, en), L, big, err);
     }
     __syncthreads();
     for (int w = threadIdx.x; w < kTileWords; w += NT) {
@@ -99,21 +142,31 @@ __device__ void tile_finish(const TileBlock &P, int64_t p0, int64_t p1, TileLds 
     __syncthreads();
 }
 
-// Partial dot products of block C's rows on this tile, from x in LDS.
+// Partial dot products of block C's rows on this tile, from x in LDS; e0 is
+// the first round of entries, loaded by the caller.
 template <int NT, typename CH>
-__device__ void tile_dots(const TileBlock &C, int64_t c0, int64_t c1, const TileLds &L,
-                          double dot_max, uint32_t *err)
+__device__ void tile_dots(const TileBlock &C, int64_t c0, int64_t c1, const Ent &e0,
+                          const TileLds &L, double dot_max, uint32_t *err)
 {
-    const CH *ch = chords<CH>(C);
     // every thread runs the same number of rounds (the shuffles are uniform)
+    const CH *ch = chords<CH>(C);
+    uint32_t m = e0.m;
+    float a = e0.a;
+    bool ok = e0.ok;
     for (int64_t r0 = c0; r0 < c1; r0 += NT) {
-        const int64_t e = r0 + threadIdx.x;
+        if (r0 != c0) {
+            const int64_t e = r0 + threadIdx.x;
+            ok = e < c1;
+            if (ok) {
+                m = C.meta[e - C.base];
+                a = chord_at(ch, e - C.base);
+            }
+        }
         uint32_t q = kNoRow;
         long long f = 0;
-        if (e < c1) {
-            const uint32_t m = C.meta[e - C.base];
+        if (ok) {
             q = m >> kTileShift;
-            const double p = (double)chord_at(ch, e - C.base) * L.x[m & (kTileWords - 1)];
+            const double p = (double)a * L.x[m & (kTileWords - 1)];
             if (q >= C.rows) {
                 atomicOr(err, 2u);
                 q = kNoRow;
@@ -146,22 +199,47 @@ __device__ inline void list_range(const TileBlock &t, int64_t T, int64_t &a, int
     }
 }
 
-// Fused step: finish block P, then the dot products of block C.
+// Loads the tile into LDS and clears the finish sums (with fin); the caller
+// has issued its other first-round loads before, so they overlap.
+template <int NT>
+__device__ inline void stage_tile(const double *xt, TileLds &L, bool fin)
+{
+    double xv[kTileWords / NT];
+#pragma unroll
+    for (int k = 0; k < kTileWords / NT; k++) xv[k] = xt[threadIdx.x + k * NT];
+#pragma unroll
+    for (int k = 0; k < kTileWords / NT; k++) {
+        const int w = threadIdx.x + k * NT;
+        L.x[w] = xv[k];
+        if (fin) {
+            L.hits[w] = 0u;
+            L.cf[w] = 0;
+            L.cb[w] = 0.0;
+        }
+    }
+}
+
+// Fused step: finish block P, then the dot products of block C.  The list
+// bounds, both lists' first round, the finished rows' data and the tile are
+// all requested before the first wait.
 template <int NT, typename CH>
 __global__ void __launch_bounds__(NT) k_drop_tile(DropTileArgs A)
 {
     __shared__ TileLds L;
-    clear_next(A, NT);
     const int64_t T = blockIdx.x;
     int64_t p0, p1, c0, c1;
     list_range(A.P, T, p0, p1);
     list_range(A.C, T, c0, c1);
+    clear_next(A, NT);
     if (p0 == p1 && c0 == c1) return;
     double *xt = A.x + (T << kTileShift);
-    for (int w = threadIdx.x; w < kTileWords; w += NT) L.x[w] = xt[w];
+    const Ent pe = load_ent<CH>(A.P, p0 + threadIdx.x, p1);
+    const Ent ce = load_ent<CH>(A.C, c0 + threadIdx.x, c1);
+    const RowData pd = load_row(A.P, pe);
+    stage_tile<NT>(xt, L, p1 > p0);
     __syncthreads();
-    if (p1 > p0) tile_finish<NT, CH>(A.P, p0, p1, L, xt, A.lambda, A.big, A.err);
-    if (c1 > c0) tile_dots<NT, CH>(A.C, c0, c1, L, A.dot_max, A.err);
+    if (p1 > p0) tile_finish<NT, CH>(A.P, p0, p1, pe, pd, L, xt, A.lambda, A.big, A.err);
+    if (c1 > c0) tile_dots<NT, CH>(A.C, c0, c1, ce, L, A.dot_max, A.err);
 }
 
 // Split form, first launch: finish block P only.
@@ -174,9 +252,11 @@ __global__ void __launch_bounds__(NT) k_drop_tile_finish(DropTileArgs A)
     list_range(A.P, T, p0, p1);
     if (p0 == p1) return;
     double *xt = A.x + (T << kTileShift);
-    for (int w = threadIdx.x; w < kTileWords; w += NT) L.x[w] = xt[w];
+    const Ent pe = load_ent<CH>(A.P, p0 + threadIdx.x, p1);
+    const RowData pd = load_row(A.P, pe);
+    stage_tile<NT>(xt, L, true);
     __syncthreads();
-    tile_finish<NT, CH>(A.P, p0, p1, L, xt, A.lambda, A.big, A.err);
+    tile_finish<NT, CH>(A.P, p0, p1, pe, pd, L, xt, A.lambda, A.big, A.err);
 }
 
 // Split form, second launch: dot products of block C only.
@@ -184,15 +264,16 @@ template <int NT, typename CH>
 __global__ void __launch_bounds__(NT) k_drop_tile_dots(DropTileArgs A)
 {
     __shared__ TileLds L;
-    clear_next(A, NT);
     const int64_t T = blockIdx.x;
     int64_t c0, c1;
     list_range(A.C, T, c0, c1);
+    clear_next(A, NT);
     if (c0 == c1) return;
     const double *xt = A.x + (T << kTileShift);
-    for (int w = threadIdx.x; w < kTileWords; w += NT) L.x[w] = xt[w];
+    const Ent ce = load_ent<CH>(A.C, c0 + threadIdx.x, c1);
+    stage_tile<NT>(xt, L, false);
     __syncthreads();
-    tile_dots<NT, CH>(A.C, c0, c1, L, A.dot_max, A.err);
+    tile_dots<NT, CH>(A.C, c0, c1, ce, L, A.dot_max, A.err);
 }
 
 __global__ void __launch_bounds__(256) k_zero_i64(long long *p, int64_t n)

@@ -33,7 +33,12 @@ __device__ inline double ipow(double base, int e)
     return r;
 }
 
-__device__ constexpr double fact(int n) { return n <= 1 ? 1.0 : (double)n * fact(n - 1); }
+// n! for n <= 9 (every use has a compile-time n after unrolling)
+__device__ inline double fact(int n)
+{
+    constexpr double f[10] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0, 5040.0, 40320.0, 362880.0};
+    return f[n];
+}
 
 __device__ inline double highland(double depth, int log_term)
 {
@@ -408,10 +413,12 @@ k_rows_count(GridDev g, HistDev H, MlpCfg m, int64_t first, int64_t n, int32_t *
 
 __global__ void __launch_bounds__(kThreads, kRowWaves)
 k_rows_seg(GridDev g, HistDev H, MlpCfg m, int64_t n, int64_t B, int64_t ntiles,
-           const int64_t *seg_off, uint32_t *btc, uint64_t *segtab, uint32_t *err)
+           const int64_t *seg_off, uint32_t *btc, uint64_t *segtab, uint32_t *err,
+           const int32_t *order)
 {
     int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
+    if (order) i = order[i];
     Emit<kSeg, float> e;
     e.btc = btc + (i / B) * ntiles;
     e.segtab = segtab + seg_off[i];
@@ -444,21 +451,24 @@ template <typename CH>
 __global__ void __launch_bounds__(kThreads, kRowWaves)
 k_rows_fill_tiled(GridDev g, HistDev H, MlpCfg m, TileFill f, CH *chord)
 {
-    int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (q >= f.n) return;
-    const int64_t i = f.first + q;
-    Emit<kTiled, CH> e;
-    e.segdst = f.segdst + f.seg_off[i];
-    e.seg_cap = f.seg_off[i + 1] - f.seg_off[i];
-    e.cap = f.cap;
-    e.err = f.err;
-    e.meta = f.meta;
-    e.chord = chord;
-    e.base = f.base;
-    e.q = (uint32_t)(i % f.B);
-    form_row<kTiled, CH>(g, H, m, i, e);
-    e.finish();
-    f.norm2[i] = (float)e.norm2;
+    // grid-stride: the grid may be held below the device's capacity so that
+    // the DROP launches running beside it always find free slots
+    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < f.n;
+         q += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = f.order ? (int64_t)f.order[f.first + q] : f.first + q;
+        Emit<kTiled, CH> e;
+        e.segdst = f.segdst + f.seg_off[i];
+        e.seg_cap = f.seg_off[i + 1] - f.seg_off[i];
+        e.cap = f.cap;
+        e.err = f.err;
+        e.meta = f.meta;
+        e.chord = chord;
+        e.base = f.base;
+        e.q = (uint32_t)(i % f.B);
+        form_row<kTiled, CH>(g, H, m, i, e);
+        e.finish();
+        f.norm2[i] = (float)e.norm2;
+    }
 }
 
 __global__ void __launch_bounds__(kThreads, kRowWaves)
@@ -502,6 +512,15 @@ k_validate(HistDev H, int64_t n, double step, uint32_t *bad, uint32_t *jmax)
         }
     }
     if (!ok) atomicAdd(bad, 1u);
+}
+
+// dst[b] = src[b * stride] for b = 0 .. n - 1
+__global__ void __launch_bounds__(kThreads)
+k_pick(const int64_t *src, int64_t stride, int64_t n, int64_t *dst)
+{
+    for (int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x; b < n;
+         b += (int64_t)gridDim.x * kThreads)
+        dst[b] = src[b * stride];
 }
 
 // ---------------------------------------------------------------- scan
@@ -595,12 +614,12 @@ hipError_t launch_rows_count(const GridDev &g, const HistDev &h, const MlpCfg &m
 
 hipError_t launch_rows_seg(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t n,
                            int64_t B, const int64_t *seg_off, uint32_t *btc, uint64_t *segtab,
-                           uint32_t *err, hipStream_t stream)
+                           uint32_t *err, const int32_t *order, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
     dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(k_rows_seg, grid, dim3(kThreads), 0, stream, g, h, m, n, B, num_tiles(g),
-                       seg_off, btc, segtab, err);
+                       seg_off, btc, segtab, err, order);
     return hipGetLastError();
 }
 
@@ -619,7 +638,9 @@ hipError_t launch_rows_fill_tiled(const GridDev &g, const HistDev &h, const MlpC
                                   const TileFill &f, hipStream_t stream)
 {
     if (f.n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((f.n + kThreads - 1) / kThreads));
+    int64_t wgs = (f.n + kThreads - 1) / kThreads;
+    if (f.max_wgs > 0 && wgs > f.max_wgs) wgs = f.max_wgs;
+    dim3 grid((unsigned)wgs);
     if (f.ch16)
         hipLaunchKernelGGL(k_rows_fill_tiled<__half>, grid, dim3(kThreads), 0, stream, g, h, m, f,
                            f.ch16);
@@ -647,6 +668,16 @@ hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *b
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_validate, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
                        0, stream, h, n, step, bad, jmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_pick(const int64_t *src, int64_t stride, int64_t n, int64_t *dst,
+                       hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t wgs = (n + kThreads - 1) / kThreads;
+    if (wgs > 1024) wgs = 1024;
+    hipLaunchKernelGGL(k_pick, dim3((unsigned)wgs), dim3(kThreads), 0, stream, src, stride, n, dst);
     return hipGetLastError();
 }
 

@@ -90,6 +90,7 @@ struct tvs_ctx {
     double *s1i = nullptr;          // entry-side MLP table (3 per vertex depth)
     int64_t nj = 0;
     int64_t *seg_off = nullptr;     // nh + 1
+    int32_t *order = nullptr;       // nh: each chunk's histories by decreasing row length
     uint64_t *segtab = nullptr;     // nseg: global entry index of each segment's first entry
     int64_t nseg = 0;
     int64_t *bt_off = nullptr;      // nblocks * ntiles + 1 list starts
@@ -108,6 +109,7 @@ struct tvs_ctx {
     double big = 0.0, dot_max = 0.0;  // fixed-point ranges of the DROP kernels
     int threads = 256;              // threads per tile workgroup
     int split = 0;                  // 1: two launches per block
+    int64_t fill_wgs = 0;           // grid cap of the sweep's row formation (0: none)
 
     // cycle state
     int64_t k = 0, ell = 0;
@@ -199,6 +201,7 @@ void free_histories(tvs_ctx *ctx)
     dfree(ctx, &ctx->row_off, (size_t)(ctx->nh + 1));
     dfree(ctx, &ctx->norm2, (size_t)ctx->nh);
     dfree(ctx, &ctx->seg_off, (size_t)(ctx->nh + 1));
+    dfree(ctx, &ctx->order, (size_t)ctx->nh);
     dfree(ctx, &ctx->s1i, (size_t)(3 * ctx->nj));
     ctx->nj = 0;
     ctx->mlp.s1i = nullptr;
@@ -363,6 +366,8 @@ tvs::TileFill chunk_fill(tvs_ctx *ctx, int64_t c, int64_t n)
     f.cap = ctx->cap;
     f.norm2 = ctx->norm2;
     f.err = ctx->flags + kFlagLists;
+    f.max_wgs = ctx->fill_wgs;
+    f.order = ctx->order;
     return f;
 }
 
@@ -484,7 +489,8 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
     int32_t *cnt = nullptr, *cseg = nullptr;
     uint32_t *btc = nullptr;
     int64_t *tmp = nullptr;
-    const int64_t ntmp = tvs::scan_tmp_elems(std::max(n, nbt)) + 1;
+    // scan scratch, later also the gathered block starts
+    const int64_t ntmp = std::max(tvs::scan_tmp_elems(std::max(n, nbt)) + 1, (n + B - 1) / B + 1);
     auto cleanup = [&]() {
         dfree(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
         dfree(ctx, &cseg, (size_t)std::max<int64_t>(n, 1));
@@ -534,6 +540,38 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
     ctx->chunk = std::max<int64_t>(chunk, 1);
     for (int64_t f = 0; f < n; f += ctx->chunk) ctx->chunk_base.push_back(off[(size_t)f]);
     ctx->chunk_base.push_back(total);
+    // processing order of the row passes: within each chunk, histories by
+    // decreasing row length (a counting sort), so that the lanes of a
+    // wavefront walk rows of similar length; each segment's place is fixed
+    // below, so the order changes no result
+    {
+        std::vector<int32_t> ord((size_t)n);
+        std::vector<int64_t> cnt_len((size_t)mx + 2);
+        for (int64_t f0 = 0; f0 < n; f0 += ctx->chunk) {
+            const int64_t f1 = std::min(n, f0 + ctx->chunk);
+            std::fill(cnt_len.begin(), cnt_len.end(), 0);
+            for (int64_t i = f0; i < f1; i++) cnt_len[(size_t)(mx - (off[(size_t)i + 1] - off[(size_t)i]))]++;
+            int64_t pos = f0;
+            for (size_t q = 0; q < cnt_len.size(); q++) {
+                const int64_t c0 = cnt_len[q];
+                cnt_len[q] = pos;
+                pos += c0;
+            }
+            for (int64_t i = f0; i < f1; i++)
+                ord[(size_t)cnt_len[(size_t)(mx - (off[(size_t)i + 1] - off[(size_t)i]))]++] = (int32_t)i;
+        }
+        rc = dalloc(ctx, &ctx->order, (size_t)n);
+        if (rc) {
+            cleanup();
+            return rc;
+        }
+        e = hipMemcpyAsync(ctx->order, ord.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            cleanup();
+            return fail(ctx, TVS_EDEVICE, std::string("row order: ") + hipGetErrorString(e));
+        }
+    }
     // integer ranges of the DROP sums: no voxel takes more than 2B entries of
     // one block, no row more than max_row entries
     ctx->big = 2097152.0 / (double)B;                              // 2^21 / B
@@ -550,29 +588,36 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
     if (e == hipSuccess) e = hipMemsetAsync(ctx->flags, 0, sizeof(uint32_t) * kNumFlags, st);
     if (e == hipSuccess)
         e = tvs::launch_rows_seg(ctx->gd, hd, ctx->mlp, n, B, ctx->seg_off, btc, ctx->segtab,
-                                 ctx->flags + kFlagLists, st);
+                                 ctx->flags + kFlagLists, ctx->order, st);
     if (e == hipSuccess)
         e = tvs::launch_scan(reinterpret_cast<const int32_t *>(btc), nbt, ctx->bt_off, tmp, st);
     if (e == hipSuccess)
         e = tvs::launch_seg_dest(ctx->gd, n, B, ctx->seg_off, ctx->bt_off, ctx->segtab,
                                  ctx->flags + kFlagLists, st);
-    // every block's lists must add up to the block's entries
+    // every block's lists must add up to the block's entries (the block
+    // starts are gathered into the freed count buffer, then copied)
     std::vector<int64_t> starts((size_t)ctx->nblocks + 1);
     if (e == hipSuccess && ctx->nblocks > 0)
-        e = hipMemcpy2DAsync(starts.data(), sizeof(int64_t), ctx->bt_off,
-                             sizeof(int64_t) * ctx->ntiles, sizeof(int64_t),
-                             (size_t)ctx->nblocks + 1, hipMemcpyDeviceToHost, st);
+        e = tvs::launch_pick(ctx->bt_off, ctx->ntiles, ctx->nblocks + 1, tmp, st);
+    if (e == hipSuccess && ctx->nblocks > 0)
+        e = hipMemcpyAsync(starts.data(), tmp, sizeof(int64_t) * (ctx->nblocks + 1),
+                           hipMemcpyDeviceToHost, st);
     uint32_t fl[kNumFlags] = {0, 0, 0, 0};
     if (e == hipSuccess)
         e = hipMemcpyAsync(fl, ctx->flags, sizeof(fl), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     cleanup();
     if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("tile lists: ") + hipGetErrorString(e));
-    bool same = !fl[kFlagLists];
-    for (int64_t b = 0; same && b < ctx->nblocks; b++)
-        same = starts[(size_t)b] == off[(size_t)(b * B)];
-    if (same && ctx->nblocks > 0) same = starts[(size_t)ctx->nblocks] == total;
-    if (!same) return fail(ctx, TVS_EDEVICE, "tile lists disagree with the row lengths");
+    if (fl[kFlagLists])
+        return fail(ctx, TVS_EDEVICE, "tile lists: a row walk disagreed with the count pass");
+    for (int64_t b = 0; b <= ctx->nblocks && ctx->nblocks > 0; b++) {
+        const int64_t want = (b < ctx->nblocks) ? off[(size_t)(b * B)] : total;
+        if (starts[(size_t)b] != want)
+            return fail(ctx, TVS_EDEVICE,
+                        "tile lists disagree with the row lengths at block " + std::to_string(b) +
+                            " of " + std::to_string(ctx->nblocks) + ": " +
+                            std::to_string(starts[(size_t)b]) + " != " + std::to_string(want));
+    }
     return TVS_OK;
 }
 
@@ -615,6 +660,7 @@ int form_entries(tvs_ctx *ctx, hipStream_t st)
     f.cap = ctx->cap;
     f.norm2 = ctx->norm2;
     f.err = ctx->flags + kFlagLists;
+    f.order = ctx->order;
     hipError_t e = tvs::launch_rows_fill_tiled(ctx->gd, hist_dev(ctx), ctx->mlp, f, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("row fill: ") + hipGetErrorString(e));
@@ -641,6 +687,8 @@ void tvs_config_default(tvs_config *cfg)
     cfg->sweep_kernel = 0;
     cfg->tile_threads = 0;
     cfg->time_sample = 0;
+    cfg->fill_wgs_per_cu = 0;
+    cfg->pad = 0;
 }
 
 const char *tvs_strerror(int status)
@@ -730,6 +778,14 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (ctx->cfg.max_tries == 0) ctx->cfg.max_tries = 100000;
     ctx->threads = cfg.tile_threads ? cfg.tile_threads : 256;
     ctx->split = (cfg.sweep_kernel == 2) ? 1 : 0;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg.device) !=
+            hipSuccess)
+            cus = 0;
+        const int per_cu = cfg.fill_wgs_per_cu ? cfg.fill_wgs_per_cu : 2;
+        ctx->fill_wgs = (per_cu > 0 && cus > 0) ? (int64_t)per_cu * cus : 0;
+    }
 
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
@@ -1230,6 +1286,7 @@ int batch_cycle(tvs_ctx *ctx, int nmax, hipStream_t st)
         if (otf && has_c && (b * B) % step == 0) {
             const int64_t c = (b * B) / step;
             tvs::TileFill f = chunk_fill(ctx, c, std::min(step, ctx->nh - c * step));
+            f.max_wgs = 0;   // in line with the chain here: the whole device
             HIPCHK(tvs::launch_rows_fill_tiled(ctx->gd, hist_dev(ctx), ctx->mlp, f, st));
         }
         tvs::DropTileArgs A;

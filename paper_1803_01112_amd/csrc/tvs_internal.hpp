@@ -118,6 +118,9 @@ struct TileFill {
     int64_t cap = 0;                // entries meta / chord can hold
     float *norm2 = nullptr;         // per history (global index)
     uint32_t *err = nullptr;        // raised if a walk disagrees with the load-time lists
+    int64_t max_wgs = 0;            // > 0: at most this many workgroups (grid-stride)
+    const int32_t *order = nullptr; // non-null: lane q forms history order[first + q] (the
+                                    // histories of a chunk by decreasing row length)
 };
 
 // ----------------------------------------------------------------- rows.hip
@@ -132,7 +135,7 @@ hipError_t launch_rows_count(const GridDev &g, const HistDev &h, const MlpCfg &m
                              int64_t n, int32_t *nnz, int32_t *nseg, hipStream_t stream);
 hipError_t launch_rows_seg(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t n,
                            int64_t B, const int64_t *seg_off, uint32_t *btc, uint64_t *segtab,
-                           uint32_t *err, hipStream_t stream);
+                           uint32_t *err, const int32_t *order, hipStream_t stream);
 hipError_t launch_seg_dest(const GridDev &g, int64_t n, int64_t B, const int64_t *seg_off,
                            const int64_t *bt_off, uint64_t *segtab, uint32_t *err,
                            hipStream_t stream);
@@ -152,6 +155,9 @@ hipError_t launch_scan(const int32_t *cnt, int64_t n, int64_t *off, int64_t *tmp
 // raises *jmax to at least every valid history's vertex count + 2.
 hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *bad,
                            uint32_t *jmax, hipStream_t stream);
+// dst[b] = src[b * stride] for b < n.
+hipError_t launch_pick(const int64_t *src, int64_t stride, int64_t n, int64_t *dst,
+                       hipStream_t stream);
 // Fills the entry-side table of m for depths j = 0 .. nj - 1 (3 doubles each).
 hipError_t launch_mlp_table(const MlpCfg &m, int64_t nj, double *tab, hipStream_t stream);
 

@@ -46,7 +46,8 @@ class Config(C.Structure):
                 ("mlp_log_term", C.c_int32), ("mlp_const_power", C.c_int32),
                 ("chunk_histories", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
                 ("device", C.c_int32), ("max_tries", C.c_int32), ("sweep_kernel", C.c_int32),
-                ("tile_threads", C.c_int32), ("time_sample", C.c_int32)]
+                ("tile_threads", C.c_int32), ("time_sample", C.c_int32),
+                ("fill_wgs_per_cu", C.c_int32), ("pad", C.c_int32)]
 
 
 _FP = C.POINTER(C.c_float)
@@ -210,7 +211,7 @@ class Context:
     def __init__(self, grid, *, block_size=3200, path_mode="otf", mlp_step_mm=0.0,
                  mlp_log_term=True, mlp_const_power=False, chunk_histories=0,
                  hbm_budget_bytes=0, device=0, max_tries=0, sweep_kernel=0, tile_threads=0,
-                 time_sample=0):
+                 time_sample=0, fill_wgs_per_cu=0):
         self._L = load_library()
         self.grid = grid
         self.nvox = int(grid.nx) * int(grid.ny) * int(grid.nz)
@@ -227,6 +228,7 @@ class Context:
         cfg.sweep_kernel = int(sweep_kernel)
         cfg.tile_threads = int(tile_threads)
         cfg.time_sample = int(time_sample)
+        cfg.fill_wgs_per_cu = int(fill_wgs_per_cu)
         self.cfg = cfg
         h = C.c_void_p()
         g = grid_struct(grid)
