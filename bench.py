@@ -337,8 +337,8 @@ def main():
                    "block_size": args.block, "lambda": args.lam, "N": args.N,
                    "alpha": args.alpha, "tv_check": bool(args.check),
                    "path_mode": args.path_mode, "nnz": nnz, "parallelism": "1 GPU"},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "cycles": len(lat)},
+        "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                        "cycles": len(lat)} if lat else None),
         "phases_ms_per_cycle": {"tv": st["tv_ms_total"] / max(st["cycles_timed"], 1),
                                 "sweep": st["sweep_ms_total"] / max(st["cycles_timed"], 1),
                                 "rows": st["rows_ms_total"] / max(st["cycles_timed"], 1),

@@ -4,9 +4,9 @@
 //
 // The S images are interleaved by voxel, x[p*S + s], so that the S values an
 // entry reads are contiguous.  The DROP sweep is the tile-wise chain of
-// drop.hip with S images at once: every entry of a tile list is read once
-// and applied to all S settings (settings taken 8 at a time through LDS);
-// hit counts depend only on the rows and are shared.  The TV steps of every
+// drop.hip with S images at once: one workgroup per (tile, group of 8
+// settings) applies each entry of the tile's lists to its 8 settings
+// through LDS; hit counts depend only on the rows.  The TV steps of every
 // setting run in one kernel per step index n, with per-setting beta read
 // from a device table indexed by a device cycle counter, so the launches of
 // one cycle can be captured once in a hipGraph and replayed for every cycle.
@@ -35,11 +35,13 @@ k_tvb_grad(GridDev G, const double *x, int S, int V, uint32_t active, const doub
     const int v = t / S, s = t - v * S;
     const int64_t nx = G.nx, ny = G.ny;
     const int64_t nvox = padded_voxels(G);
-    const int64_t p = (int64_t)blockIdx.x * V + v;     // brick-layout word
-    int64_t i = 0, j = 0, k = 0;
-    if (p < nvox) vcoord(G, p, i, j, k);
+    // a fixed grid strides over batches of V voxels (few partial sums)
     double sq = 0.0;
-    if (v < V && p < nvox && i < nx && j < ny && ((active >> s) & 1u)) {
+    for (int64_t p = (int64_t)blockIdx.x * V + v; v < V && p < nvox;
+         p += (int64_t)gridDim.x * V) {     // tiled-layout word
+        int64_t i = 0, j = 0, k = 0;
+        vcoord(G, p, i, j, k);
+        if (!(i < nx && j < ny && ((active >> s) & 1u))) continue;
         const double e2 = eps[s] * eps[s];
         auto X = [&](int64_t di, int64_t dj) { return x[vaddr(G, i + di, j + dj, k) * S + s]; };
         auto dxf = [&](int64_t ii, int64_t jj) {
@@ -64,7 +66,7 @@ k_tvb_grad(GridDev G, const double *x, int S, int V, uint32_t active, const doub
             if (mm > 0.0) gv += dyf(0, -1) / mm;
         }
         g[p * S + s] = gv;
-        sq = gv * gv;
+        sq += gv * gv;
     }
     red[t] = sq;
     __syncthreads();
@@ -155,6 +157,12 @@ unsigned elem_grid(int64_t n)
 // ------------------------------------------------------------- DROP, S images
 constexpr int kGroup = 8;   // settings per pass through LDS
 
+// LDS index of (voxel word w, setting s of the group): the settings of a
+// voxel are XOR-swizzled by w so that lanes holding different voxels and the
+// same setting fall into different banks (without it every voxel's setting s
+// shares one bank pair).
+__device__ inline int sx(int w, int s) { return w * kGroup + (s ^ (w & (kGroup - 1))); }
+
 struct BatchLds {
     double x[kTileWords * kGroup];
     long long cf[kTileWords * kGroup];
@@ -163,7 +171,10 @@ struct BatchLds {
 };
 
 // One step of the tile-wise chain for S settings: finish block P and form
-// the dot products of block C (dot arrays row-major: dot[q * S + s]).
+// the dot products of block C (dot arrays row-major: dot[q * S + s]).  The
+// per-entry quotient a_ij / ||a_i||^2 and the per-voxel 1 / s_j are formed
+// once and shared by the settings (a rounding apart from the single-image
+// kernel, which divides per value).
 template <typename CH>
 __global__ void __launch_bounds__(kThreads)
 k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
@@ -171,8 +182,8 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
     __shared__ BatchLds L;
     const int t = threadIdx.x;
     if (A.zero)
-        for (int64_t q = (int64_t)blockIdx.x * kThreads + t; q < A.B * S;
-             q += (int64_t)gridDim.x * kThreads)
+        for (int64_t q = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kThreads + t;
+             q < A.B * S; q += (int64_t)gridDim.x * gridDim.y * kThreads)
             A.zero[q] = 0;
     const int64_t T = blockIdx.x;
     int64_t p0 = 0, p1 = 0, c0 = 0, c1 = 0;
@@ -194,11 +205,30 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
         chc = A.C.ch16;
     }
     double *xt = A.x + (T << kTileShift) * S;
-    for (int g0 = 0; g0 < S; g0 += kGroup) {
+    // the first round of both lists and the finished rows' data, loaded once
+    // for all setting groups
+    uint32_t pm = 0u, cm = 0u;
+    double pa = 0.0, ca = 0.0, pw = 0.0, pn2 = 1.0;
+    const bool pok = p0 + t < p1, cok = c0 + t < c1;
+    if (pok) {
+        pm = A.P.meta[p0 + t - A.P.base];
+        pa = (double)chord_at(chp, p0 + t - A.P.base);
+    }
+    if (cok) {
+        cm = A.C.meta[c0 + t - A.C.base];
+        ca = (double)chord_at(chc, c0 + t - A.C.base);
+    }
+    if (pok && (pm >> kTileShift) < A.P.rows) {
+        pw = (double)A.P.wepl[pm >> kTileShift];
+        pn2 = (double)A.P.n2[pm >> kTileShift];
+    }
+    // one group of settings per workgroup (the grid's second dimension)
+    {
+        const int g0 = (int)blockIdx.y * kGroup;
         const int G = (S - g0 < kGroup) ? S - g0 : kGroup;
         for (int i = t; i < kTileWords * G; i += kThreads) {
             const int w = i / G, s = i - w * G;
-            L.x[w * kGroup + s] = xt[(int64_t)w * S + g0 + s];
+            L.x[sx(w, s)] = xt[(int64_t)w * S + g0 + s];
         }
         if (p1 > p0) {
             for (int i = t; i < kTileWords * kGroup; i += kThreads) {
@@ -208,71 +238,95 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
             for (int w = t; w < kTileWords; w += kThreads) L.hits[w] = 0u;
             __syncthreads();
             for (int64_t e = p0 + t; e < p1; e += kThreads) {
-                const uint32_t m = A.P.meta[e - A.P.base];
+                const bool first = e == p0 + t;
+                const uint32_t m = first ? pm : A.P.meta[e - A.P.base];
                 const int w = (int)(m & (kTileWords - 1));
                 const uint32_t q = m >> kTileShift;
                 if (q >= A.P.rows) {
                     atomicOr(A.err, 2u);
                     continue;
                 }
-                const double a = (double)chord_at(chp, e - A.P.base);
-                const double wp = (double)A.P.wepl[q], n2 = (double)A.P.n2[q];
+                const double a = first ? pa : (double)chord_at(chp, e - A.P.base);
+                const double wp = first ? pw : (double)A.P.wepl[q];
+                const double n2 = first ? pn2 : (double)A.P.n2[q];
+                const double an2 = a / n2;   // one division for all settings
                 atomicAdd(&L.hits[w], 1u);
                 for (int s = 0; s < G; s++) {
-                    const double r = (wp - (double)A.P.dot[(int64_t)q * S + g0 + s] * kDotUnit) / n2;
-                    const double v = r * a;
+                    const double res = wp - (double)A.P.dot[(int64_t)q * S + g0 + s] * kDotUnit;
+                    const double v = res * an2;
                     if (fabs(v) <= A.big)
-                        atomicAdd(reinterpret_cast<unsigned long long *>(&L.cf[w * kGroup + s]),
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&L.cf[sx(w, s)]),
                                   (unsigned long long)__double2ll_rn(v * kCorrScale));
                     else
-                        atomicAdd(&L.cb[w * kGroup + s], v);
+                        atomicAdd(&L.cb[sx(w, s)], v);
                 }
             }
             __syncthreads();
-            for (int i = t; i < kTileWords * G; i += kThreads) {
-                const int w = i / G, s = i - w * G;
+            for (int w = t; w < kTileWords; w += kThreads) {
                 const uint32_t h = L.hits[w];
-                if (h) {
-                    const int k = w * kGroup + s;
+                if (!h) continue;
+                const double inv_h = 1.0 / (double)h;   // one division for all settings
+                for (int s = 0; s < G; s++) {
+                    const int k = sx(w, s);
                     const double c = (double)L.cf[k] * kCorrUnit + L.cb[k];
-                    const double nx = L.x[k] + lambda[g0 + s] * c / (double)h;
+                    const double nx = L.x[k] + lambda[g0 + s] * c * inv_h;
                     L.x[k] = nx;
                     xt[(int64_t)w * S + g0 + s] = nx;
                 }
             }
         }
         __syncthreads();
-        // every thread runs the same rounds and settings (the shuffles are uniform)
+        // every thread runs the same rounds and settings (the shuffles are
+        // uniform).  The run sums of the group's settings are staged in LDS
+        // (in the finish sums' space, free by now) and leave as atomics of 8
+        // settings of one row each: one 64-byte line per run instead of 8.
+        const int wave = t >> 6, lane = t & 63;
+        long long *stg_v = reinterpret_cast<long long *>(L.cb) + wave * 64 * kGroup;
+        uint32_t *stg_q = L.hits + wave * 64;
         for (int64_t r0 = c0; r0 < c1; r0 += kThreads) {
             const int64_t e = r0 + t;
             uint32_t q = kNoRow;
             int w = 0;
             double a = 0.0;
             if (e < c1) {
-                const uint32_t m = A.C.meta[e - A.C.base];
+                const bool first = r0 == c0;
+                const uint32_t m = first ? cm : A.C.meta[e - A.C.base];
                 q = m >> kTileShift;
                 w = (int)(m & (kTileWords - 1));
-                a = (double)chord_at(chc, e - A.C.base);
+                a = first ? ca : (double)chord_at(chc, e - A.C.base);
                 if (q >= A.C.rows) {
                     atomicOr(A.err, 2u);
                     q = kNoRow;
                 }
             }
             const dev::Runs runs = dev::wave_runs(q);
+            const bool emit = runs.tail && q != kNoRow;
+            const unsigned long long tails = __ballot(emit);
+            const int k = __popcll(tails & ((1ull << lane) - 1ull));
             for (int s = 0; s < G; s++) {
                 long long f = 0;
                 if (q != kNoRow) {
-                    const double p = a * L.x[w * kGroup + s];
+                    const double p = a * L.x[sx(w, s)];
                     if (fabs(p) <= A.dot_max) f = __double2ll_rn(p * kDotScale);
                     else atomicOr(A.err, 1u);
                 }
                 f = dev::run_sum(f, runs);
-                if (runs.tail && q != kNoRow)
-                    atomicAdd(reinterpret_cast<unsigned long long *>(A.C.dot + (int64_t)q * S + g0 + s),
-                              (unsigned long long)f);
+                if (emit) stg_v[k * kGroup + s] = f;
             }
+            if (emit) stg_q[k] = q;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            const int n = __popcll(tails);
+            for (int b = 0; b < n; b += 64 / kGroup) {
+                const int j = b + (lane >> 3), s = lane & (kGroup - 1);
+                if (j < n && s < G)
+                    atomicAdd(reinterpret_cast<unsigned long long *>(A.C.dot + (int64_t)stg_q[j] * S +
+                                                                     g0 + s),
+                              (unsigned long long)stg_v[j * kGroup + s]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
-        __syncthreads();   // LDS is reused by the next group
     }
 }
 
@@ -284,7 +338,8 @@ int64_t batch_num_parts(const GridDev &g, int S)
 {
     const int64_t nvox = padded_voxels(g);
     const int V = batch_vox_per_wg(S);
-    return (nvox + V - 1) / V;
+    const int64_t batches = (nvox + V - 1) / V;
+    return batches < 1024 ? batches : 1024;    // the gradient kernel's grid
 }
 
 hipError_t launch_tvb_grad(const GridDev &g, const BatchBuffers &b, uint32_t active,
@@ -338,12 +393,13 @@ hipError_t launch_drop_tiles_batch(const DropTileArgs &a, const BatchBuffers &b,
 {
     if (ntiles <= 0 || (!a.P.valid && !a.C.valid)) return hipSuccess;
     const bool half = a.P.valid ? (a.P.ch16 != nullptr) : (a.C.ch16 != nullptr);
+    const dim3 grid((unsigned)ntiles, (unsigned)((b.S + kGroup - 1) / kGroup));
     if (half)
-        hipLaunchKernelGGL(k_drop_tile_batch<__half>, dim3((unsigned)ntiles), dim3(kThreads), 0,
-                           stream, a, b.S, (const double *)b.lambda);
+        hipLaunchKernelGGL(k_drop_tile_batch<__half>, grid, dim3(kThreads), 0, stream, a, b.S,
+                           (const double *)b.lambda);
     else
-        hipLaunchKernelGGL(k_drop_tile_batch<float>, dim3((unsigned)ntiles), dim3(kThreads), 0,
-                           stream, a, b.S, (const double *)b.lambda);
+        hipLaunchKernelGGL(k_drop_tile_batch<float>, grid, dim3(kThreads), 0, stream, a, b.S,
+                           (const double *)b.lambda);
     return hipGetLastError();
 }
 
