@@ -16,6 +16,7 @@ Prints one JSON line.  Only one GPU is supported: --gpus above 1 exits.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -45,6 +46,39 @@ def tile_step_bytes(nnz, nblocks, chord_bytes, nvox, block):
     once (float64); per row of both blocks WEPL, ||a||^2 (float32) and the
     64-bit dot product."""
     return 2.0 * (4.0 + chord_bytes) * nnz / max(nblocks, 1) + 16.0 * nvox + 32.0 * block
+
+
+# sources of the DROP step kernel: a counter record taken on other sources no
+# longer describes the kernel
+DROP_SOURCES = ("paper_1803_01112_amd/csrc/drop.hip", "paper_1803_01112_amd/csrc/device_common.hpp",
+                "paper_1803_01112_amd/csrc/tvs_internal.hpp")
+COUNTER_RECORD = "profiles/k_drop_tile_vol200_20M_counters.md"
+
+
+def drop_source_hash():
+    h = hashlib.sha256()
+    for f in DROP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per DROP launch from the committed counter record
+    (FETCH_SIZE and WRITE_SIZE passes, each scaled by what it reads for a
+    copy of known size), or None when the record is absent, was taken on
+    another workload or on other kernel sources."""
+    path = os.path.join(ROOT, COUNTER_RECORD)
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("counter-record: "):
+                rec = json.loads(line[len("counter-record: "):])
+    if not rec or rec.get("workload") != workload or rec.get("source_sha256") != drop_source_hash():
+        return None
+    return rec["bytes_per_launch"]
 
 
 def mlp_vertices(h, step):
@@ -220,7 +254,15 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--serve-path", default="f32")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a 256 MiB read + 256 MiB write kernel (scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--print-source-hash", action="store_true",
+                    help="print the hash of the DROP kernel sources and exit")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(drop_source_hash())
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported",
@@ -288,6 +330,9 @@ def main():
                     frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_ms=k1_ms,
                     algorithmic_per_launch=per_launch)
     roof["per_cycle_ms"] = per_cycle
+    key = f"{w.name}/{H}/B{args.block}/{args.path_mode}"
+    if dom == "k_drop_tile":
+        roof["traffic"] = measured_traffic(key)
 
     forms = {}
     for form in [f for f in args.forms.split(",") if f]:
@@ -314,6 +359,14 @@ def main():
         log("serving stream")
         serving = run_serving(tvs, args)
         log(f"serving: {serving}")
+
+    if args.copy_calibration:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.add(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
+        del a, b
 
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cpu = None if args.no_cpu else cpu_baseline(w, args, cores)

@@ -270,12 +270,14 @@ void reset_state(tvs_ctx *ctx)
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// Records a timing event on st; returns its index in the pool (or -1).
+// Records a timing event on st; returns its index in the pool (or -1). Pool
+// events skip the system-scope fence: they carry timestamps only, and the fence
+// (an L2 write-back) would otherwise be timed with the work it brackets.
 long mark(tvs_ctx *ctx, hipStream_t st)
 {
     if (ctx->tev_used == ctx->tev.size()) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
         ctx->tev.push_back(e);
     }
     if (hipEventRecord(ctx->tev[ctx->tev_used], st) != hipSuccess) return -1;
@@ -287,7 +289,7 @@ long slot(tvs_ctx *ctx)
 {
     if (ctx->tev_used == ctx->tev.size()) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
         ctx->tev.push_back(e);
     }
     return (long)ctx->tev_used++;
