@@ -40,11 +40,35 @@ __device__ inline double fact(int n)
     return f[n];
 }
 
+// a / b, correctly rounded (the IEEE quotient bit for bit), from y = 1/b
+// rounded to nearest: a * y corrected twice by its residual a - b q (exact
+// in an FMA).  After the first correction the estimate lies within one ulp
+// of a / b; from there one correction with a correctly rounded reciprocal
+// gives the correctly rounded quotient (Markstein's theorem; it needs no
+// underflow or overflow on the way, which holds for every quotient it is
+// used for here).  Five float64 operations against the eleven, one of them a
+// quarter-rate reciprocal, of a general division.
+__device__ inline double div_rn(double a, double b, double y)
+{
+    double q = a * y;
+    double r = fma(-q, b, a);
+    q = fma(r, y, q);
+    r = fma(-q, b, a);
+    return fma(r, y, q);
+}
+
+// a / n for a small integer n known at compile time (after unrolling).
+__device__ inline double div_int(double a, int n)
+{
+    if ((n & (n - 1)) == 0) return a / (double)n;     // power of two: exact multiply
+    return div_rn(a, (double)n, 1.0 / (double)n);
+}
+
 __device__ inline double highland(double depth, int log_term)
 {
     double f = 1.0;
-    if (log_term) f = 1.0 + 0.038 * log(depth / kX0);
-    return kE0 * kE0 * f * f / kX0;
+    if (log_term) f = 1.0 + 0.038 * log(div_rn(depth, kX0, 1.0 / kX0));
+    return div_rn(kE0 * kE0 * f * f, kX0, 1.0 / kX0);
 }
 
 // 1/(beta^2 p^2) of a 200 MeV proton in water, per mm^k.
@@ -172,12 +196,12 @@ struct Emit {
     }
 };
 
-// Grid coordinates (p - o) / v of a point.
+// Grid coordinates (p - o) / v of a point (quotients correctly rounded).
 __device__ inline void to_grid(const GridDev &g, const double p[3], double gp[3])
 {
-    gp[0] = (p[0] - g.ox) / g.vx;
-    gp[1] = (p[1] - g.oy) / g.vy;
-    gp[2] = (p[2] - g.oz) / g.vz;
+    gp[0] = div_rn(p[0] - g.ox, g.vx, g.rvx);
+    gp[1] = div_rn(p[1] - g.oy, g.vy, g.rvy);
+    gp[2] = div_rn(p[2] - g.oz, g.vz, g.rvz);
 }
 
 // Walks segment q0 -> q1 given both end points and their grid coordinates
@@ -283,10 +307,10 @@ template <int MODE, typename CH>
 __device__ void form_row(const GridDev &g, const HistDev &H, const MlpCfg &m, int64_t i,
                          Emit<MODE, CH> &e)
 {
-    double ex = H.ex[i], ey = H.ey[i], ez = H.ez[i];
-    double qx = H.qx[i], qy = H.qy[i], qz = H.qz[i];
-    double eth = H.eth[i], eps = H.eps[i], qth = H.qth[i], qps = H.qps[i];
-    double ux = H.ux[i], uy = H.uy[i];
+    double ex = H.s(kEx)[i], ey = H.s(kEy)[i], ez = H.s(kEz)[i];
+    double qx = H.s(kQx)[i], qy = H.s(kQy)[i], qz = H.s(kQz)[i];
+    double eth = H.s(kEth)[i], eps = H.s(kEps)[i], qth = H.s(kQth)[i], qps = H.s(kQps)[i];
+    double ux = H.s(kUx)[i], uy = H.s(kUy)[i];
     double nrm = sqrt(ux * ux + uy * uy);
     ux = ux / nrm;
     uy = uy / nrm;
@@ -339,7 +363,7 @@ __device__ void form_row(const GridDev &g, const HistDev &H, const MlpCfg &m, in
         for (int mm = 0; mm < 3; mm++)
 #pragma unroll
             for (int k = 0; k < 6; k++)
-                j2[mm] += c[k] * pw[mm + k + 1] / (double)(mm + k + 1);
+                j2[mm] += div_int(c[k] * pw[mm + k + 1], mm + k + 1);
         double A2 = highland(d2, m.log_term);
         M2 S2 = {A2 * j2[2], A2 * j2[1], A2 * j2[1], A2 * j2[0]};
         M2 R0 = {1.0, d1, 0.0, 1.0};
@@ -491,22 +515,20 @@ k_validate(HistDev H, int64_t n, double step, uint32_t *bad, uint32_t *jmax)
 {
     int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
-    const float *f[13] = {H.ex, H.ey, H.ez, H.qx, H.qy, H.qz, H.eth, H.eps, H.qth, H.qps,
-                          H.ux, H.uy, H.wepl};
     bool ok = true;
     for (int q = 0; q < 13; q++) {
-        float v = f[q][i];
+        float v = H.s(q)[i];
         if (!isfinite(v) || fabsf(v) > 1.0e6f) ok = false;
     }
     if (ok) {
-        double ux = H.ux[i], uy = H.uy[i];
+        double ux = H.s(kUx)[i], uy = H.s(kUy)[i];
         double nn = ux * ux + uy * uy;
         if (!(nn >= 1.0e-12)) {
             ok = false;
         } else {
             double nrm = sqrt(nn);
-            double L = ((double)H.qx[i] - (double)H.ex[i]) * (ux / nrm) +
-                       ((double)H.qy[i] - (double)H.ey[i]) * (uy / nrm);
+            double L = ((double)H.s(kQx)[i] - (double)H.s(kEx)[i]) * (ux / nrm) +
+                       ((double)H.s(kQy)[i] - (double)H.s(kEy)[i]) * (uy / nrm);
             if (L / step > 1048576.0) ok = false;
             else if (L > 0.0) atomicMax(jmax, (uint32_t)ceil(L / step) + 2u);
         }

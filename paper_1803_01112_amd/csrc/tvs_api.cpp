@@ -242,10 +242,7 @@ void free_batch(tvs_ctx *ctx)
 
 HistDev hist_dev(const tvs_ctx *ctx)
 {
-    const float *b = ctx->hist;
-    const int64_t n = ctx->nh;
-    return HistDev{b + 0 * n, b + 1 * n, b + 2 * n,  b + 3 * n,  b + 4 * n,  b + 5 * n, b + 6 * n,
-                   b + 7 * n, b + 8 * n, b + 9 * n, b + 10 * n, b + 11 * n, b + 12 * n};
+    return HistDev{ctx->hist, ctx->nh};
 }
 
 tvs::TvBuffers tv_bufs(tvs_ctx *ctx)

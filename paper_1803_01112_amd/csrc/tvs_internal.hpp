@@ -22,6 +22,7 @@ struct GridDev {
     double vx, vy, vz;
     double ox, oy, oz;
     int32_t ntx, nty;         // tiles per slice along x and y
+    double rvx, rvy, rvz;     // 1/vx, 1/vy, 1/vz rounded to nearest
 };
 
 // Tiled layout.  Each slice is cut into 16 x 16 voxel tiles of 256
@@ -68,12 +69,18 @@ __host__ __device__ inline int64_t padded_voxels(const GridDev &g)
 inline GridDev make_grid_dev(const tvs_grid &g)
 {
     return GridDev{g.nx, g.ny, g.nz, g.vx, g.vy, g.vz, g.ox, g.oy, g.oz,
-                   (g.nx + kTileSide - 1) / kTileSide, (g.ny + kTileSide - 1) / kTileSide};
+                   (g.nx + kTileSide - 1) / kTileSide, (g.ny + kTileSide - 1) / kTileSide,
+                   1.0 / g.vx, 1.0 / g.vy, 1.0 / g.vz};
 }
 
-// SoA history streams on the device (13 float32 arrays of length n_hist).
+// SoA history streams on the device: 13 float32 arrays of length n, one
+// after the other from base, in the order of HistStream.  Two words of
+// kernel arguments instead of thirteen pointers.
+enum HistStream { kEx = 0, kEy, kEz, kQx, kQy, kQz, kEth, kEps, kQth, kQps, kUx, kUy, kWepl };
 struct HistDev {
-    const float *ex, *ey, *ez, *qx, *qy, *qz, *eth, *eps, *qth, *qps, *ux, *uy, *wepl;
+    const float *base;
+    int64_t n;
+    __host__ __device__ const float *s(int k) const { return base + (int64_t)k * n; }
 };
 
 struct MlpCfg {
