@@ -219,6 +219,12 @@ __device__ inline void stage_tile(const double *xt, TileLds &L, bool fin)
     }
 }
 
+// The DROP steps form a chain of short dependent launches, while the rows
+// of later blocks are formed beside them on another stream by long float64
+// waves.  A step's waves take the highest issue priority on their SIMD so
+// that the chain is not held back behind the row formation.
+__device__ inline void chain_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // Fused step: finish block P, then the dot products of block C.  The list
 // bounds, both lists' first round, the finished rows' data and the tile are
 // all requested before the first wait.
@@ -226,6 +232,7 @@ template <int NT, typename CH>
 __global__ void __launch_bounds__(NT) k_drop_tile(DropTileArgs A)
 {
     __shared__ TileLds L;
+    chain_priority();
     const int64_t T = blockIdx.x;
     int64_t p0, p1, c0, c1;
     list_range(A.P, T, p0, p1);
@@ -247,6 +254,7 @@ template <int NT, typename CH>
 __global__ void __launch_bounds__(NT) k_drop_tile_finish(DropTileArgs A)
 {
     __shared__ TileLds L;
+    chain_priority();
     const int64_t T = blockIdx.x;
     int64_t p0, p1;
     list_range(A.P, T, p0, p1);
@@ -264,6 +272,7 @@ template <int NT, typename CH>
 __global__ void __launch_bounds__(NT) k_drop_tile_dots(DropTileArgs A)
 {
     __shared__ TileLds L;
+    chain_priority();
     const int64_t T = blockIdx.x;
     int64_t c0, c1;
     list_range(A.C, T, c0, c1);

@@ -25,6 +25,9 @@ constexpr int kThreads = 256;
 // Row kernels: hold the register budget to 3 wavefronts per SIMD (168
 // VGPRs), enough to overlap the float64 latency of one lane's walk.
 constexpr int kRowWaves = 3;
+// List entries staged per lane before they are written (LDS: 8 bytes each,
+// 32 KB per 256-lane workgroup with float32 chords).
+constexpr int kStage = 16;
 
 __device__ inline double ipow(double base, int e)
 {
@@ -129,6 +132,11 @@ struct Emit {
     uint32_t *meta = nullptr;    // kTiled
     int64_t base = 0, dst = 0;   // kTiled
     uint32_t q = 0;              // kTiled: row within its block
+    // kTiled: entries of the open segment are staged in this lane's LDS slots
+    // and written out together when the segment closes or the slots fill
+    // (list places dst - ns .. dst - 1), so that every list line is written
+    // in one burst instead of one 4-byte store per walk step
+    int ns = 0;
     // kSeg, kTiled: guards against a walk that disagrees with the load-time
     // count (segments of this row, entries of the buffer); a disagreement
     // writes nothing and raises *err
@@ -159,6 +167,7 @@ struct Emit {
         const int32_t t = cur >> kTileShift;
         if (t != tile) {
             close_seg();
+            if constexpr (MODE == kTiled) drain();
             tile = t;
             if constexpr (MODE == kSeg || MODE == kTiled) {
                 if (nseg >= seg_cap) bad();
@@ -176,10 +185,12 @@ struct Emit {
         if constexpr (MODE == kTiled) {
             if (ok && (dst < 0 || dst >= cap)) bad();
             if (ok) {
-                meta[dst] = (uint32_t)(cur & (kTileWords - 1)) | (q << kTileShift);
-                if constexpr (sizeof(CH) == 4) chord[dst] = (float)cur_len;
-                else chord[dst] = __float2half((float)cur_len);
+                const int slot = ns * kThreads + (int)threadIdx.x;
+                stage_meta()[slot] = (uint32_t)(cur & (kTileWords - 1)) | (q << kTileShift);
+                if constexpr (sizeof(CH) == 4) stage_chord()[slot] = (float)cur_len;
+                else stage_chord()[slot] = __float2half((float)cur_len);
                 dst++;
+                if (++ns == kStage) drain();
             }
         }
         if constexpr (MODE == kSeg) seg_len++;
@@ -189,10 +200,35 @@ struct Emit {
         cur_len = 0.0;
     }
 
+    // kTiled staging slots: slot k of lane l at k * kThreads + l (LDS)
+    static __device__ inline uint32_t *stage_meta()
+    {
+        __shared__ uint32_t sm[kStage * kThreads];
+        return sm;
+    }
+    static __device__ inline CH *stage_chord()
+    {
+        __shared__ CH sc[kStage * kThreads];
+        return sc;
+    }
+
+    // kTiled: writes the staged entries to their consecutive list places
+    __device__ inline void drain()
+    {
+        const int64_t d0 = dst - ns;
+        for (int k = 0; k < ns; k++) {
+            const int slot = k * kThreads + (int)threadIdx.x;
+            meta[d0 + k] = stage_meta()[slot];
+            chord[d0 + k] = stage_chord()[slot];
+        }
+        ns = 0;
+    }
+
     __device__ inline void finish()
     {
         flush();
         close_seg();
+        if constexpr (MODE == kTiled) drain();
     }
 };
 
@@ -218,13 +254,16 @@ __device__ void walk_segment(const GridDev &g, const double q0[3], const double 
     double len = sqrt(dx * dx + dy * dy + dz * dz);
     if (!(len > 0.0)) return;
 
-    // Per axis: next integer plane in the direction of travel, the last one
-    // inside [0, n], and its crossing parameter tau = (m - g0) / dg.
-    double mnext[3], mend[3], step[3], tnext[3];
-    bool act[3];
+    // Per axis: next integer plane in the direction of travel, how many
+    // planes inside [0, n] remain after it, and its crossing parameter
+    // tau = (m - g0) / dg.  An axis with no plane left has tau = 2, past the
+    // segment's end, so it is never the nearest crossing.
+    double mnext[3], tnext[3];
+    int rem[3];
     for (int a = 0; a < 3; a++) {
-        act[a] = false;
+        mnext[a] = 0.0;
         tnext[a] = 2.0;
+        rem[a] = 0;
         if (dg[a] == 0.0) continue;
         double lo = (g0[a] < g1[a]) ? g0[a] : g1[a];
         double hi = (g0[a] < g1[a]) ? g1[a] : g0[a];
@@ -233,9 +272,8 @@ __device__ void walk_segment(const GridDev &g, const double q0[3], const double 
         if (mlo < 0.0) mlo = 0.0;
         if (mhi > (double)n[a]) mhi = (double)n[a];
         if (mlo > mhi) continue;
-        act[a] = true;
-        if (dg[a] > 0.0) { mnext[a] = mlo; mend[a] = mhi; step[a] = 1.0; }
-        else { mnext[a] = mhi; mend[a] = mlo; step[a] = -1.0; }
+        mnext[a] = (dg[a] > 0.0) ? mlo : mhi;
+        rem[a] = (int)(mhi - mlo);
         tnext[a] = (mnext[a] - g0[a]) / dg[a];
     }
 
@@ -243,20 +281,19 @@ __device__ void walk_segment(const GridDev &g, const double q0[3], const double 
     for (;;) {
         double tb = 1.0;
         for (int a = 0; a < 3; a++)
-            if (act[a] && tnext[a] < tb) tb = tnext[a];
+            if (tnext[a] < tb) tb = tnext[a];
         if (tb > prev) {
             double ta = prev;
             prev = tb;
             double tm = (ta + tb) * 0.5;
+            double c[3];
             bool inside = true;
-            int64_t vi[3];
             for (int a = 0; a < 3; a++) {
-                double c = floor(g0[a] + tm * dg[a]);
-                if (c < 0.0 || c >= (double)n[a]) { inside = false; break; }
-                vi[a] = (int64_t)c;
+                c[a] = floor(g0[a] + tm * dg[a]);
+                inside = inside && !(c[a] < 0.0 || c[a] >= (double)n[a]);
             }
             if (inside) {
-                int32_t lin = (int32_t)vaddr(g, vi[0], vi[1], vi[2]);
+                int32_t lin = vaddr32(g, (int32_t)c[0], (int32_t)c[1], (int32_t)c[2]);
                 double clen = (tb - ta) * len;
                 if (lin == e.cur) {
                     e.cur_len += clen;
@@ -269,9 +306,14 @@ __device__ void walk_segment(const GridDev &g, const double q0[3], const double 
         }
         if (tb >= 1.0) break;
         for (int a = 0; a < 3; a++) {
-            if (act[a] && tnext[a] == tb) {
-                if (mnext[a] == mend[a]) { act[a] = false; tnext[a] = 2.0; }
-                else { mnext[a] += step[a]; tnext[a] = (mnext[a] - g0[a]) / dg[a]; }
+            if (tnext[a] == tb) {
+                if (rem[a] == 0) {
+                    tnext[a] = 2.0;
+                } else {
+                    rem[a]--;
+                    mnext[a] += (dg[a] > 0.0) ? 1.0 : -1.0;
+                    tnext[a] = (mnext[a] - g0[a]) / dg[a];
+                }
             }
         }
     }

@@ -41,6 +41,15 @@ __host__ __device__ inline int64_t vaddr(const GridDev &g, int64_t i, int64_t j,
     return (tile << kTileShift) | in;
 }
 
+// vaddr in 32-bit arithmetic, for images of fewer than 2^31 words (every
+// image a context accepts).
+__host__ __device__ inline int32_t vaddr32(const GridDev &g, int32_t i, int32_t j, int32_t k)
+{
+    const int32_t tile = (k * g.nty + (j >> 4)) * g.ntx + (i >> 4);
+    const int32_t in = ((((j & 15) >> 1) << 2 | ((i & 15) >> 2)) << 3) | ((j & 1) << 2) | (i & 3);
+    return (tile << kTileShift) | in;
+}
+
 // Inverse of vaddr: voxel coordinates of tiled-layout word a.
 __host__ __device__ inline void vcoord(const GridDev &g, int64_t a, int64_t &i, int64_t &j,
                                        int64_t &k)
