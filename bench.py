@@ -48,37 +48,40 @@ def tile_step_bytes(nnz, nblocks, chord_bytes, nvox, block):
     return 2.0 * (4.0 + chord_bytes) * nnz / max(nblocks, 1) + 16.0 * nvox + 32.0 * block
 
 
-# sources of the DROP step kernel: a counter record taken on other sources no
-# longer describes the kernel
-DROP_SOURCES = ("paper_1803_01112_amd/csrc/drop.hip", "paper_1803_01112_amd/csrc/device_common.hpp",
-                "paper_1803_01112_amd/csrc/tvs_internal.hpp")
-COUNTER_RECORD = "profiles/k_drop_tile_vol200_20M_counters.md"
+# sources of each measured kernel: a counter record taken on other sources
+# no longer describes the kernel
+KERNEL_SOURCES = {
+    "k_drop_tile": ("paper_1803_01112_amd/csrc/drop.hip", "paper_1803_01112_amd/csrc/device_common.hpp",
+                    "paper_1803_01112_amd/csrc/tvs_internal.hpp"),
+    "k_rows_fill_tiled": ("paper_1803_01112_amd/csrc/rows.hip", "paper_1803_01112_amd/csrc/tvs_internal.hpp"),
+}
 
 
-def drop_source_hash():
+def source_hash(kernel):
     h = hashlib.sha256()
-    for f in DROP_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per DROP launch from the committed counter record
-    (FETCH_SIZE and WRITE_SIZE passes, each scaled by what it reads for a
-    copy of known size), or None when the record is absent, was taken on
-    another workload or on other kernel sources."""
-    path = os.path.join(ROOT, COUNTER_RECORD)
-    if not os.path.exists(path):
-        return None
-    rec = None
-    with open(path) as fh:
-        for line in fh:
-            if line.startswith("counter-record: "):
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from a committed counter record
+    (profiles/*_counters.md: FETCH_SIZE and WRITE_SIZE passes, each scaled
+    by what it reads for a copy of known size), or None when there is no
+    record for this kernel and workload taken on the current sources."""
+    import glob
+    want = source_hash(kernel)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_counters.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("counter-record: "):
+                    continue
                 rec = json.loads(line[len("counter-record: "):])
-    if not rec or rec.get("workload") != workload or rec.get("source_sha256") != drop_source_hash():
-        return None
-    return rec["bytes_per_launch"]
+                if (rec.get("kernel_family") == kernel and rec.get("workload") == workload
+                        and rec.get("source_sha256") == want):
+                    return rec["bytes_per_launch"]
+    return None
 
 
 def mlp_vertices(h, step):
@@ -258,10 +261,11 @@ def main():
                     help="end with a 256 MiB read + 256 MiB write kernel (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--print-source-hash", action="store_true",
-                    help="print the hash of the DROP kernel sources and exit")
+                    help="print the hash of each measured kernel's sources and exit")
     args = ap.parse_args()
     if args.print_source_hash:
-        print(drop_source_hash())
+        for k in KERNEL_SOURCES:
+            print(k, source_hash(k))
         return
 
     if args.gpus != 1:
@@ -330,9 +334,7 @@ def main():
                     frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_ms=k1_ms,
                     algorithmic_per_launch=per_launch)
     roof["per_cycle_ms"] = per_cycle
-    key = f"{w.name}/{H}/B{args.block}/{args.path_mode}"
-    if dom == "k_drop_tile":
-        roof["traffic"] = measured_traffic(key)
+    roof["traffic"] = measured_traffic(dom, f"{w.name}/{H}/B{args.block}/{args.path_mode}")
 
     forms = {}
     for form in [f for f in args.forms.split(",") if f]:
