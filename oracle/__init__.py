@@ -109,6 +109,13 @@ def lib():
                                      C.POINTER(C.c_int64), C.POINTER(OrStepLog), C.c_int64,
                                      C.POINTER(C.c_int32), C.c_int64]
         L.or_superiorize.restype = C.c_int64
+        ip = C.POINTER(C.c_int64)
+        L.or_fbp_bin.argtypes = [C.POINTER(OrGrid), C.POINTER(OrHist), C.c_int64, C.c_int32,
+                                 C.c_double, C.c_int32, dp, ip]
+        L.or_fbp_filter.argtypes = [dp, C.c_int64, C.c_int32, C.c_double, dp]
+        L.or_fbp_backproject.argtypes = [C.POINTER(OrGrid), dp, C.c_int32, C.c_double, C.c_int32,
+                                         dp]
+        L.or_median_slices.argtypes = [C.POINTER(OrGrid), dp, C.c_int32, dp]
         _lib = L
     return _lib
 
@@ -273,3 +280,59 @@ class Superiorizer:
                      worst_margin=r.worst_margin) for r in logs[:min(n, cap)]]
         self.steps.extend(recs)
         return recs
+
+
+# --------------------------------------------------------------------------- initial iterate
+def fbp_lateral_bins(grid, tau):
+    """Lateral bins covering the grid: 2 * ceil(R / tau) + 2, R the largest
+    distance of a slice corner from the rotation axis."""
+    xs = (float(grid.ox), float(grid.ox) + grid.nx * float(grid.vx))
+    ys = (float(grid.oy), float(grid.oy) + grid.ny * float(grid.vy))
+    R = max(np.hypot(x, y) for x in xs for y in ys)
+    return 2 * int(np.ceil(R / tau)) + 2
+
+
+def fbp_bin(grid, hist, A, tau, nt):
+    """Mean WEPL per (angle, slice, lateral) bin, and the bins' history counts."""
+    hs, keep = _hist_struct(hist)
+    nh = len(keep["ex"])
+    p = np.zeros(A * grid.nz * nt, np.float64)
+    cnt = np.zeros(A * grid.nz * nt, np.int64)
+    lib().or_fbp_bin(C.byref(_grid(grid)), C.byref(hs), nh, int(A), float(tau), int(nt), _dp(p),
+                     cnt.ctypes.data_as(C.POINTER(C.c_int64)))
+    return p, cnt
+
+
+def fbp_filter(p, nt, tau):
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    q = np.zeros_like(p)
+    lib().or_fbp_filter(_dp(p), p.size // nt, int(nt), float(tau), _dp(q))
+    return q
+
+
+def fbp_backproject(grid, q, A, tau, nt):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    x = np.zeros(grid.nvox, np.float64)
+    lib().or_fbp_backproject(C.byref(_grid(grid)), _dp(q), int(A), float(tau), int(nt), _dp(x))
+    return x
+
+
+def median_slices(grid, x, r):
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    y = np.zeros_like(x)
+    lib().or_median_slices(C.byref(_grid(grid)), _dp(x), int(r), _dp(y))
+    return y
+
+
+def fbp_initial(grid, hist, A, tau=None, median_r=2, clip=True):
+    """Initial iterate: FBP of the binned histories, negatives set to 0
+    (clip), then the in-slice median of radius median_r (0: none)."""
+    tau = float(grid.vx) if tau is None else float(tau)
+    nt = fbp_lateral_bins(grid, tau)
+    p, _ = fbp_bin(grid, hist, A, tau, nt)
+    x = fbp_backproject(grid, fbp_filter(p, nt, tau), A, tau, nt)
+    if clip:
+        x = np.maximum(x, 0.0)
+    if median_r > 0:
+        x = median_slices(grid, x, median_r)
+    return x

@@ -706,3 +706,142 @@ int64_t or_superiorize(const or_grid *g, const or_system *sys, double *x,
     free(z);
     return nlog;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Initial iterate: filtered backprojection of binned histories and an       */
+/* in-slice median filter.  The paper starts its reconstructions from an     */
+/* initial iterate with a median filter of radius 2 applied (Section III-E,  */
+/* citing earlier work); the backprojection itself is not given there.      */
+/* Reading: textbook parallel-beam FBP.  Each history's straight line from    */
+/* entry to exit is binned at its crossing of the depth u = 0 (the rotation  */
+/* axis): angle bin a = round(phi / (2 pi / A)) mod A of the beam direction, */
+/* lateral bin m of t in width tau (nt bins centred on t = 0), slice k of    */
+/* the height v.  A bin's projection is the mean WEPL of its histories      */
+/* (0 when empty).  Rows are filtered with the discrete Ram-Lak kernel       */
+/* h(0) = 1/(4 tau^2), h(n odd) = -1/(n^2 pi^2 tau^2), h(n even) = 0, times */
+/* tau, and backprojected with linear interpolation and weight pi / A (A    */
+/* angles over 360 degrees see every line twice).  Median: lower median of  */
+/* the (2r+1)^2 window clipped to the slice.                                */
+/* ------------------------------------------------------------------------ */
+#define OR_FBP_FIXED 4294967296.0   /* WEPL sums in units of 2^-32 mm */
+
+static const double or_pi = 3.14159265358979323846;
+
+/* Bin index (a, k, m) of one history, or -1 when it falls outside. */
+static int64_t or_fbp_bin_index(const or_grid *g, const double h[12], int32_t A, double tau,
+                                int32_t nt)
+{
+    double ex = h[0], ey = h[1], ez = h[2], qx = h[3], qy = h[4], qz = h[5];
+    double ux = h[10], uy = h[11];
+    double nrm = sqrt(ux * ux + uy * uy);
+    ux = ux / nrm;
+    uy = uy / nrm;
+    double u0 = ex * ux + ey * uy, t0 = -ex * uy + ey * ux;
+    double u2 = qx * ux + qy * uy, t2 = -qx * uy + qy * ux;
+    double L = u2 - u0;
+    if (!(L > 0.0)) return -1;
+    double f = (0.0 - u0) / L;
+    double tc = t0 + (t2 - t0) * f;
+    double vc = ez + (qz - ez) * f;
+    double phi = atan2(uy, ux);
+    double da = 2.0 * or_pi / (double)A;
+    int64_t a = (int64_t)floor(phi / da + 0.5);
+    a %= A;
+    if (a < 0) a += A;
+    double mm = floor(tc / tau + 0.5 * (double)nt);
+    if (!(mm >= 0.0 && mm < (double)nt)) return -1;
+    double kk = floor((vc - g->oz) / g->vz);
+    if (!(kk >= 0.0 && kk < (double)g->nz)) return -1;
+    return (a * g->nz + (int64_t)kk) * nt + (int64_t)mm;
+}
+
+/* Projections p[(a * nz + k) * nt + m]: mean WEPL per bin; counts too. */
+void or_fbp_bin(const or_grid *g, const or_hist *H, int64_t nh, int32_t A, double tau,
+                int32_t nt, double *p, int64_t *count)
+{
+    int64_t nb = (int64_t)A * g->nz * nt;
+    int64_t *sum = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+    for (int64_t b = 0; b < nb; b++) count[b] = 0;
+    for (int64_t i = 0; i < nh; i++) {
+        double h[12];
+        or_hist_get(H, i, h);
+        int64_t b = or_fbp_bin_index(g, h, A, tau, nt);
+        if (b < 0) continue;
+        sum[b] += (int64_t)llrint((double)H->wepl[i] * OR_FBP_FIXED);
+        count[b] += 1;
+    }
+    for (int64_t b = 0; b < nb; b++)
+        p[b] = count[b] ? ((double)sum[b] / OR_FBP_FIXED) / (double)count[b] : 0.0;
+    free(sum);
+}
+
+/* Ram-Lak filtered rows: q[r * nt + m] = tau * sum_s p[r * nt + s] h(m - s). */
+void or_fbp_filter(const double *p, int64_t rows, int32_t nt, double tau, double *q)
+{
+    for (int64_t r = 0; r < rows; r++)
+        for (int32_t m = 0; m < nt; m++) {
+            double acc = 0.0;
+            for (int32_t s = 0; s < nt; s++) {
+                int32_t n = m - s;
+                double hv;
+                if (n == 0) hv = 1.0 / (4.0 * tau * tau);
+                else if (n % 2 != 0) hv = -1.0 / ((double)n * (double)n * or_pi * or_pi * tau * tau);
+                else continue;
+                acc += p[r * nt + s] * hv;
+            }
+            q[r * nt + m] = tau * acc;
+        }
+}
+
+/* Backprojection into the x-fastest image x (nx * ny * nz). */
+void or_fbp_backproject(const or_grid *g, const double *q, int32_t A, double tau, int32_t nt,
+                        double *x)
+{
+    double da = 2.0 * or_pi / (double)A;
+    for (int64_t k = 0; k < g->nz; k++)
+        for (int64_t j = 0; j < g->ny; j++)
+            for (int64_t i = 0; i < g->nx; i++) {
+                double X = g->ox + ((double)i + 0.5) * g->vx;
+                double Y = g->oy + ((double)j + 0.5) * g->vy;
+                double acc = 0.0;
+                for (int32_t a = 0; a < A; a++) {
+                    double phi = (double)a * da;
+                    double t = -X * sin(phi) + Y * cos(phi);
+                    double sp = t / tau + 0.5 * (double)nt - 0.5;
+                    double m0 = floor(sp);
+                    double w = sp - m0;
+                    const double *row = q + ((int64_t)a * g->nz + k) * nt;
+                    double v0 = (m0 >= 0.0 && m0 < (double)nt) ? row[(int64_t)m0] : 0.0;
+                    double v1 = (m0 + 1.0 >= 0.0 && m0 + 1.0 < (double)nt) ? row[(int64_t)m0 + 1] : 0.0;
+                    acc += (1.0 - w) * v0 + w * v1;
+                }
+                x[i + g->nx * (j + g->ny * k)] = acc * (or_pi / (double)A);
+            }
+}
+
+static int or_cmp_double_asc(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x < y) ? -1 : (x > y) ? 1 : 0;
+}
+
+/* In-slice median of radius r (window clipped to the slice, lower median). */
+void or_median_slices(const or_grid *g, const double *x, int32_t r, double *y)
+{
+    int32_t w = 2 * r + 1;
+    double *buf = (double *)malloc(sizeof(double) * (size_t)(w * w));
+    for (int64_t k = 0; k < g->nz; k++)
+        for (int64_t j = 0; j < g->ny; j++)
+            for (int64_t i = 0; i < g->nx; i++) {
+                int n = 0;
+                for (int64_t dj = -r; dj <= r; dj++)
+                    for (int64_t di = -r; di <= r; di++) {
+                        int64_t ii = i + di, jj = j + dj;
+                        if (ii < 0 || ii >= g->nx || jj < 0 || jj >= g->ny) continue;
+                        buf[n++] = x[ii + g->nx * (jj + g->ny * k)];
+                    }
+                qsort(buf, (size_t)n, sizeof(double), or_cmp_double_asc);
+                y[i + g->nx * (j + g->ny * k)] = buf[(n - 1) / 2];
+            }
+    free(buf);
+}
