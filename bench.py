@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--serve-path", default="f32")
+    ap.add_argument("--fbp", action="store_true",
+                    help="also time the initial iterate (FBP + median) of all histories")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 256 MiB read + 256 MiB write kernel (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -287,7 +289,8 @@ def main():
     torch.cuda.synchronize()
     step_mm = min(w.grid.vx, w.grid.vy)
     vertices = mlp_vertices(h, step_mm)
-    del h
+    if not args.fbp:
+        del h
 
     log(f"timing {args.path_mode}: warmup {args.warmup}, steps {args.steps}")
     ctx, st, dt, load_s = run_form(tvs, torch, w, dev, x0, args, args.path_mode, args.steps,
@@ -305,6 +308,29 @@ def main():
         ctx.iterate(1, args.lam, args.N, args.alpha, tv_check=args.check, seed=args.seed)
         torch.cuda.synchronize()
         lat.append(1e3 * (time.perf_counter() - t0))
+
+    # initial iterate: FBP of all histories + radius-2 median, timed on the
+    # device (returned to the host), the oracle's on a bounded prefix
+    fbp = None
+    if args.fbp:
+        tms = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.initial_fbp(w.n_angles, median_radius=2)
+            tms.append(time.perf_counter() - t0)
+        fbp = dict(ms=1e3 * min(tms), unit="ms per initial iterate", histories=H,
+                   n_angles=w.n_angles, median_radius=2)
+        if not args.no_cpu:
+            import oracle
+            n = min(H, args.cpu_sample * 10)
+            hs = {k: v[:n] for k, v in h.items()}
+            t0 = time.perf_counter()
+            oracle.fbp_initial(w.grid, hs, w.n_angles, median_r=2)
+            fbp["cpu_oracle"] = dict(seconds=time.perf_counter() - t0, histories=n, cores=1,
+                                     kind="oracle")
+        log(f"fbp: {fbp}")
+        del h
     ctx.close()
 
     # dominant kernel of the timed region: the DROP step (one launch per
@@ -402,6 +428,7 @@ def main():
         "roofline": roof,
         "forms": forms,
         "batch": batch,
+        "fbp": fbp,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -225,6 +225,31 @@ int tvs_iterate_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, int32_t K, v
  * TVS_ERANGE for s outside the batch, TVS_ESTATE without a batch. */
 int tvs_get_batch_image(tvs_ctx *ctx, int32_t s, float *out, int on_device, void *stream);
 
+/* Initial iterate by filtered backprojection (FBP) of the loaded histories,
+ * then an in-slice median filter.  The paper starts each reconstruction from
+ * a median-filtered initial iterate, radius 2 (arXiv 1803.01112, Section
+ * III-E, citing earlier work for how it is formed); the form here is the
+ * textbook parallel-beam one: every history's straight line from entry to
+ * exit is binned where it crosses the rotation axis (depth u = 0) by beam
+ * angle (A bins over 360 degrees), lateral position (bins of width t_bin_mm
+ * centred on the axis, enough to cover the grid) and slice; a bin holds the
+ * mean WEPL of its histories; rows are filtered with the discrete Ram-Lak
+ * kernel and backprojected with linear interpolation.  The result becomes
+ * the context image, as by tvs_set_image (schedule and batch reset), and is
+ * also copied to out (nx * ny * nz float32, x fastest, host or device) when
+ * out is not NULL.  Waits for the work.  TVS_EINVAL for n_angles < 1,
+ * t_bin_mm < 0 or median_radius outside 0..2; TVS_ESTATE before
+ * tvs_load_histories; TVS_ENOMEM when the bins do not fit the budget. */
+typedef struct {
+    int32_t n_angles;       /* A, beam angles evenly spaced over 360 degrees */
+    int32_t median_radius;  /* 0 (none) .. 2; the paper's initial iterate uses 2 */
+    double t_bin_mm;        /* lateral bin width; 0: the grid's vx */
+    int32_t clip_negative;  /* 1: negative values set to 0 before the median */
+    int32_t pad;
+} tvs_fbp_params;
+
+int tvs_initial_fbp(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_device, void *stream);
+
 /* Counters and timings of the context. */
 int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out);
 

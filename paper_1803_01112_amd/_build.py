@@ -23,6 +23,7 @@ SOURCES = {
     "drop.hip": ["-ffp-contract=off"],
     "tv.hip": ["-ffp-contract=off"],
     "batch.hip": ["-ffp-contract=off"],
+    "fbp.hip": ["-ffp-contract=off"],
     "serve.cpp": ["-x", "hip"],
     "tvs_api.cpp": ["-x", "hip"],
 }

@@ -960,6 +960,85 @@ int tvs_set_image(tvs_ctx *ctx, const float *x0, int on_device, void *stream)
     return TVS_OK;
 }
 
+int tvs_initial_fbp(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_device, void *stream)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    if (!p) return fail(ctx, TVS_EINVAL, "params is NULL");
+    if (p->n_angles < 1) return fail(ctx, TVS_EINVAL, "n_angles must be >= 1");
+    if (!(p->t_bin_mm >= 0.0) || !std::isfinite(p->t_bin_mm))
+        return fail(ctx, TVS_EINVAL, "t_bin_mm must be finite and >= 0");
+    if (p->median_radius < 0 || p->median_radius > 2)
+        return fail(ctx, TVS_EINVAL, "median_radius must lie in 0..2");
+    if (!ctx->loaded) return fail(ctx, TVS_ESTATE, "tvs_initial_fbp before tvs_load_histories");
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    const tvs_grid &g = ctx->grid;
+    const double tau = p->t_bin_mm > 0.0 ? p->t_bin_mm : g.vx;
+    // lateral bins: 2 ceil(R / tau) + 2, R the farthest slice corner from the axis
+    double R = 0.0;
+    for (int cx = 0; cx < 2; cx++)
+        for (int cy = 0; cy < 2; cy++)
+            R = std::max(R, std::hypot(g.ox + cx * g.nx * g.vx, g.oy + cy * g.ny * g.vy));
+    const double ntd = 2.0 * std::ceil(R / tau) + 2.0;
+    if (!(ntd <= 16777216.0)) return fail(ctx, TVS_EINVAL, "t_bin_mm too small for the grid");
+    const int32_t nt = (int32_t)ntd, A = p->n_angles;
+    const int64_t nb = (int64_t)A * g.nz * nt;
+
+    unsigned long long *sum = nullptr;
+    uint32_t *cnt = nullptr;
+    double *pb = nullptr, *qb = nullptr, *cs = nullptr, *img = nullptr;
+    auto release = [&]() {
+        dfree(ctx, &sum, (size_t)nb);
+        dfree(ctx, &cnt, (size_t)nb);
+        dfree(ctx, &pb, (size_t)nb);
+        dfree(ctx, &qb, (size_t)nb);
+        dfree(ctx, &cs, (size_t)(2 * A));
+        dfree(ctx, &img, (size_t)ctx->nimg);
+    };
+    int rc = dalloc(ctx, &sum, (size_t)nb);
+    if (!rc) rc = dalloc(ctx, &cnt, (size_t)nb);
+    if (!rc) rc = dalloc(ctx, &pb, (size_t)nb);
+    if (!rc) rc = dalloc(ctx, &qb, (size_t)nb);
+    if (!rc) rc = dalloc(ctx, &cs, (size_t)(2 * A));
+    if (!rc) rc = dalloc(ctx, &img, (size_t)ctx->nimg);
+    if (rc) {
+        release();
+        return rc;
+    }
+    // cos, sin of every beam angle a * 2 pi / A
+    std::vector<double> tab((size_t)(2 * A));
+    const double da = 2.0 * 3.14159265358979323846 / (double)A;
+    for (int32_t a = 0; a < A; a++) {
+        const double phi = (double)a * da;
+        tab[(size_t)(2 * a)] = std::cos(phi);
+        tab[(size_t)(2 * a + 1)] = std::sin(phi);
+    }
+    hipError_t e = hipMemsetAsync(sum, 0, sizeof(unsigned long long) * nb, st);
+    if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(cs, tab.data(), sizeof(double) * 2 * A, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = tvs::launch_fbp_bin(ctx->gd, hist_dev(ctx), ctx->nh, A, tau, nt, sum, cnt, st);
+    if (e == hipSuccess) e = tvs::launch_fbp_mean(sum, cnt, nb, pb, st);
+    if (e == hipSuccess) e = tvs::launch_fbp_filter(pb, (int64_t)A * g.nz, nt, tau, qb, st);
+    if (e == hipSuccess)
+        e = tvs::launch_fbp_backproject(ctx->gd, qb, cs, A, tau, nt, p->clip_negative ? 1 : 0, img, st);
+    if (e == hipSuccess) e = tvs::launch_median(ctx->gd, img, p->median_radius, ctx->xio, st);
+    // the result becomes the context image, as by tvs_set_image
+    if (e == hipSuccess) e = tvs::launch_widen(ctx->gd, ctx->xio, ctx->x, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->x0, ctx->x, sizeof(double) * ctx->nvox, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->flags + kFlagRange, 0, sizeof(uint32_t), st);
+    if (e == hipSuccess && out)
+        e = hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nimg,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    release();
+    if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("initial fbp: ") + hipGetErrorString(e));
+    reset_state(ctx);
+    ctx->batch.valid = false;
+    return TVS_OK;
+}
+
 int tvs_iterate(tvs_ctx *ctx, const tvs_params *p, int32_t K, void *stream)
 {
     if (!ctx) return TVS_EINVAL;

@@ -172,6 +172,18 @@ hipError_t launch_scan(const int32_t *cnt, int64_t n, int64_t *off, int64_t *tmp
 hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *bad,
                            uint32_t *jmax, hipStream_t stream);
 // dst[b] = src[b * stride] for b < n.
+// Initial iterate (fbp.hip): binning, Ram-Lak filter, backprojection,
+// in-slice median (radius 0..2; 0 only narrows the image to float32).
+hipError_t launch_fbp_bin(const GridDev &g, const HistDev &h, int64_t n, int32_t A, double tau,
+                          int32_t nt, unsigned long long *sum, uint32_t *cnt, hipStream_t stream);
+hipError_t launch_fbp_mean(const unsigned long long *sum, const uint32_t *cnt, int64_t nb, double *p,
+                           hipStream_t stream);
+hipError_t launch_fbp_filter(const double *p, int64_t rows, int32_t nt, double tau, double *q,
+                             hipStream_t stream);
+hipError_t launch_fbp_backproject(const GridDev &g, const double *q, const double *cs, int32_t A,
+                                  double tau, int32_t nt, int clip, double *x, hipStream_t stream);
+hipError_t launch_median(const GridDev &g, const double *x, int radius, float *out,
+                         hipStream_t stream);
 hipError_t launch_pick(const int64_t *src, int64_t stride, int64_t n, int64_t *dst,
                        hipStream_t stream);
 // Fills the entry-side table of m for depths j = 0 .. nj - 1 (3 doubles each).

@@ -26,7 +26,7 @@ EXPORTED = ("tvs_config_default", "tvs_create", "tvs_destroy", "tvs_load_histori
             "tvs_debug_rows", "tvs_strerror", "tvs_last_error", "tvs_iterate_batch",
             "tvs_get_batch_image", "tvs_server_config_default", "tvs_server_create",
             "tvs_server_footprint", "tvs_server_submit", "tvs_server_query", "tvs_server_wait",
-            "tvs_server_get_counters", "tvs_server_destroy", "tvs_autotune")
+            "tvs_server_get_counters", "tvs_server_destroy", "tvs_autotune", "tvs_initial_fbp")
 
 
 class TvsError(RuntimeError):
@@ -61,6 +61,11 @@ class Params(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("N", C.c_int32), ("alpha", C.c_double),
                 ("tv_check", C.c_int32), ("variant", C.c_int32), ("tv_eps", C.c_double),
                 ("seed", C.c_uint64), ("gamma", C.c_double)]
+
+
+class FbpParams(C.Structure):
+    _fields_ = [("n_angles", C.c_int32), ("median_radius", C.c_int32), ("t_bin_mm", C.c_double),
+                ("clip_negative", C.c_int32), ("pad", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -140,6 +145,7 @@ def load_library(path: str = LIB):
     L.tvs_get_stats.argtypes = [C.c_void_p, P(Stats)]
     L.tvs_iterate_batch.argtypes = [C.c_void_p, P(Params), C.c_int32, C.c_int32, C.c_void_p]
     L.tvs_get_batch_image.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int, C.c_void_p]
+    L.tvs_initial_fbp.argtypes = [C.c_void_p, P(FbpParams), C.c_void_p, C.c_int, C.c_void_p]
     L.tvs_get_step_log.argtypes = [C.c_void_p, P(StepLog), C.c_int64, P(C.c_int64)]
     L.tvs_debug_rows.argtypes = [C.c_void_p, C.c_int64, C.c_int64, P(C.c_int64), P(C.c_int32),
                                  _FP, _FP, C.c_int64]
@@ -339,6 +345,26 @@ class Context:
             return out
         self._check(self._L.tvs_get_image(self._h, C.c_void_p(out.ctypes.data), 0,
                                           _stream_handle(stream)), "tvs_get_image")
+        return out
+
+    def initial_fbp(self, n_angles, median_radius=2, t_bin_mm=0.0, clip_negative=True, out=None,
+                    stream=None):
+        """Initial iterate by filtered backprojection of the loaded histories and
+        an in-slice median (tvs_initial_fbp); it becomes the context image.
+        Returns it (float32, x fastest) in `out` (host array or device tensor)
+        or a new host array."""
+        prm = FbpParams(int(n_angles), int(median_radius), float(t_bin_mm), int(bool(clip_negative)), 0)
+        if out is None:
+            out = np.zeros(self.nvox, np.float32)
+        if _is_device(out):
+            self._check(self._L.tvs_initial_fbp(self._h, C.byref(prm), C.c_void_p(out.data_ptr()), 1,
+                                                _stream_handle(stream)), "tvs_initial_fbp")
+            return out
+        buf = np.ascontiguousarray(out, dtype=np.float32)
+        self._check(self._L.tvs_initial_fbp(self._h, C.byref(prm), buf.ctypes.data_as(C.c_void_p), 0,
+                                            _stream_handle(stream)), "tvs_initial_fbp")
+        if buf is not out:
+            out[...] = buf.reshape(out.shape)
         return out
 
     def stats(self) -> dict:

@@ -36,6 +36,11 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(names) == set(tvs.EXPORTED)
 
 
+def test_initial_fbp_rejects_a_null_context(lib):
+    prm = tvs.FbpParams(90, 2, 0.0, 1, 0)
+    assert lib.tvs_initial_fbp(None, C.byref(prm), None, 0, None) == tvs.TVS_EINVAL
+
+
 def test_status_strings(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.tvs_strerror(code).decode()
