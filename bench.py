@@ -140,6 +140,44 @@ def cpu_baseline(w, args, cores):
                        f"N={args.N} TV steps and one DROP sweep (single thread); {el:.1f} s")
 
 
+def precision_report(tvs, torch, args):
+    """Image error of each path form against the oracle on the two-slice
+    sub-problem of the 256x256x32 phantom (slab256: 256x256x2 voxels of
+    1x1x2.5 mm, 3.75M histories at 360 angles, B = 3200), K cycles at the
+    benchmark's lambda, N, alpha: max and RMS of |x - x_oracle| /
+    max(|x_oracle|, 0.1), and the largest change of a 7 mm insert ROI mean."""
+    import oracle
+    from paper_1803_01112_amd import quality, synth
+    w = synth.workload("slab256", n_hist=args.precision_hist)
+    h = w.histories()
+    x0 = w.initial_image()
+    K = args.precision_cycles
+    kw = dict(lam=args.lam, N=args.N, alpha=args.alpha, seed=args.seed)
+    t0 = time.perf_counter()
+    rows = oracle.build_rows(w.grid, h, min(w.grid.vx, w.grid.vy))
+    S = oracle.Superiorizer(w.grid, rows, x0, args.block)
+    S.iterate(K, **kw)
+    t_or = time.perf_counter() - t0
+    del rows
+    ref = S.x
+    roi_ref = [q["mean"] for q in quality.measure(ref, w.grid, w.phantom)["rois"]]
+    dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in h.items()}
+    out = dict(workload=f"{w.name}: {w.grid.nx}x{w.grid.ny}x{w.grid.nz}, {w.n_hist} histories",
+               cycles=K, oracle_seconds=t_or, forms={})
+    for form in ("f32", "f16", "otf"):
+        with tvs.Context(w.grid, block_size=args.block, path_mode=form) as ctx:
+            ctx.load_histories(dev)
+            ctx.set_image(x0)
+            ctx.iterate(K, **kw)
+            x = ctx.get_image().astype(np.float64)
+        e = np.abs(x - ref) / np.maximum(np.abs(ref), 0.1)
+        roi = [q["mean"] for q in quality.measure(x, w.grid, w.phantom)["rois"]]
+        out["forms"][form] = dict(max_rel=float(e.max()), rms_rel=float(np.sqrt(np.mean(e * e))),
+                                  max_roi_mean_delta=float(np.max(np.abs(np.subtract(roi, roi_ref)))))
+        log(f"precision {form}: {out['forms'][form]}")
+    return out
+
+
 def batch_settings():
     """24 settings: lambda in {1e-4, 2e-4} x N in {1, 3, 6} x alpha in {0.5, 0.75, 0.85, 0.95}."""
     out = []
@@ -259,6 +297,11 @@ def main():
     ap.add_argument("--serve-path", default="f32")
     ap.add_argument("--fbp", action="store_true",
                     help="also time the initial iterate (FBP + median) of all histories")
+    ap.add_argument("--precision", action="store_true",
+                    help="also report each path form's image error against the oracle on the "
+                         "two-slice sub-problem of the 256x256x32 phantom")
+    ap.add_argument("--precision-hist", type=int, default=3_750_000)
+    ap.add_argument("--precision-cycles", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 256 MiB read + 256 MiB write kernel (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -396,6 +439,11 @@ def main():
         log("copy calibration: 268435456 bytes read, 268435456 bytes written")
         del a, b
 
+    precision = None
+    if args.precision:
+        log("precision report")
+        precision = precision_report(tvs, torch, args)
+
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cpu = None if args.no_cpu else cpu_baseline(w, args, cores)
 
@@ -429,6 +477,7 @@ def main():
         "forms": forms,
         "batch": batch,
         "fbp": fbp,
+        "precision": precision,
         "serving": serving,
         "cpu_baseline": cpu,
     }
