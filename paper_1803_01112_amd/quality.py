@@ -173,6 +173,9 @@ def main(argv=None):
     ap.add_argument("--block", type=int, default=3200)
     ap.add_argument("--path-mode", default="f32")
     ap.add_argument("--seeds", type=int, default=4)
+    ap.add_argument("--initial", default="flat", choices=("flat", "fbp"),
+                    help="start from the hull-masked flat image or from the FBP initial "
+                         "iterate with a radius-2 median (tvs_initial_fbp)")
     ap.add_argument("--out", default=None, help="write the records as JSON here")
     args = ap.parse_args(argv)
 
@@ -181,17 +184,21 @@ def main(argv=None):
     w = synth.workload(args.workload, n_hist=args.n_hist)
     h = w.histories()
     dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in h.items()}
-    x0 = w.initial_image()
     settings = paper_grid(args.seeds)
     ctx = tvs.Context(w.grid, block_size=args.block, path_mode=args.path_mode)
     ctx.load_histories(dev)
+    if args.initial == "fbp":
+        x0 = ctx.initial_fbp(w.n_angles, median_radius=2)
+    else:
+        x0 = w.initial_image()
+    x0_measure = measure(x0, w.grid, w.phantom)
     t0 = time.perf_counter()
     recs = run_study(ctx, w.grid, w.phantom, x0, settings, args.cycles)
     dt = time.perf_counter() - t0
     ctx.close()
     summ = summarize(recs, settings)
     summ.update(workload=w.name, n_hist=w.n_hist, cycles=args.cycles, settings=len(settings),
-                seconds=dt)
+                seconds=dt, initial=args.initial, initial_measure=x0_measure)
     if args.out:
         with open(args.out, "w") as fh:
             json.dump(dict(summary=summ, records=recs), fh)
