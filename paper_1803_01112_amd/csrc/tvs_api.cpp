@@ -383,8 +383,11 @@ int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st, int64_t limit = -1)
     const int64_t nchunks = (nh_run + step - 1) / step;
     hipStream_t fs = ctx->fill_stream;
     HIPCHK(tvs::launch_zero_i64(ctx->dot, 3 * B, st));
+    // a chunk is always formed whole, also when the sweep stops inside it:
+    // its rows are formed in length order, so the first n of them are not
+    // the histories of the first blocks
     auto fill = [&](int64_t c) -> int {
-        const int64_t n = std::min(step, nh_run - c * step);
+        const int64_t n = std::min(step, ctx->nh - c * step);
         tvs::TileFill f = chunk_fill(ctx, c, n);
         HIPCHK(hipStreamWaitEvent(fs, ctx->ev_free[c & 1], 0));
         long a = mark(ctx, fs);
