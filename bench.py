@@ -458,7 +458,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.grid.nx}x{w.grid.ny}x{w.grid.nz} voxels of "
                                f"{w.grid.vx}x{w.grid.vy}x{w.grid.vz} mm, {w.diameter:.0f} mm "
