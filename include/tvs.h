@@ -83,9 +83,10 @@ typedef struct {
                                 (64, 128, 256); 0: 256 */
     int32_t time_sample;     /* k > 0: kernel-stamped HIP events on the launches of every
                                 k-th DROP block (per-launch durations in tvs_stats); 0: off */
-    int32_t fill_wgs_per_cu; /* on-the-fly rows: workgroups per compute unit of the row
-                                formation that runs beside the DROP chain (the rest of each
-                                CU stays free for it); 0: 2; < 0: no limit */
+    int32_t fill_wgs_per_cu; /* on-the-fly rows: cap on the workgroups per compute unit of
+                                the row formation that runs beside the DROP chain; 0 or < 0:
+                                no cap (its register budget already leaves every SIMD room
+                                for the DROP step's waves) */
     int32_t pad;
 } tvs_config;
 

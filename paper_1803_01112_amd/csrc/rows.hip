@@ -22,9 +22,11 @@ namespace {
 constexpr double kE0 = 13.6;     // MeV, Highland constant
 constexpr double kX0 = 360.8;    // mm, radiation length of water
 constexpr int kThreads = 256;
-// Row kernels: hold the register budget to 3 wavefronts per SIMD (168
-// VGPRs), enough to overlap the float64 latency of one lane's walk.
-constexpr int kRowWaves = 3;
+__device__ const double kZero3[3] = {0.0, 0.0, 0.0};
+// Row kernels: a budget of 2 wavefronts per SIMD (the two vertices a lane
+// evaluates side by side need ~180 VGPRs); beside the sweep's row formation
+// this leaves room on every SIMD for the DROP step's waves.
+constexpr int kRowWaves = 2;
 // List entries staged per lane before they are written (LDS: 8 bytes each,
 // 32 KB per 256-lane workgroup with float32 chords).
 constexpr int kStage = 16;
@@ -379,23 +381,20 @@ __device__ void form_row(const GridDev &g, const HistDev &H, const MlpCfg &m, in
         c[k] = (k % 2) ? -acc : acc;
     }
 
-    double prevp[3] = {ex, ey, ez};
-    double prevg[3];
-    to_grid(g, prevp, prevg);
-    for (int64_t j = 1; j < J; j++) {
+    bool miss = false;
+    // MLP vertex j (1 <= j < J); the table index is clamped and a depth past
+    // the table only noted, so that the body has no branch and two vertices
+    // can be evaluated side by side
+    auto vertex = [&](int64_t j, double p[3]) {
         double d1 = (double)j * m.step;
         double d2 = L - d1;
-        // the table covers every depth of the loaded histories (their vertex
-        // counts bound it); a depth past it raises the consistency flag
-        double s1[3] = {0.0, 0.0, 0.0};
-        if (j < m.nj) {
-            s1[0] = m.s1i[3 * j];
-            s1[1] = m.s1i[3 * j + 1];
-            s1[2] = m.s1i[3 * j + 2];
-        } else if (m.err) {
-            atomicOr(m.err, 1u);
-        }
-        // powers d2^e as the running product 1 * d2 * d2 ... (as ipow forms them)
+        // (the table covers every depth of the loaded histories, their
+        // vertex counts bound it; a depth past it raises the consistency
+        // flag, and an empty table is never indexed)
+        const bool in_tab = j < m.nj;
+        miss |= !in_tab;
+        const double *tab = m.nj > 0 ? m.s1i + 3 * (in_tab ? j : m.nj - 1) : kZero3;
+        double s1[3] = {tab[0], tab[1], tab[2]};
         double pw[9];
         pw[0] = 1.0;
 #pragma unroll
@@ -439,8 +438,31 @@ __device__ void form_row(const GridDev &g, const HistDev &H, const MlpCfg &m, in
             y1v = y0_;
         }
         double u = u0 + d1;
-        double p[3] = {u * ux - y1t * uy, u * uy + y1t * ux, y1v};
-        double pg[3];
+        p[0] = u * ux - y1t * uy;
+        p[1] = u * uy + y1t * ux;
+        p[2] = y1v;
+    };
+
+    double prevp[3] = {ex, ey, ez};
+    double prevg[3];
+    to_grid(g, prevp, prevg);
+    int64_t j = 1;
+    for (; j + 1 < J; j += 2) {
+        double pa[3], pb[3], ga[3], gb[3];
+        vertex(j, pa);
+        vertex(j + 1, pb);
+        to_grid(g, pa, ga);
+        to_grid(g, pb, gb);
+        walk_segment<MODE, CH>(g, prevp, pa, prevg, ga, e);
+        walk_segment<MODE, CH>(g, pa, pb, ga, gb, e);
+        for (int a = 0; a < 3; a++) {
+            prevp[a] = pb[a];
+            prevg[a] = gb[a];
+        }
+    }
+    if (j < J) {
+        double p[3], pg[3];
+        vertex(j, p);
         to_grid(g, p, pg);
         walk_segment<MODE, CH>(g, prevp, p, prevg, pg, e);
         for (int a = 0; a < 3; a++) {
@@ -448,6 +470,7 @@ __device__ void form_row(const GridDev &g, const HistDev &H, const MlpCfg &m, in
             prevg[a] = pg[a];
         }
     }
+    if (miss && m.err) atomicOr(m.err, 1u);
     double last[3] = {qx, qy, qz};
     double lastg[3];
     to_grid(g, last, lastg);

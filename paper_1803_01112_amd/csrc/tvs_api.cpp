@@ -785,7 +785,7 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg.device) !=
             hipSuccess)
             cus = 0;
-        const int per_cu = cfg.fill_wgs_per_cu ? cfg.fill_wgs_per_cu : 2;
+        const int per_cu = cfg.fill_wgs_per_cu;
         ctx->fill_wgs = (per_cu > 0 && cus > 0) ? (int64_t)per_cu * cus : 0;
     }
 
