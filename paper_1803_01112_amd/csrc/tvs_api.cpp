@@ -648,7 +648,13 @@ int form_entries(tvs_ctx *ctx, hipStream_t st)
     }
     if (!rc && ctx->ch16) HIPCHK(hipMemsetAsync(ctx->ch16, 0, sizeof(__half) * ctx->cap, st));
     if (rc) return rc;
-    if (otf || ctx->nh == 0) return TVS_OK;
+    if (otf) {
+        // the first sweep's row formation runs on the fill stream: it must
+        // not start before these clears, or they overwrite formed entries
+        for (int q = 0; q < 2; q++) HIPCHK(hipEventRecord(ctx->ev_free[q], st));
+        return TVS_OK;
+    }
+    if (ctx->nh == 0) return TVS_OK;
     tvs::TileFill f;
     f.first = 0;
     f.n = ctx->nh;

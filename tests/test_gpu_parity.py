@@ -317,3 +317,27 @@ def test_rows_bitexact_vol200_sample():
             rows = oracle.build_rows(w.grid, h, 1.0)
             ctx.load_histories(h)
             check_rows(ctx, rows, 0, 2000)
+
+
+def test_first_sweep_after_device_load_large_chunks():
+    """With device-resident inputs nothing in loading or setting the image
+    waits on the host, so the first sweep's row formation (on its own
+    stream) follows the load's clears of the entry buffers only through
+    the library's own ordering.  On-the-fly images with large chunks, in
+    several contexts in a row, must equal the stored-path image exactly
+    (rows and sums are the same integers on both paths)."""
+    import torch
+    w = synth.workload("vol200", n_hist=4_000_000)
+    print("vol200, 4M histories, chunks of 2M", flush=True)
+    h = {k: torch.from_numpy(v).to("cuda:0") for k, v in w.histories().items()}
+    x0 = torch.from_numpy(w.initial_image()).to("cuda:0")
+    kw = dict(lam=1e-4, N=5, alpha=0.75, seed=1)
+    images = []
+    for mode, chunk in (("f32", 0), ("otf", 2_097_152), ("otf", 2_097_152), ("otf", 0)):
+        with tvs.Context(w.grid, block_size=3200, path_mode=mode, chunk_histories=chunk) as ctx:
+            ctx.load_histories(h)
+            ctx.set_image(x0)
+            ctx.iterate(1, **kw)
+            images.append(ctx.get_image())
+    for img in images[1:]:
+        np.testing.assert_array_equal(img, images[0])
