@@ -131,6 +131,12 @@ def load_library(path: str = LIB):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libtvs.so not built at {path}: run __graft_entry__.build() first")
+    # PyTorch's wheel carries its own HIP and HSA runtimes, which its
+    # libraries request under other file names than the system's.  Loaded
+    # first, they also serve libtvs (same sonames), so the process holds one
+    # runtime; loaded after libtvs, they would be a second runtime, and
+    # PyTorch would then find no GPU.
+    import torch  # noqa: F401
     L = C.CDLL(path)
     P = C.POINTER
     L.tvs_config_default.argtypes = [P(Config)]
