@@ -123,7 +123,7 @@ struct Emit {
     double cur_len = 0.0;
     double norm2 = 0.0;
     int64_t n = 0;               // entries emitted
-    int64_t nseg = 0;            // segments opened
+    int32_t nseg = 0;            // segments opened
     int32_t tile = -1;           // tile of the open segment
     uint32_t seg_len = 0;        // kSeg: entries of the open segment
     int32_t *idx = nullptr;      // kRowMajor
@@ -142,7 +142,8 @@ struct Emit {
     // kSeg, kTiled: guards against a walk that disagrees with the load-time
     // count (segments of this row, entries of the buffer); a disagreement
     // writes nothing and raises *err
-    int64_t seg_cap = 0, cap = 0;
+    int32_t seg_cap = 0;
+    int64_t cap = 0;
     uint32_t *err = nullptr;
     bool ok = true;
 
@@ -511,7 +512,7 @@ k_rows_seg(GridDev g, HistDev H, MlpCfg m, int64_t n, int64_t B, int64_t ntiles,
     Emit<kSeg, float> e;
     e.btc = btc + (i / B) * ntiles;
     e.segtab = segtab + seg_off[i];
-    e.seg_cap = seg_off[i + 1] - seg_off[i];
+    e.seg_cap = (int32_t)(seg_off[i + 1] - seg_off[i]);
     e.err = err;
     form_row<kSeg, float>(g, H, m, i, e);
     e.finish();
@@ -547,7 +548,7 @@ k_rows_fill_tiled(GridDev g, HistDev H, MlpCfg m, TileFill f, CH *chord)
         const int64_t i = f.order ? (int64_t)f.order[f.first + q] : f.first + q;
         Emit<kTiled, CH> e;
         e.segdst = f.segdst + f.seg_off[i];
-        e.seg_cap = f.seg_off[i + 1] - f.seg_off[i];
+        e.seg_cap = (int32_t)(f.seg_off[i + 1] - f.seg_off[i]);
         e.cap = f.cap;
         e.err = f.err;
         e.meta = f.meta;
