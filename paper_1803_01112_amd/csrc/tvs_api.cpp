@@ -537,8 +537,18 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
     ctx->nseg = nseg;
     ctx->nblocks = (n + B - 1) / B;
     int64_t chunk = ctx->cfg.chunk_histories;
-    if (chunk <= 0) chunk = std::max<int64_t>(B, ((int64_t)1 << 20) / B * B);
-    else chunk = (chunk + B - 1) / B * B;
+    if (chunk <= 0) {
+        // about 2^20 histories, as even as whole blocks allow: the row
+        // formation of the next sweep's first chunk waits for the DROP chain
+        // to leave that chunk's buffer, i.e. to finish the next-to-last chunk,
+        // so a small last chunk would leave the formation stream idle
+        const int64_t target = std::max<int64_t>(B, ((int64_t)1 << 20) / B * B);
+        const int64_t parts = std::max<int64_t>(1, (n + target - 1) / target);
+        chunk = ((n + parts - 1) / parts + B - 1) / B * B;
+        chunk = std::max<int64_t>(chunk, B);
+    } else {
+        chunk = (chunk + B - 1) / B * B;
+    }
     ctx->chunk = std::max<int64_t>(chunk, 1);
     for (int64_t f = 0; f < n; f += ctx->chunk) ctx->chunk_base.push_back(off[(size_t)f]);
     ctx->chunk_base.push_back(total);
