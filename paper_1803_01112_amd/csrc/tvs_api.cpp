@@ -794,7 +794,10 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     double step = cfg.mlp_step_mm > 0.0 ? cfg.mlp_step_mm : std::min(grid->vx, grid->vy);
     ctx->mlp = tvs::MlpCfg{step, cfg.mlp_log_term ? 1 : 0, cfg.mlp_const_power ? 1 : 0};
     if (ctx->cfg.max_tries == 0) ctx->cfg.max_tries = 100000;
-    ctx->threads = cfg.tile_threads ? cfg.tile_threads : 256;
+    // smaller tile workgroups leave the row formation beside the DROP chain
+    // more room on the fly; alone, the chain is fastest with 256 lanes
+    ctx->threads = cfg.tile_threads ? cfg.tile_threads
+                                    : (cfg.path_mode == TVS_PATH_ON_THE_FLY ? 128 : 256);
     ctx->split = (cfg.sweep_kernel == 2) ? 1 : 0;
     {
         int cus = 0;
