@@ -439,6 +439,43 @@ def main():
         log("copy calibration: 268435456 bytes read, 268435456 bytes written")
         del a, b
 
+    # a STREAM-like reference on this device: a plain device-to-device copy
+    # of 2 GiB, read plus written bytes over its time (the roofline keeps the
+    # published peak; this says how much of it a plain copy reaches here)
+    src = torch.ones(512 << 20, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    hbm_measured = {"copy_gbs": copy_gbs, "frac_of_published": copy_gbs / HBM_PEAK_GBS,
+                    "what": "device-to-device copy of 2 GiB, bytes read + written / time"}
+    del src, dst
+    log(f"plain copy: {copy_gbs:.0f} GB/s")
+    # reference rate of unique-address float32 global atomic adds (torch's
+    # index_add_, one atomic per element, consecutive addresses), against
+    # which the DROP step's atomic requests are set in the committed counter
+    # record (there is no published atomic peak)
+    n_at = 64 << 20
+    acc = torch.zeros(n_at, dtype=torch.float32, device="cuda:0")
+    idx = torch.arange(n_at, dtype=torch.int64, device="cuda:0")
+    val = torch.ones(n_at, dtype=torch.float32, device="cuda:0")
+    acc.index_add_(0, idx, val)
+    e0.record()
+    for _ in range(3):
+        acc.index_add_(0, idx, val)
+    e1.record()
+    torch.cuda.synchronize()
+    at_ms = e0.elapsed_time(e1) / 3
+    atomic_reference = {"what": "torch index_add_, float32, 64M unique consecutive addresses",
+                        "lane_atomics_per_s": n_at / (at_ms * 1e-3), "ms": at_ms}
+    del acc, idx, val
+    log(f"atomic reference: {atomic_reference}")
+
     precision = None
     if args.precision:
         log("precision report")
@@ -474,6 +511,8 @@ def main():
                                 "drop": st["drop_ms_total"] / max(st["cycles_timed"], 1)},
         "load_s": load_s,
         "roofline": roof,
+        "hbm_measured": hbm_measured,
+        "atomic_reference": atomic_reference,
         "forms": forms,
         "batch": batch,
         "fbp": fbp,
