@@ -123,18 +123,25 @@ def cpu_baseline(w, args, cores):
     reps = 0
     x = x0
     state = None
+    t_rows = t_cycle = 0.0
     while True:
+        ta = time.perf_counter()
         rows = oracle.build_rows(w.grid, h, min(w.grid.vx, w.grid.vy))
+        tb = time.perf_counter()
         S = oracle.Superiorizer(w.grid, rows, x, args.block)
         if state is not None:
             S.state = state
         S.iterate(1, args.lam, args.N, args.alpha, tv_check=args.check, seed=args.seed)
         x, state = S.x.copy(), S.state
+        t_rows += tb - ta
+        t_cycle += time.perf_counter() - tb
         reps += 1
         el = time.perf_counter() - t0
         if el > args.cpu_seconds or reps >= 20:
             break
     return dict(value=n * reps / el, unit="histories/s", cores=cores, kind="oracle",
+                phases_s_per_cycle={"rows_mlp_walk": t_rows / reps,
+                                    "tv_steps_and_drop_sweep": t_cycle / reps},
                 sample=f"first {n} histories of the {w.name} scan ({w.n_hist}), {reps} cycle(s) "
                        f"each re-forming rows (MLP+walk, OpenMP {cores} threads) then "
                        f"N={args.N} TV steps and one DROP sweep (single thread); {el:.1f} s")
