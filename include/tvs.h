@@ -80,8 +80,8 @@ typedef struct {
                                 and form this block's dot products, tile by tile);
                                 2: the same work in two launches per block */
     int32_t tile_threads;    /* threads per image-tile workgroup of the DROP kernels
-                                (64, 128, 256); 0: 128 on the fly, 256 with a path
-                                store */
+                                (64, 128, 256); 0: 128 on the fly and for grids of
+                                more than 16 image tiles per CU, else 256 */
     int32_t time_sample;     /* k > 0: kernel-stamped HIP events on the launches of every
                                 k-th DROP block (per-launch durations in tvs_stats); 0: off */
     int32_t fill_wgs_per_cu; /* on-the-fly rows: cap on the workgroups per compute unit of

@@ -794,10 +794,6 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     double step = cfg.mlp_step_mm > 0.0 ? cfg.mlp_step_mm : std::min(grid->vx, grid->vy);
     ctx->mlp = tvs::MlpCfg{step, cfg.mlp_log_term ? 1 : 0, cfg.mlp_const_power ? 1 : 0};
     if (ctx->cfg.max_tries == 0) ctx->cfg.max_tries = 100000;
-    // smaller tile workgroups leave the row formation beside the DROP chain
-    // more room on the fly; alone, the chain is fastest with 256 lanes
-    ctx->threads = cfg.tile_threads ? cfg.tile_threads
-                                    : (cfg.path_mode == TVS_PATH_ON_THE_FLY ? 128 : 256);
     ctx->split = (cfg.sweep_kernel == 2) ? 1 : 0;
     {
         int cus = 0;
@@ -806,6 +802,14 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
             cus = 0;
         const int per_cu = cfg.fill_wgs_per_cu;
         ctx->fill_wgs = (per_cu > 0 && cus > 0) ? (int64_t)per_cu * cus : 0;
+        // Tile workgroup size: 128 lanes on the fly (they leave the row
+        // formation beside the DROP chain more room) and for grids of more
+        // tiles than twice the 256-lane workgroups the device holds at once
+        // (8 per CU: fewer rounds of workgroups per step); else 256 lanes,
+        // with which a step of a path store is shortest
+        const int64_t resident256 = 8 * (int64_t)(cus > 0 ? cus : 256);
+        const bool small = cfg.path_mode == TVS_PATH_ON_THE_FLY || ctx->ntiles > 2 * resident256;
+        ctx->threads = cfg.tile_threads ? cfg.tile_threads : (small ? 128 : 256);
     }
 
     size_t freeb = 0, totalb = 0;
