@@ -25,6 +25,10 @@
  *     duration of the call only: the library copies what it keeps.
  *   - `stream` is a hipStream_t (NULL: the context's own stream).  Work is
  *     enqueued on it; a call that returns data in host memory waits for it.
+ *     Calls on one context that name different streams are ordered by the
+ *     caller (as for any two streams), except that the library orders its
+ *     own second stream, on which rows are formed on the fly, after the
+ *     load's work and before every later use of the rows.
  *   - Lengths are in mm; images are float32 RSP, nx*ny*nz values, x fastest
  *     (index ix + nx*(iy + ny*iz)).
  *   - One context must not be used by two threads at once; distinct
