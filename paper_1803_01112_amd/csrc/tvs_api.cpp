@@ -1428,9 +1428,13 @@ int tvs_iterate_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, int32_t K, v
     if (!ctx->loaded) return fail(ctx, TVS_ESTATE, "tvs_iterate_batch before tvs_load_histories");
     HIPCHK(hipSetDevice(ctx->cfg.device));
     hipStream_t st = pick(ctx, stream);
-    // the chunk buffers must be free of the single-image sweep's work
+    // the chunk buffers must be free of the single-image sweep's work (its
+    // last reads are marked by the buffer-free events, also when it ran on
+    // another stream)
     HIPCHK(hipStreamSynchronize(ctx->fill_stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY)
+        for (int q = 0; q < 2; q++) HIPCHK(hipStreamWaitEvent(st, ctx->ev_free[q], 0));
     auto &B = ctx->batch;
     bool same = B.valid && B.S == S;
     for (int q = 0; same && q < S; q++) same = same_params(B.p[q], p[q]);
