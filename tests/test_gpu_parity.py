@@ -341,3 +341,19 @@ def test_first_sweep_after_device_load_large_chunks():
             images.append(ctx.get_image())
     for img in images[1:]:
         np.testing.assert_array_equal(img, images[0])
+
+
+def test_rows_bitexact_vol256_sample():
+    """Rows of the 256x256x32 phantom's scan (60M histories at 360 angles):
+    samples across the scan, formed by the library's row kernel, bit-exact
+    against the oracle."""
+    w = synth.workload("vol256")
+    rng = np.random.default_rng(1)
+    starts = sorted(rng.choice(w.n_hist // 1000, 8, replace=False) * 1000)
+    print(f"vol256 samples at {starts}", flush=True)
+    with tvs.Context(w.grid) as ctx:
+        for s in starts:
+            h = w.histories(first=int(s), count=2000)
+            rows = oracle.build_rows(w.grid, h, 1.0)
+            ctx.load_histories(h)
+            check_rows(ctx, rows, 0, 2000)
