@@ -58,7 +58,7 @@ uint64_t footprint(const tvs_request &r, int64_t chunk)
     const uint64_t B = (uint64_t)(r.block_size > 0 ? r.block_size : 3200);
     const uint64_t nblocks = (n + B - 1) / B;
     uint64_t rows_held;
-    if (r.path_mode == TVS_PATH_ON_THE_FLY) rows_held = 2 * std::min<uint64_t>(n, (uint64_t)chunk);
+    if (r.path_mode == TVS_PATH_ON_THE_FLY) rows_held = 3 * std::min<uint64_t>(n, (uint64_t)chunk);  // ring of 3
     else rows_held = n;
     // entries: 32-bit tag + chord (float32, or float16 for the f16 store)
     const uint64_t entry = (r.path_mode == TVS_PATH_STORE_F16) ? 6 : 8;

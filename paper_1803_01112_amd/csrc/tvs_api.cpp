@@ -30,6 +30,11 @@ namespace {
 
 constexpr int kNumStreams = 13;
 
+// On the fly, rows are formed into a ring of chunk buffers: with three, the
+// formation stream can form the next sweep's first chunk while the DROP
+// chain still reads the last two of this sweep.
+constexpr int kChunkBuffers = 3;
+
 // Flags on the device: DROP fixed-point range, tile-list consistency,
 // history validation.
 enum { kFlagRange = 0, kFlagLists = 1, kFlagInvalid = 2, kFlagJmax = 3, kNumFlags = 4 };
@@ -95,14 +100,16 @@ struct tvs_ctx {
     int64_t nseg = 0;
     int64_t *bt_off = nullptr;      // nblocks * ntiles + 1 list starts
     int64_t nblocks = 0;
-    uint32_t *meta[2] = {nullptr, nullptr};   // entries: the store, or two chunk buffers
-    float *ch32[2] = {nullptr, nullptr};
+    // entries: the store, or a ring of chunk buffers on the fly
+    uint32_t *meta[kChunkBuffers] = {};
+    float *ch32[kChunkBuffers] = {};
     __half *ch16 = nullptr;
     int64_t cap = 0;                // entries per buffer
     int nbuf = 0;
-    hipStream_t fill_stream = nullptr;          // row formation of the next chunk
-    hipEvent_t ev_filled[2] = {nullptr, nullptr};
-    hipEvent_t ev_free[2] = {nullptr, nullptr};
+    int64_t cbase = 0;              // ring position of the next sweep's first chunk
+    hipStream_t fill_stream = nullptr;          // row formation of the next chunks
+    hipEvent_t ev_filled[kChunkBuffers] = {};
+    hipEvent_t ev_free[kChunkBuffers] = {};
     int64_t nnz = 0, max_row = 0, skipped = 0;
     int64_t chunk = 0;              // histories per chunk (a multiple of B)
     std::vector<int64_t> chunk_base;  // entry offset of each chunk start (and the end)
@@ -195,6 +202,9 @@ void dfree(tvs_ctx *ctx, T **p, size_t count)
 
 int64_t bt_len(const tvs_ctx *ctx) { return ctx->nblocks * ctx->ntiles + 1; }
 
+// Ring buffer of chunk c of the current sweep (on the fly).
+int chunk_buffer(const tvs_ctx *ctx, int64_t c) { return (int)((ctx->cbase + c) % ctx->nbuf); }
+
 void free_histories(tvs_ctx *ctx)
 {
     dfree(ctx, &ctx->hist, (size_t)(kNumStreams * ctx->nh));
@@ -208,7 +218,7 @@ void free_histories(tvs_ctx *ctx)
     ctx->mlp.nj = 0;
     dfree(ctx, &ctx->segtab, (size_t)ctx->nseg);
     dfree(ctx, &ctx->bt_off, (size_t)bt_len(ctx));
-    for (int q = 0; q < 2; q++) {
+    for (int q = 0; q < kChunkBuffers; q++) {
         dfree(ctx, &ctx->meta[q], (size_t)ctx->cap);
         dfree(ctx, &ctx->ch32[q], (size_t)ctx->cap);
     }
@@ -219,6 +229,7 @@ void free_histories(tvs_ctx *ctx)
     ctx->nblocks = 0;
     ctx->cap = 0;
     ctx->nbuf = 0;
+    ctx->cbase = 0;
     ctx->nnz = ctx->max_row = ctx->skipped = 0;
     ctx->chunk_base.clear();
 }
@@ -334,7 +345,7 @@ TileBlock block_view(tvs_ctx *ctx, int64_t b, long long *dot_base, int64_t dot_s
     const int64_t B = ctx->cfg.block_size;
     const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
     const int64_t c = otf ? (b * B) / ctx->chunk : 0;
-    const int buf = otf ? (int)(c & 1) : 0;
+    const int buf = otf ? chunk_buffer(ctx, c) : 0;
     TileBlock t;
     t.meta = ctx->meta[buf];
     t.ch32 = ctx->ch32[buf];
@@ -359,8 +370,8 @@ tvs::TileFill chunk_fill(tvs_ctx *ctx, int64_t c, int64_t n)
     f.seg_off = ctx->seg_off;
     f.segdst = reinterpret_cast<const int64_t *>(ctx->segtab);
     f.base = ctx->chunk_base[(size_t)c];
-    f.meta = ctx->meta[c & 1];
-    f.ch32 = ctx->ch32[c & 1];
+    f.meta = ctx->meta[chunk_buffer(ctx, c)];
+    f.ch32 = ctx->ch32[chunk_buffer(ctx, c)];
     f.ch16 = ctx->ch16;
     f.cap = ctx->cap;
     f.norm2 = ctx->norm2;
@@ -389,24 +400,27 @@ int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st, int64_t limit = -1)
     auto fill = [&](int64_t c) -> int {
         const int64_t n = std::min(step, ctx->nh - c * step);
         tvs::TileFill f = chunk_fill(ctx, c, n);
-        HIPCHK(hipStreamWaitEvent(fs, ctx->ev_free[c & 1], 0));
+        HIPCHK(hipStreamWaitEvent(fs, ctx->ev_free[chunk_buffer(ctx, c)], 0));
         long a = mark(ctx, fs);
         HIPCHK(tvs::launch_rows_fill_tiled(ctx->gd, hist_dev(ctx), ctx->mlp, f, fs));
         span(ctx, 2, a, mark(ctx, fs));
-        HIPCHK(hipEventRecord(ctx->ev_filled[c & 1], fs));
+        HIPCHK(hipEventRecord(ctx->ev_filled[chunk_buffer(ctx, c)], fs));
         return TVS_OK;
     };
+    const int64_t NB = ctx->nbuf;
     if (otf) {
-        int rc = fill(0);
-        if (!rc && nchunks > 1) rc = fill(1);
-        if (rc) return rc;
+        for (int64_t c = 0; c < std::min<int64_t>(NB, nchunks); c++) {
+            int rc = fill(c);
+            if (rc) return rc;
+        }
     }
     long e0 = mark(ctx, st);
     for (int64_t b = 0; b <= nb; b++) {
         const bool has_c = b < nb;
         const int64_t c = has_c ? (b * B) / step : -1;
         const bool first_of_chunk = has_c && (b * B) % step == 0;
-        if (otf && first_of_chunk) HIPCHK(hipStreamWaitEvent(st, ctx->ev_filled[c & 1], 0));
+        if (otf && first_of_chunk)
+            HIPCHK(hipStreamWaitEvent(st, ctx->ev_filled[chunk_buffer(ctx, c)], 0));
         tvs::DropTileArgs A;
         if (b > 0) A.P = block_view(ctx, b - 1, ctx->dot, B);
         if (has_c) A.C = block_view(ctx, b, ctx->dot, B);
@@ -424,16 +438,22 @@ int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st, int64_t limit = -1)
         HIPCHK(tvs::launch_drop_tiles(A, ctx->ntiles, ctx->threads, ctx->split, st,
                                       timed ? &kt : nullptr));
         if (otf && first_of_chunk && c >= 1) {
-            // the launch above was the last to read chunk c - 1's buffer
-            HIPCHK(hipEventRecord(ctx->ev_free[(c - 1) & 1], st));
-            if (c + 1 < nchunks) {
-                int rc = fill(c + 1);
+            // the launch above was the last to read chunk c - 1's buffer,
+            // which takes chunk c - 1 + NB next
+            HIPCHK(hipEventRecord(ctx->ev_free[chunk_buffer(ctx, c - 1)], st));
+            if (c - 1 + NB < nchunks) {
+                int rc = fill(c - 1 + NB);
                 if (rc) return rc;
             }
         }
     }
     span(ctx, 3, e0, mark(ctx, st));
-    if (otf) HIPCHK(hipEventRecord(ctx->ev_free[(nchunks - 1) & 1], st));
+    if (otf) {
+        HIPCHK(hipEventRecord(ctx->ev_free[chunk_buffer(ctx, nchunks - 1)], st));
+        // the ring continues with the next sweep, whose first chunks take the
+        // buffers freed first
+        ctx->cbase = (ctx->cbase + nchunks) % NB;
+    }
     return TVS_OK;
 }
 
@@ -644,7 +664,9 @@ int form_entries(tvs_ctx *ctx, hipStream_t st)
             cap = std::max(cap, ctx->chunk_base[q + 1] - ctx->chunk_base[q]);
     }
     ctx->cap = std::max<int64_t>(cap, 1);
-    ctx->nbuf = (otf && ctx->chunk_base.size() > 2) ? 2 : 1;
+    const int64_t nchunks = (int64_t)ctx->chunk_base.size() - 1;
+    ctx->nbuf = otf ? (int)std::max<int64_t>(1, std::min<int64_t>(kChunkBuffers, nchunks)) : 1;
+    ctx->cbase = 0;
     int rc = TVS_OK;
     for (int q = 0; q < ctx->nbuf && !rc; q++) {
         rc = dalloc(ctx, &ctx->meta[q], (size_t)ctx->cap);
@@ -661,7 +683,7 @@ int form_entries(tvs_ctx *ctx, hipStream_t st)
     if (otf) {
         // the first sweep's row formation runs on the fill stream: it must
         // not start before these clears, or they overwrite formed entries
-        for (int q = 0; q < 2; q++) HIPCHK(hipEventRecord(ctx->ev_free[q], st));
+        for (int q = 0; q < kChunkBuffers; q++) HIPCHK(hipEventRecord(ctx->ev_free[q], st));
         return TVS_OK;
     }
     if (ctx->nh == 0) return TVS_OK;
@@ -743,7 +765,7 @@ void tvs_destroy(tvs_ctx *ctx)
     dfree(ctx, &ctx->ticket, (size_t)4);
     for (auto &e : ctx->tev)
         if (e) (void)hipEventDestroy(e);
-    for (int q = 0; q < 2; q++) {
+    for (int q = 0; q < kChunkBuffers; q++) {
         if (ctx->ev_filled[q]) (void)hipEventDestroy(ctx->ev_filled[q]);
         if (ctx->ev_free[q]) (void)hipEventDestroy(ctx->ev_free[q]);
     }
@@ -839,7 +861,7 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
         tvs_destroy(ctx);
         return TVS_EDEVICE;
     }
-    for (int q = 0; q < 2; q++) {
+    for (int q = 0; q < kChunkBuffers; q++) {
         if (hipEventCreateWithFlags(&ctx->ev_filled[q], hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&ctx->ev_free[q], hipEventDisableTiming) != hipSuccess ||
             hipEventRecord(ctx->ev_free[q], ctx->stream) != hipSuccess) {
@@ -1434,7 +1456,7 @@ int tvs_iterate_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, int32_t K, v
     HIPCHK(hipStreamSynchronize(ctx->fill_stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY)
-        for (int q = 0; q < 2; q++) HIPCHK(hipStreamWaitEvent(st, ctx->ev_free[q], 0));
+        for (int q = 0; q < kChunkBuffers; q++) HIPCHK(hipStreamWaitEvent(st, ctx->ev_free[q], 0));
     auto &B = ctx->batch;
     bool same = B.valid && B.S == S;
     for (int q = 0; same && q < S; q++) same = same_params(B.p[q], p[q]);
