@@ -226,6 +226,7 @@ def run_serving(tvs, args):
     for g in grids:
         w = synth.workload(g, n_hist=hmax)
         pools[g] = (w, w.histories(), w.initial_image())
+        log(f"serving pool {g}: {hmax} histories")
     pairs = [(1e-4, 12), (1.5e-4, 8), (2e-4, 6)]
     reqs = []
     for q in range(args.serve_requests):
@@ -249,6 +250,7 @@ def run_serving(tvs, args):
             s.wait(sub(s, r))
         t_alone = time.perf_counter() - t0
     cap_rate = len(reqs) / t_alone
+    log(f"serving: {len(reqs)} requests one at a time in {t_alone:.1f} s")
     out = dict(requests=len(reqs), history_cycles=work, serial_s=t_alone,
                serial_value=work / t_alone, loads={})
     for rho in [float(v) for v in args.serve_loads.split(",")]:
@@ -269,6 +271,7 @@ def run_serving(tvs, args):
                                       p99_ms=float(np.percentile(lat, 99)), completed=ok,
                                       peak_active=c["peak_active"],
                                       peak_gb=c["peak_bytes"] / 2**30)
+        log(f"serving at load {rho}: {out['loads'][str(rho)]}")
     return out
 
 
