@@ -185,7 +185,7 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
         for (int64_t q = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kThreads + t;
              q < A.B * S; q += (int64_t)gridDim.x * gridDim.y * kThreads)
             A.zero[q] = 0;
-    const int64_t T = blockIdx.x;
+    const int64_t T = A.tiles ? (int64_t)A.tiles[blockIdx.x] : (int64_t)blockIdx.x;
     int64_t p0 = 0, p1 = 0, c0 = 0, c1 = 0;
     if (A.P.valid) {
         p0 = A.P.toff[T];
@@ -393,7 +393,7 @@ hipError_t launch_drop_tiles_batch(const DropTileArgs &a, const BatchBuffers &b,
 {
     if (ntiles <= 0 || (!a.P.valid && !a.C.valid)) return hipSuccess;
     const bool half = a.P.valid ? (a.P.ch16 != nullptr) : (a.C.ch16 != nullptr);
-    const dim3 grid((unsigned)ntiles, (unsigned)((b.S + kGroup - 1) / kGroup));
+    const dim3 grid((unsigned)(a.tiles ? a.nact : ntiles), (unsigned)((b.S + kGroup - 1) / kGroup));
     if (half)
         hipLaunchKernelGGL(k_drop_tile_batch<__half>, grid, dim3(kThreads), 0, stream, a, b.S,
                            (const double *)b.lambda);

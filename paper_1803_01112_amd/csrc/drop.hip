@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(NT) k_drop_tile(DropTileArgs A)
 {
     __shared__ TileLds L;
     chain_priority();
-    const int64_t T = blockIdx.x;
+    const int64_t T = A.tiles ? (int64_t)A.tiles[blockIdx.x] : (int64_t)blockIdx.x;
     int64_t p0, p1, c0, c1;
     list_range(A.P, T, p0, p1);
     list_range(A.C, T, c0, c1);
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(NT) k_drop_tile_finish(DropTileArgs A)
 {
     __shared__ TileLds L;
     chain_priority();
-    const int64_t T = blockIdx.x;
+    const int64_t T = A.tiles ? (int64_t)A.tiles[blockIdx.x] : (int64_t)blockIdx.x;
     int64_t p0, p1;
     list_range(A.P, T, p0, p1);
     if (p0 == p1) return;
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(NT) k_drop_tile_dots(DropTileArgs A)
 {
     __shared__ TileLds L;
     chain_priority();
-    const int64_t T = blockIdx.x;
+    const int64_t T = A.tiles ? (int64_t)A.tiles[blockIdx.x] : (int64_t)blockIdx.x;
     int64_t c0, c1;
     list_range(A.C, T, c0, c1);
     clear_next(A, NT);
@@ -283,6 +283,19 @@ __global__ void __launch_bounds__(NT) k_drop_tile_dots(DropTileArgs A)
     stage_tile<NT>(xt, L, false);
     __syncthreads();
     tile_dots<NT, CH>(A.C, c0, c1, ce, L, A.dot_max, A.err);
+}
+
+// One lane per tile, walking the blocks (lanes of neighbouring tiles read
+// neighbouring list starts).
+__global__ void __launch_bounds__(256) k_tile_active(const int64_t *bt_off, int64_t nblocks,
+                                                     int64_t ntiles, uint32_t *flag)
+{
+    const int64_t T = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (T >= ntiles) return;
+    uint32_t on = 0u;
+    for (int64_t b = 0; b < nblocks && !on; b++)
+        on = bt_off[b * ntiles + T + 1] > bt_off[b * ntiles + T] ? 1u : 0u;
+    flag[T] = on;
 }
 
 __global__ void __launch_bounds__(256) k_zero_i64(long long *p, int64_t n)
@@ -305,7 +318,7 @@ template <int NT, typename CH>
 hipError_t drop_tiles(const DropTileArgs &a, int64_t ntiles, int split, hipStream_t stream,
                       const KTimer &t)
 {
-    const dim3 grid((unsigned)ntiles), block(NT);
+    const dim3 grid((unsigned)(a.tiles ? a.nact : ntiles)), block(NT);
     if (!split) {
         launch(k_drop_tile<NT, CH>, grid, block, stream, t.e[0], t.e[1], a);
         return hipGetLastError();
@@ -337,6 +350,15 @@ hipError_t launch_drop_tiles(const DropTileArgs &a, int64_t ntiles, int threads,
     const bool half = a.P.valid ? (a.P.ch16 != nullptr) : (a.C.ch16 != nullptr);
     return half ? drop_tiles_nt<__half>(a, ntiles, threads, split, stream, t)
                 : drop_tiles_nt<float>(a, ntiles, threads, split, stream, t);
+}
+
+hipError_t launch_tile_active(const int64_t *bt_off, int64_t nblocks, int64_t ntiles,
+                              uint32_t *flag, hipStream_t stream)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_active, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, stream,
+                       bt_off, nblocks, ntiles, flag);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero_i64(long long *p, int64_t n, hipStream_t stream)

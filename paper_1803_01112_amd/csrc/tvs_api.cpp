@@ -99,6 +99,8 @@ struct tvs_ctx {
     uint64_t *segtab = nullptr;     // nseg: global entry index of each segment's first entry
     int64_t nseg = 0;
     int64_t *bt_off = nullptr;      // nblocks * ntiles + 1 list starts
+    int32_t *act = nullptr;         // tiles that some block's lists cross
+    int64_t nact = 0;
     int64_t nblocks = 0;
     // entries: the store, or a ring of chunk buffers on the fly
     uint32_t *meta[kChunkBuffers] = {};
@@ -218,6 +220,8 @@ void free_histories(tvs_ctx *ctx)
     ctx->mlp.nj = 0;
     dfree(ctx, &ctx->segtab, (size_t)ctx->nseg);
     dfree(ctx, &ctx->bt_off, (size_t)bt_len(ctx));
+    dfree(ctx, &ctx->act, (size_t)std::max<int64_t>(ctx->nact, 1));
+    ctx->nact = 0;
     for (int q = 0; q < kChunkBuffers; q++) {
         dfree(ctx, &ctx->meta[q], (size_t)ctx->cap);
         dfree(ctx, &ctx->ch32[q], (size_t)ctx->cap);
@@ -431,6 +435,8 @@ int run_sweep(tvs_ctx *ctx, double lambda, hipStream_t st, int64_t limit = -1)
         A.zero = ctx->dot + ((b + 1) % 3) * B;
         A.B = B;
         A.err = ctx->flags + kFlagRange;
+        A.tiles = ctx->act;
+        A.nact = ctx->nact;
         const bool samp = ctx->cfg.time_sample > 0 && has_c && b > 0 &&
                           b % ctx->cfg.time_sample == 0;
         tvs::KTimer kt;
@@ -498,6 +504,36 @@ int count_rows(tvs_ctx *ctx, int64_t first, int64_t n, int64_t *row_off_dev, hip
     dfree(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
     dfree(ctx, &tmp, (size_t)tvs::scan_tmp_elems(n) + 1);
     if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("row count: ") + hipGetErrorString(e));
+    return TVS_OK;
+}
+
+// The tiles that some block's lists cross (a tile outside the scanned
+// object has no entry in any block): the DROP steps launch one workgroup
+// per such tile only.  At least one tile is kept, so that a step always has
+// a workgroup to clear the next dot-product buffer.
+int build_active_tiles(tvs_ctx *ctx, hipStream_t st)
+{
+    const int64_t nt = ctx->ntiles;
+    uint32_t *flag = nullptr;
+    int rc = dalloc(ctx, &flag, (size_t)std::max<int64_t>(nt, 1));
+    if (rc) return rc;
+    std::vector<uint32_t> f((size_t)std::max<int64_t>(nt, 1), 0u);
+    hipError_t e = tvs::launch_tile_active(ctx->bt_off, ctx->nblocks, nt, flag, st);
+    if (e == hipSuccess && nt > 0)
+        e = hipMemcpyAsync(f.data(), flag, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(ctx, &flag, (size_t)std::max<int64_t>(nt, 1));
+    if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("active tiles: ") + hipGetErrorString(e));
+    std::vector<int32_t> a;
+    for (int64_t T = 0; T < nt; T++)
+        if (f[(size_t)T]) a.push_back((int32_t)T);
+    if (a.empty()) a.push_back(0);
+    rc = dalloc(ctx, &ctx->act, a.size());
+    if (rc) return rc;
+    ctx->nact = (int64_t)a.size();
+    e = hipMemcpyAsync(ctx->act, a.data(), sizeof(int32_t) * a.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("active tiles: ") + hipGetErrorString(e));
     return TVS_OK;
 }
 
@@ -650,7 +686,7 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
                             " of " + std::to_string(ctx->nblocks) + ": " +
                             std::to_string(starts[(size_t)b]) + " != " + std::to_string(want));
     }
-    return TVS_OK;
+    return build_active_tiles(ctx, st);
 }
 
 // Allocates the entry buffers and, for a path store, forms every row now.
@@ -1424,6 +1460,8 @@ int batch_cycle(tvs_ctx *ctx, int nmax, hipStream_t st)
         A.zero = Bt.dot + ((b + 1) % 3) * B * S;
         A.B = B;
         A.err = ctx->flags + kFlagRange;
+        A.tiles = ctx->act;
+        A.nact = ctx->nact;
         HIPCHK(tvs::launch_drop_tiles_batch(A, Bt.b, ctx->ntiles, st));
     }
     HIPCHK(tvs::launch_tick(Bt.b.cyc, st));
