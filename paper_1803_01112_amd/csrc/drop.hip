@@ -286,16 +286,17 @@ __global__ void __launch_bounds__(NT) k_drop_tile_dots(DropTileArgs A)
 }
 
 // One lane per tile, walking the blocks (lanes of neighbouring tiles read
-// neighbouring list starts).
+// neighbouring list starts): the tile's entries over all blocks, saturated
+// at 2^32 - 1.
 __global__ void __launch_bounds__(256) k_tile_active(const int64_t *bt_off, int64_t nblocks,
-                                                     int64_t ntiles, uint32_t *flag)
+                                                     int64_t ntiles, uint32_t *total)
 {
     const int64_t T = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (T >= ntiles) return;
-    uint32_t on = 0u;
-    for (int64_t b = 0; b < nblocks && !on; b++)
-        on = bt_off[b * ntiles + T + 1] > bt_off[b * ntiles + T] ? 1u : 0u;
-    flag[T] = on;
+    uint64_t tot = 0;
+    for (int64_t b = 0; b < nblocks; b++)
+        tot += (uint64_t)(bt_off[b * ntiles + T + 1] - bt_off[b * ntiles + T]);
+    total[T] = tot > 0xffffffffull ? 0xffffffffu : (uint32_t)tot;
 }
 
 __global__ void __launch_bounds__(256) k_zero_i64(long long *p, int64_t n)
@@ -353,11 +354,11 @@ hipError_t launch_drop_tiles(const DropTileArgs &a, int64_t ntiles, int threads,
 }
 
 hipError_t launch_tile_active(const int64_t *bt_off, int64_t nblocks, int64_t ntiles,
-                              uint32_t *flag, hipStream_t stream)
+                              uint32_t *total, hipStream_t stream)
 {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tile_active, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, stream,
-                       bt_off, nblocks, ntiles, flag);
+                       bt_off, nblocks, ntiles, total);
     return hipGetLastError();
 }
 

@@ -509,24 +509,28 @@ int count_rows(tvs_ctx *ctx, int64_t first, int64_t n, int64_t *row_off_dev, hip
 
 // The tiles that some block's lists cross (a tile outside the scanned
 // object has no entry in any block): the DROP steps launch one workgroup
-// per such tile only.  At least one tile is kept, so that a step always has
-// a workgroup to clear the next dot-product buffer.
+// per such tile only, in order of decreasing entries over the scan, so that
+// the longest lists are dispatched first and do not trail the step.  At
+// least one tile is kept, so that a step always has a workgroup to clear
+// the next dot-product buffer.
 int build_active_tiles(tvs_ctx *ctx, hipStream_t st)
 {
     const int64_t nt = ctx->ntiles;
-    uint32_t *flag = nullptr;
-    int rc = dalloc(ctx, &flag, (size_t)std::max<int64_t>(nt, 1));
+    uint32_t *total = nullptr;
+    int rc = dalloc(ctx, &total, (size_t)std::max<int64_t>(nt, 1));
     if (rc) return rc;
     std::vector<uint32_t> f((size_t)std::max<int64_t>(nt, 1), 0u);
-    hipError_t e = tvs::launch_tile_active(ctx->bt_off, ctx->nblocks, nt, flag, st);
+    hipError_t e = tvs::launch_tile_active(ctx->bt_off, ctx->nblocks, nt, total, st);
     if (e == hipSuccess && nt > 0)
-        e = hipMemcpyAsync(f.data(), flag, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost, st);
+        e = hipMemcpyAsync(f.data(), total, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    dfree(ctx, &flag, (size_t)std::max<int64_t>(nt, 1));
+    dfree(ctx, &total, (size_t)std::max<int64_t>(nt, 1));
     if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("active tiles: ") + hipGetErrorString(e));
     std::vector<int32_t> a;
     for (int64_t T = 0; T < nt; T++)
         if (f[(size_t)T]) a.push_back((int32_t)T);
+    std::stable_sort(a.begin(), a.end(),
+                     [&](int32_t x, int32_t y) { return f[(size_t)x] > f[(size_t)y]; });
     if (a.empty()) a.push_back(0);
     rc = dalloc(ctx, &ctx->act, a.size());
     if (rc) return rc;

@@ -220,7 +220,8 @@ struct DropTileArgs {
     int64_t B = 0;
     uint32_t *err = nullptr;
     // tiles that some block's lists cross (the others have no work in any
-    // step); non-null: workgroup i takes tile tiles[i], nact workgroups
+    // step), the busiest first; non-null: workgroup i takes tile tiles[i],
+    // nact workgroups
     const int32_t *tiles = nullptr;
     int64_t nact = 0;
 };
@@ -237,10 +238,10 @@ struct KTimer {
 hipError_t launch_drop_tiles(const DropTileArgs &a, int64_t ntiles, int threads, int split,
                              hipStream_t stream, const KTimer *kt = nullptr);
 hipError_t launch_zero_i64(long long *p, int64_t n, hipStream_t stream);
-// flag[T] = 1 when some block's list of tile T is non-empty (list starts
-// bt_off of nblocks x ntiles lists), else 0.
+// total[T] = entries of tile T over the lists of every block (list starts
+// bt_off of nblocks x ntiles lists), saturated at 2^32 - 1.
 hipError_t launch_tile_active(const int64_t *bt_off, int64_t nblocks, int64_t ntiles,
-                              uint32_t *flag, hipStream_t stream);
+                              uint32_t *total, hipStream_t stream);
 
 // ----------------------------------------------------------------- tv.hip
 struct TvBuffers {
