@@ -143,3 +143,146 @@ def test_decoupled_schedule_beta():
     # second cycle (k = 1) steps by alpha * gamma
     step2 = np.linalg.norm(S2.x - S.x)
     assert step2 == pytest.approx(0.6 * 0.5, rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# The retry branch of the checked step and the length of the unchecked step,
+# pinned against images stepped explicitly here.  TV is recomputed with numpy
+# (per-slice forward differences, Section IV's "sum of local variations");
+# the direction v = -grad/||grad|| takes the oracle's subgradient, which
+# tests/test_oracle_tv.py pins against finite differences.
+# ---------------------------------------------------------------------------
+def _empty_rows():
+    return dict(row_off=np.zeros(1, np.int64), idx=np.zeros(0, np.int32),
+                chord=np.zeros(0), norm2=np.zeros(0), wepl=np.zeros(0))
+
+
+def _np_tv(grid, x):
+    v = np.asarray(x, np.float64).reshape(grid.nz, grid.ny, grid.nx)
+    dx = np.zeros_like(v)
+    dy = np.zeros_like(v)
+    dx[:, :, :-1] = v[:, :, 1:] - v[:, :, :-1]
+    dy[:, :-1, :] = v[:, 1:, :] - v[:, :-1, :]
+    return float(np.sum(np.sqrt(dx * dx + dy * dy)))
+
+
+def _v(grid, x):
+    """v = -grad phi / ||grad phi|| from the oracle's subgradient."""
+    g, n2 = oracle.tv_grad(grid, x)
+    gn = np.sqrt(n2)
+    return -g / gn if gn > 0 else np.zeros_like(g)
+
+
+def test_checked_step_retries_with_beta_recomputed():
+    """Appendix C, checked NTVS (reading: beta = alpha^ell recomputed after
+    every ell += 1).  A small-amplitude image and alpha = 1/2 make the first
+    tries (beta = 1, 1/2, ...) overshoot, so the step needs several tries:
+    every rejected try t must raise TV, the accepted image must be
+    x + alpha^(ell0 + tries - 1) v with TV not above TV(x), and ell must
+    advance by exactly the number of tries.  The literal listing (beta never
+    updated inside the loop) rejects forever and fails here."""
+    g = synth.Grid(16, 16, 1, 1.0, 1.0, 1.0, -8.0, -8.0, -0.5)
+    rng = np.random.default_rng(31)
+    x0 = 0.01 * rng.standard_normal(g.nvox)
+    alpha = 0.5
+    S = oracle.Superiorizer(g, _empty_rows(), x0, 10)
+    recs = S.iterate(1, 1e-3, 1, alpha, tv_check=1, seed=4, max_tries=200)
+    r = recs[0]
+    tries, ell0 = r["tries"], r["ell_start"]
+    assert ell0 == S.ell_log[0] == 0              # rand(0, 0) = 0
+    assert r["accepted"] == 1 and tries >= 3
+    v = _v(g, x0)
+    phx = _np_tv(g, x0)
+    assert r["phi_x"] == pytest.approx(phx, rel=1e-13)
+    for t in range(1, tries):                     # every rejected try raised TV
+        z = x0 + alpha ** (ell0 + t - 1) * v
+        assert _np_tv(g, z) > phx
+    z = x0 + alpha ** (ell0 + tries - 1) * v      # the accepted try
+    np.testing.assert_allclose(S.x, z, rtol=0, atol=1e-15)
+    assert _np_tv(g, S.x) <= phx
+    assert r["phi_z"] == pytest.approx(_np_tv(g, S.x), rel=1e-13)
+    assert S.state.ell == ell0 + tries
+
+
+def test_checked_steps_chain_ell_across_steps_and_cycles():
+    """Several checked steps and cycles: each step starts at the ell its
+    predecessor left (start + tries), each cycle draws ell_k = rand(k, ell)
+    from the pinned SplitMix64 stream, and every step's image is the one
+    stepped here with beta = alpha^(start + tries - 1)."""
+    g = synth.Grid(12, 10, 2, 1.0, 1.0, 1.0, -6.0, -5.0, -1.0)
+    rng = np.random.default_rng(5)
+    x0 = 0.02 * rng.standard_normal(g.nvox)
+    alpha, N, K, seed = 0.6, 3, 3, 123
+    S = oracle.Superiorizer(g, _empty_rows(), x0, 10)
+    x = x0.copy()
+    state, ell = seed, 0
+    for k in range(K):
+        recs = S.iterate(1, 1e-3, N, alpha, tv_check=1, seed=seed, max_tries=500)
+        ell, state = oracle.rand_ell(k, ell, state)
+        assert S.ell_log[k] == ell
+        for r in recs:
+            assert r["ell_start"] == ell and r["accepted"] == 1
+            v = _v(g, x)
+            phx = _np_tv(g, x)
+            for t in range(1, r["tries"]):
+                assert _np_tv(g, x + alpha ** (ell + t - 1) * v) > phx
+            x = x + alpha ** (ell + r["tries"] - 1) * v
+            assert _np_tv(g, x) <= phx
+            ell += r["tries"]
+        np.testing.assert_allclose(S.x, x, rtol=0, atol=1e-14)
+        assert S.state.ell == ell
+    assert any(r["tries"] > 1 for r in S.steps)
+
+
+def test_checked_step_gives_up_after_max_tries():
+    """A bounded retry loop leaves the image unchanged and logs the step as
+    not accepted when no try within max_tries lowers TV."""
+    g = synth.Grid(16, 16, 1, 1.0, 1.0, 1.0, -8.0, -8.0, -0.5)
+    rng = np.random.default_rng(31)
+    x0 = 0.01 * rng.standard_normal(g.nvox)
+    S = oracle.Superiorizer(g, _empty_rows(), x0, 10)
+    recs = S.iterate(1, 1e-3, 1, 0.5, tv_check=1, seed=4, max_tries=1)
+    assert recs[0]["tries"] == 1 and recs[0]["accepted"] == 0
+    np.testing.assert_array_equal(S.x, x0)
+    assert S.state.ell == 1
+
+
+def test_unchecked_ntvs_step_length_is_alpha_to_ell():
+    """Appendix C without the check: step n of cycle k moves the image by
+    exactly alpha^(ell_k + n) along v, with ell_k = rand(k, ell) drawn once
+    per cycle; the image is followed step by step here (empty system, so
+    P_T is the identity)."""
+    g = synth.Grid(12, 12, 1, 1.0, 1.0, 1.0, -6.0, -6.0, -0.5)
+    rng = np.random.default_rng(77)
+    x0 = rng.standard_normal(g.nvox)
+    alpha, N, K, seed = 0.75, 3, 5, 2024
+    S = oracle.Superiorizer(g, _empty_rows(), x0, 10)
+    x = x0.copy()
+    state, ell = seed, 0
+    for k in range(K):
+        prev = S.x.copy()
+        S.iterate(1, 1e-3, N, alpha, seed=seed)
+        ell, state = oracle.rand_ell(k, ell, state)
+        assert S.ell_log[k] == ell
+        for n in range(N):
+            step = alpha ** ell * _v(g, x)
+            assert np.linalg.norm(step) == pytest.approx(alpha ** ell, rel=1e-13)
+            x = x + step
+            ell += 1
+        np.testing.assert_allclose(S.x, x, rtol=0, atol=1e-13)
+        if N == 1:
+            assert np.linalg.norm(S.x - prev) == pytest.approx(alpha ** S.ell_log[k], rel=1e-12)
+    assert S.state.ell == ell
+    # a draw below the previous end happened (the schedule is not the N = 1 one)
+    assert any(S.ell_log[k] < S.ell_log[k - 1] + N for k in range(1, K))
+
+
+def test_unchecked_single_step_length():
+    """N = 1: the cycle's one step has length alpha^(ell_k) exactly."""
+    g = synth.Grid(10, 10, 1, 1.0, 1.0, 1.0, -5.0, -5.0, -0.5)
+    x0 = np.random.default_rng(3).standard_normal(g.nvox)
+    S = oracle.Superiorizer(g, _empty_rows(), x0, 10)
+    for k in range(4):
+        prev = S.x.copy()
+        S.iterate(1, 1e-3, 1, 0.8, seed=9)
+        assert np.linalg.norm(S.x - prev) == pytest.approx(0.8 ** S.ell_log[k], rel=1e-12)
