@@ -234,7 +234,7 @@ int tvs_get_batch_image(tvs_ctx *ctx, int32_t s, float *out, int on_device, void
 /* Initial iterate by filtered backprojection (FBP) of the loaded histories,
  * then an in-slice median filter.  The paper starts each reconstruction from
  * a median-filtered initial iterate, radius 2 (arXiv 1803.01112, Section
- * III-E, citing earlier work for how it is formed); the form here is the
+ * V-A, citing earlier work for how it is formed); the form here is the
  * textbook parallel-beam one: every history's straight line from entry to
  * exit is binned where it crosses the rotation axis (depth u = 0) by beam
  * angle (A bins over 360 degrees), lateral position (bins of width t_bin_mm

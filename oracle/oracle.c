@@ -710,7 +710,7 @@ int64_t or_superiorize(const or_grid *g, const or_system *sys, double *x,
 /* ------------------------------------------------------------------------ */
 /* Initial iterate: filtered backprojection of binned histories and an       */
 /* in-slice median filter.  The paper starts its reconstructions from an     */
-/* initial iterate with a median filter of radius 2 applied (Section III-E,  */
+/* initial iterate with a median filter of radius 2 applied (Section V-A,   */
 /* citing earlier work); the backprojection itself is not given there.      */
 /* Reading: textbook parallel-beam FBP.  Each history's straight line from    */
 /* entry to exit is binned at its crossing of the depth u = 0 (the rotation  */

@@ -3,7 +3,7 @@
 //
 // The paper starts every reconstruction from an initial iterate to which a
 // median filter of radius 2 has been applied (arXiv 1803.01112, Section
-// III-E); it cites, and does not spell out, how that iterate is formed.
+// V-A); it cites, and does not spell out, how that iterate is formed.
 // Reading: textbook parallel-beam FBP.
 //   binning      each history's straight line from entry to exit, at its
 //                crossing of the depth u = 0 (the rotation axis): angle bin

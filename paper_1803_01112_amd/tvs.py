@@ -206,6 +206,29 @@ def _ptr(a):
     return C.c_void_p(arr.ctypes.data), 0, arr
 
 
+def _out_ptr(out, n, stream):
+    """(pointer, on_device, stream handle) of an output buffer of at least n
+    float32 values.  A device tensor must be contiguous float32; without an
+    explicit stream its copy is queued on torch's current stream, so later
+    torch work on that stream sees it.  A host array must be a writeable,
+    C-contiguous float32 array."""
+    if _is_device(out):
+        import torch
+        if out.dtype != torch.float32 or not out.is_contiguous():
+            raise TypeError("device outputs must be contiguous float32 tensors")
+        if out.numel() < n:
+            raise ValueError(f"output holds {out.numel()} values, {n} needed")
+        if stream is None:
+            stream = torch.cuda.current_stream(out.device)
+        return C.c_void_p(out.data_ptr()), 1, _stream_handle(stream)
+    if not isinstance(out, np.ndarray) or out.dtype != np.float32 or \
+            not out.flags["C_CONTIGUOUS"] or not out.flags["WRITEABLE"]:
+        raise TypeError("host outputs must be writeable C-contiguous float32 arrays")
+    if out.size < n:
+        raise ValueError(f"output holds {out.size} values, {n} needed")
+    return C.c_void_p(out.ctypes.data), 0, _stream_handle(stream)
+
+
 def grid_struct(g) -> Grid:
     return Grid(int(g.nx), int(g.ny), int(g.nz), float(g.vx), float(g.vy), float(g.vz),
                 float(g.ox), float(g.oy), float(g.oz))
@@ -334,23 +357,15 @@ class Context:
     def get_batch_image(self, s, out=None, stream=None):
         if out is None:
             out = np.zeros(self.nvox, np.float32)
-        if _is_device(out):
-            self._check(self._L.tvs_get_batch_image(self._h, int(s), C.c_void_p(out.data_ptr()), 1,
-                                                    _stream_handle(stream)), "tvs_get_batch_image")
-            return out
-        self._check(self._L.tvs_get_batch_image(self._h, int(s), C.c_void_p(out.ctypes.data), 0,
-                                                _stream_handle(stream)), "tvs_get_batch_image")
+        p, d, st = _out_ptr(out, self.nvox, stream)
+        self._check(self._L.tvs_get_batch_image(self._h, int(s), p, d, st), "tvs_get_batch_image")
         return out
 
     def get_image(self, out=None, stream=None):
         if out is None:
             out = np.zeros(self.nvox, np.float32)
-        if _is_device(out):
-            self._check(self._L.tvs_get_image(self._h, C.c_void_p(out.data_ptr()), 1,
-                                              _stream_handle(stream)), "tvs_get_image")
-            return out
-        self._check(self._L.tvs_get_image(self._h, C.c_void_p(out.ctypes.data), 0,
-                                          _stream_handle(stream)), "tvs_get_image")
+        p, d, st = _out_ptr(out, self.nvox, stream)
+        self._check(self._L.tvs_get_image(self._h, p, d, st), "tvs_get_image")
         return out
 
     def initial_fbp(self, n_angles, median_radius=2, t_bin_mm=0.0, clip_negative=True, out=None,
@@ -362,15 +377,8 @@ class Context:
         prm = FbpParams(int(n_angles), int(median_radius), float(t_bin_mm), int(bool(clip_negative)), 0)
         if out is None:
             out = np.zeros(self.nvox, np.float32)
-        if _is_device(out):
-            self._check(self._L.tvs_initial_fbp(self._h, C.byref(prm), C.c_void_p(out.data_ptr()), 1,
-                                                _stream_handle(stream)), "tvs_initial_fbp")
-            return out
-        buf = np.ascontiguousarray(out, dtype=np.float32)
-        self._check(self._L.tvs_initial_fbp(self._h, C.byref(prm), buf.ctypes.data_as(C.c_void_p), 0,
-                                            _stream_handle(stream)), "tvs_initial_fbp")
-        if buf is not out:
-            out[...] = buf.reshape(out.shape)
+        p, d, st = _out_ptr(out, self.nvox, stream)
+        self._check(self._L.tvs_initial_fbp(self._h, C.byref(prm), p, d, st), "tvs_initial_fbp")
         return out
 
     def stats(self) -> dict:

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1803_01112_amd import tvs
@@ -88,3 +89,21 @@ def test_null_context_calls(lib):
     assert lib.tvs_get_stats(None, None) == tvs.TVS_EINVAL
     assert lib.tvs_iterate(None, None, 1, None) == tvs.TVS_EINVAL
     assert lib.tvs_load_histories(None, 0, None, 0, None) == tvs.TVS_EINVAL
+
+
+def test_output_buffers_checked_before_the_call():
+    """Outputs of the wrong type, layout or size are refused by the binding
+    before anything is written through their pointer."""
+    ok = np.zeros(10, np.float32)
+    p, d, st = tvs._out_ptr(ok, 10, None)
+    assert d == 0 and st is None and p.value == ok.ctypes.data
+    with pytest.raises(ValueError):
+        tvs._out_ptr(np.zeros(9, np.float32), 10, None)
+    with pytest.raises(TypeError):
+        tvs._out_ptr(np.zeros(10, np.float64), 10, None)
+    with pytest.raises(TypeError):
+        tvs._out_ptr(np.zeros(20, np.float32)[::2], 10, None)
+    ro = np.zeros(10, np.float32)
+    ro.flags["WRITEABLE"] = False
+    with pytest.raises(TypeError):
+        tvs._out_ptr(ro, 10, None)

@@ -1,7 +1,7 @@
 """GPU parity of the initial iterate (tvs_initial_fbp): filtered
 backprojection of the binned histories and the in-slice median, against the
 oracle's implementation of the same reading (the paper's initial iterate
-with a radius-2 median, Section III-E).
+with a radius-2 median, Section V-A).
 
 Both sides evaluate the same float64 operations in the same order (bin sums
 as integers, fixed summation orders, the same cos/sin of the beam angles),

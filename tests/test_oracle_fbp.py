@@ -1,6 +1,6 @@
 """Pins of the oracle's initial iterate: binning of histories, the Ram-Lak
 filter, backprojection and the in-slice median (the paper starts from a
-median-filtered initial iterate, radius 2, Section III-E; the backprojection
+median-filtered initial iterate, radius 2, Section V-A; the backprojection
 follows the textbook parallel-beam form, see the oracle's header).
 
 Pinned by: the filter's impulse response against the kernel's closed form,
