@@ -177,7 +177,7 @@ def load_library(path: str = LIB):
         getattr(L, name).restype = C.c_int
     for name in ("tvs_create", "tvs_load_histories", "tvs_set_image", "tvs_iterate",
                  "tvs_get_image", "tvs_get_stats", "tvs_get_step_log", "tvs_debug_rows",
-                 "tvs_iterate_batch", "tvs_get_batch_image"):
+                 "tvs_iterate_batch", "tvs_get_batch_image", "tvs_initial_fbp"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -207,10 +207,13 @@ def _ptr(a):
 
 
 def _out_ptr(out, n, stream):
-    """(pointer, on_device, stream handle) of an output buffer of at least n
-    float32 values.  A device tensor must be contiguous float32; without an
-    explicit stream its copy is queued on torch's current stream, so later
-    torch work on that stream sees it.  A host array must be a writeable,
+    """(pointer, on_device, stream handle, wait) of an output buffer of at
+    least n float32 values.  A device tensor must be contiguous float32;
+    without an explicit stream its copy is queued on torch's current stream
+    when that is a stream of its own, so later torch work there sees it.
+    torch's default stream has the null handle, which the library reads as
+    the context's own stream: then `wait` is set and the caller synchronises
+    the device after the call.  A host array must be a writeable,
     C-contiguous float32 array."""
     if _is_device(out):
         import torch
@@ -219,14 +222,36 @@ def _out_ptr(out, n, stream):
         if out.numel() < n:
             raise ValueError(f"output holds {out.numel()} values, {n} needed")
         if stream is None:
-            stream = torch.cuda.current_stream(out.device)
-        return C.c_void_p(out.data_ptr()), 1, _stream_handle(stream)
+            cur = torch.cuda.current_stream(out.device)
+            if int(cur.cuda_stream) != 0:
+                return C.c_void_p(out.data_ptr()), 1, _stream_handle(cur), False
+            return C.c_void_p(out.data_ptr()), 1, None, True
+        return C.c_void_p(out.data_ptr()), 1, _stream_handle(stream), False
     if not isinstance(out, np.ndarray) or out.dtype != np.float32 or \
             not out.flags["C_CONTIGUOUS"] or not out.flags["WRITEABLE"]:
         raise TypeError("host outputs must be writeable C-contiguous float32 arrays")
     if out.size < n:
         raise ValueError(f"output holds {out.size} values, {n} needed")
-    return C.c_void_p(out.ctypes.data), 0, _stream_handle(stream)
+    return C.c_void_p(out.ctypes.data), 0, _stream_handle(stream), False
+
+
+def _settle(out, wait):
+    """After a call that wrote device tensor `out` on the context's own
+    stream: wait for the device, so that later torch work reads the result."""
+    if wait:
+        import torch
+        torch.cuda.synchronize(out.device)
+
+
+def _inputs_ready(arrays, stream):
+    """Device inputs produced on torch's current stream are complete before
+    the library (on its own stream when none is given) reads them."""
+    if stream is None:
+        for a in arrays:
+            if _is_device(a):
+                import torch
+                torch.cuda.current_stream(a.device).synchronize()
+                return
 
 
 def grid_struct(g) -> Grid:
@@ -310,6 +335,7 @@ class Context:
             ptrs[k] = p
             keep.append(ka)
         hs = Histories(*[ptrs[k] for k in HIST_FIELDS])
+        _inputs_ready(keep, stream)
         rc = self._L.tvs_load_histories(self._h, n, C.byref(hs), int(dev or 0),
                                         _stream_handle(stream))
         self._check(rc, "tvs_load_histories")
@@ -318,6 +344,7 @@ class Context:
         p, d, keep = _ptr(x)
         if len(keep.reshape(-1)) != self.nvox:
             raise ValueError("image size does not match the grid")
+        _inputs_ready([keep], stream)
         self._check(self._L.tvs_set_image(self._h, p, d, _stream_handle(stream)), "tvs_set_image")
 
     def iterate(self, K, lam, N, alpha, tv_check=False, variant="ntvs", tv_eps=0.0, seed=0,
@@ -357,15 +384,17 @@ class Context:
     def get_batch_image(self, s, out=None, stream=None):
         if out is None:
             out = np.zeros(self.nvox, np.float32)
-        p, d, st = _out_ptr(out, self.nvox, stream)
+        p, d, st, wait = _out_ptr(out, self.nvox, stream)
         self._check(self._L.tvs_get_batch_image(self._h, int(s), p, d, st), "tvs_get_batch_image")
+        _settle(out, wait)
         return out
 
     def get_image(self, out=None, stream=None):
         if out is None:
             out = np.zeros(self.nvox, np.float32)
-        p, d, st = _out_ptr(out, self.nvox, stream)
+        p, d, st, wait = _out_ptr(out, self.nvox, stream)
         self._check(self._L.tvs_get_image(self._h, p, d, st), "tvs_get_image")
+        _settle(out, wait)
         return out
 
     def initial_fbp(self, n_angles, median_radius=2, t_bin_mm=0.0, clip_negative=True, out=None,
@@ -377,8 +406,9 @@ class Context:
         prm = FbpParams(int(n_angles), int(median_radius), float(t_bin_mm), int(bool(clip_negative)), 0)
         if out is None:
             out = np.zeros(self.nvox, np.float32)
-        p, d, st = _out_ptr(out, self.nvox, stream)
+        p, d, st, wait = _out_ptr(out, self.nvox, stream)
         self._check(self._L.tvs_initial_fbp(self._h, C.byref(prm), p, d, st), "tvs_initial_fbp")
+        _settle(out, wait)
         return out
 
     def stats(self) -> dict:

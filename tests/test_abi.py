@@ -95,8 +95,8 @@ def test_output_buffers_checked_before_the_call():
     """Outputs of the wrong type, layout or size are refused by the binding
     before anything is written through their pointer."""
     ok = np.zeros(10, np.float32)
-    p, d, st = tvs._out_ptr(ok, 10, None)
-    assert d == 0 and st is None and p.value == ok.ctypes.data
+    p, d, st, wait = tvs._out_ptr(ok, 10, None)
+    assert d == 0 and st is None and not wait and p.value == ok.ctypes.data
     with pytest.raises(ValueError):
         tvs._out_ptr(np.zeros(9, np.float32), 10, None)
     with pytest.raises(TypeError):
