@@ -256,6 +256,25 @@ typedef struct {
 
 int tvs_initial_fbp(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_device, void *stream);
 
+/* tvs_initial_fbp for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same initial iterate, with every intermediate (bin sums
+ * and counts, mean and filtered projections, angle table, backprojected
+ * image) in one fixed workspace of 64 MiB that the library holds on every
+ * device it runs on, from the first tvs_create there until the process
+ * ends.  It calls no hipMalloc, hipFree or other allocating routine.  The
+ * workspace needs 28 B per bin (n_angles x nz x lateral bins) + 16 B per
+ * angle + 8 B per voxel, each part rounded up to 256 B; a larger problem
+ * is refused with TVS_ERANGE before any device work (200x200x20 voxels of
+ * 1x1x2.5 mm at 180 angles and 1 mm bins need 35 MB).  Every call on one device
+ * shares that device's workspace and overwrites it, clearing what must
+ * start at zero itself: calls that overlap on one device (two streams, two
+ * threads) race and must be serialised by the caller.  Waits for the work
+ * only when out is host memory; otherwise the work is queued on the stream.
+ * Other arguments, the result and the errors are those of tvs_initial_fbp. */
+int tvs_initial_fbp_noalloc(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_device,
+                            void *stream);
+
 /* Counters and timings of the context. */
 int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out);
 

@@ -158,6 +158,17 @@ k_median(GridDev g, const double *x, float *out)
     out[o] = (float)med;
 }
 
+// cs[2a], cs[2a+1] = cos, sin of angle a * 2 pi / A, formed on the device
+// (the allocation-free entry point takes no host table)
+__global__ void __launch_bounds__(kThreads) k_fbp_angles(int32_t A, double *cs)
+{
+    const int32_t a = (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (a >= A) return;
+    const double phi = (double)a * (2.0 * kPi / (double)A);
+    cs[2 * a] = cos(phi);
+    cs[2 * a + 1] = sin(phi);
+}
+
 __global__ void __launch_bounds__(kThreads) k_narrow_abi(const double *x, int64_t n, float *out)
 {
     const int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -200,6 +211,13 @@ hipError_t launch_fbp_backproject(const GridDev &g, const double *q, const doubl
     const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
     hipLaunchKernelGGL(k_fbp_backproject, grid_for(nvox), dim3(kThreads), 0, stream, g, q, cs, A,
                        tau, nt, clip, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_fbp_angles(int32_t A, double *cs, hipStream_t stream)
+{
+    if (A <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fbp_angles, grid_for(A), dim3(kThreads), 0, stream, A, cs);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -59,6 +60,42 @@ int64_t draw_ell(int64_t k, int64_t ell, uint64_t &state)
     uint64_t span = (uint64_t)(ell - k) + 1u;
     unsigned __int128 p = (unsigned __int128)u * span;
     return k + (int64_t)(uint64_t)(p >> 64);
+}
+
+// Device workspace of tvs_initial_fbp_noalloc: one file-scope array, held by
+// every device the library runs on until the process ends.  Host code never
+// uses the array's name as an address: each device's copy is looked up once
+// (fbp_scratch_setup, from tvs_create with that device current) and its
+// address is passed to the kernels.
+constexpr size_t kFbpScratchBytes = (size_t)64 << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kFbpScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_status[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Looks up this device's copy of `scratch` (the device must be current).
+void fbp_scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_done[dev]) return;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+    g_scratch_status[dev] = e;
+    g_scratch_done[dev] = true;
 }
 
 }  // namespace
@@ -845,6 +882,7 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg.device < 0 || cfg.device >= ndev)
         return TVS_EDEVICE;
     if (hipSetDevice(cfg.device) != hipSuccess) return TVS_EDEVICE;
+    fbp_scratch_setup(cfg.device);
 
     ctx = new tvs_ctx();
     ctx->grid = *grid;
@@ -1048,30 +1086,55 @@ int tvs_set_image(tvs_ctx *ctx, const float *x0, int on_device, void *stream)
     return TVS_OK;
 }
 
-int tvs_initial_fbp(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_device, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Checks the FBP parameters against the context and sizes the bins: lateral
+// bin width tau, nt lateral bins (2 ceil(R / tau) + 2, R the farthest slice
+// corner from the axis), nb = A * nz * nt bins.
+int fbp_geometry(tvs_ctx *ctx, const tvs_fbp_params *p, const char *who, double &tau,
+                 int32_t &nt, int64_t &nb)
 {
-    if (!ctx) return TVS_EINVAL;
-    ctx->err.clear();
     if (!p) return fail(ctx, TVS_EINVAL, "params is NULL");
     if (p->n_angles < 1) return fail(ctx, TVS_EINVAL, "n_angles must be >= 1");
     if (!(p->t_bin_mm >= 0.0) || !std::isfinite(p->t_bin_mm))
         return fail(ctx, TVS_EINVAL, "t_bin_mm must be finite and >= 0");
     if (p->median_radius < 0 || p->median_radius > 2)
         return fail(ctx, TVS_EINVAL, "median_radius must lie in 0..2");
-    if (!ctx->loaded) return fail(ctx, TVS_ESTATE, "tvs_initial_fbp before tvs_load_histories");
-    HIPCHK(hipSetDevice(ctx->cfg.device));
-    hipStream_t st = pick(ctx, stream);
+    if (!ctx->loaded) return fail(ctx, TVS_ESTATE, std::string(who) + " before tvs_load_histories");
     const tvs_grid &g = ctx->grid;
-    const double tau = p->t_bin_mm > 0.0 ? p->t_bin_mm : g.vx;
-    // lateral bins: 2 ceil(R / tau) + 2, R the farthest slice corner from the axis
+    tau = p->t_bin_mm > 0.0 ? p->t_bin_mm : g.vx;
     double R = 0.0;
     for (int cx = 0; cx < 2; cx++)
         for (int cy = 0; cy < 2; cy++)
             R = std::max(R, std::hypot(g.ox + cx * g.nx * g.vx, g.oy + cy * g.ny * g.vy));
     const double ntd = 2.0 * std::ceil(R / tau) + 2.0;
     if (!(ntd <= 16777216.0)) return fail(ctx, TVS_EINVAL, "t_bin_mm too small for the grid");
-    const int32_t nt = (int32_t)ntd, A = p->n_angles;
-    const int64_t nb = (int64_t)A * g.nz * nt;
+    nt = (int32_t)ntd;
+    nb = (int64_t)p->n_angles * g.nz * nt;
+    return TVS_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+int tvs_initial_fbp(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_device, void *stream)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    double tau = 0.0;
+    int32_t nt = 0;
+    int64_t nb = 0;
+    int rc = fbp_geometry(ctx, p, "tvs_initial_fbp", tau, nt, nb);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    const tvs_grid &g = ctx->grid;
+    const int32_t A = p->n_angles;
 
     unsigned long long *sum = nullptr;
     uint32_t *cnt = nullptr;
@@ -1084,7 +1147,7 @@ int tvs_initial_fbp(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_de
         dfree(ctx, &cs, (size_t)(2 * A));
         dfree(ctx, &img, (size_t)ctx->nimg);
     };
-    int rc = dalloc(ctx, &sum, (size_t)nb);
+    rc = dalloc(ctx, &sum, (size_t)nb);
     if (!rc) rc = dalloc(ctx, &cnt, (size_t)nb);
     if (!rc) rc = dalloc(ctx, &pb, (size_t)nb);
     if (!rc) rc = dalloc(ctx, &qb, (size_t)nb);
@@ -1122,6 +1185,81 @@ int tvs_initial_fbp(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_de
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     release();
     if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("initial fbp: ") + hipGetErrorString(e));
+    reset_state(ctx);
+    ctx->batch.valid = false;
+    return TVS_OK;
+}
+
+int tvs_initial_fbp_noalloc(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_device,
+                            void *stream)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    double tau = 0.0;
+    int32_t nt = 0;
+    int64_t nb = 0;
+    int rc = fbp_geometry(ctx, p, "tvs_initial_fbp_noalloc", tau, nt, nb);
+    if (rc) return rc;
+    const int32_t A = p->n_angles;
+    // workspace layout: bin sums and counts (cleared), mean and filtered
+    // projections, angle table, backprojected image; each part 256-aligned
+    const size_t o_sum = 0;
+    const size_t o_cnt = o_sum + align256(sizeof(unsigned long long) * (size_t)nb);
+    const size_t o_pb = o_cnt + align256(sizeof(uint32_t) * (size_t)nb);
+    const size_t o_qb = o_pb + align256(sizeof(double) * (size_t)nb);
+    const size_t o_cs = o_qb + align256(sizeof(double) * (size_t)nb);
+    const size_t o_img = o_cs + align256(sizeof(double) * 2 * (size_t)A);
+    const size_t need = o_img + align256(sizeof(double) * (size_t)ctx->nimg);
+    if (need > kFbpScratchBytes)
+        return fail(ctx, TVS_ERANGE,
+                    "tvs_initial_fbp_noalloc needs " + std::to_string(need) +
+                        " B of workspace (" + std::to_string(nb) + " bins, " +
+                        std::to_string(ctx->nimg) + " voxels); its fixed workspace holds " +
+                        std::to_string(kFbpScratchBytes) + " B");
+    const int dev = ctx->cfg.device;
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(ctx, TVS_EDEVICE, "device ordinal beyond the workspace table");
+    HIPCHK(hipSetDevice(dev));
+    fbp_scratch_setup(dev);
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev])
+            return fail(ctx, TVS_EDEVICE,
+                        std::string("workspace address lookup failed: ") +
+                            hipGetErrorString(g_scratch_status[dev]));
+        base = static_cast<unsigned char *>(g_scratch_ptr[dev]);
+    }
+    hipStream_t st = pick(ctx, stream);
+    auto *sum = reinterpret_cast<unsigned long long *>(base + o_sum);
+    auto *cnt = reinterpret_cast<uint32_t *>(base + o_cnt);
+    auto *pb = reinterpret_cast<double *>(base + o_pb);
+    auto *qb = reinterpret_cast<double *>(base + o_qb);
+    auto *cs = reinterpret_cast<double *>(base + o_cs);
+    auto *img = reinterpret_cast<double *>(base + o_img);
+    const tvs_grid &g = ctx->grid;
+    // sums and counts start at zero (a fill kernel: the workspace keeps the
+    // previous call's contents)
+    hipError_t e = tvs::launch_zero_i64(reinterpret_cast<long long *>(base + o_sum),
+                                        (int64_t)(o_pb / sizeof(long long)), st);
+    if (e == hipSuccess) e = tvs::launch_fbp_angles(A, cs, st);
+    if (e == hipSuccess) e = tvs::launch_fbp_bin(ctx->gd, hist_dev(ctx), ctx->nh, A, tau, nt, sum, cnt, st);
+    if (e == hipSuccess) e = tvs::launch_fbp_mean(sum, cnt, nb, pb, st);
+    if (e == hipSuccess) e = tvs::launch_fbp_filter(pb, (int64_t)A * g.nz, nt, tau, qb, st);
+    if (e == hipSuccess)
+        e = tvs::launch_fbp_backproject(ctx->gd, qb, cs, A, tau, nt, p->clip_negative ? 1 : 0, img, st);
+    if (e == hipSuccess) e = tvs::launch_median(ctx->gd, img, p->median_radius, ctx->xio, st);
+    if (e == hipSuccess) e = tvs::launch_widen(ctx->gd, ctx->xio, ctx->x, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->x0, ctx->x, sizeof(double) * ctx->nvox, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = tvs::launch_set_counter(reinterpret_cast<int32_t *>(ctx->flags + kFlagRange), 0, st);
+    if (e == hipSuccess && out)
+        e = hipMemcpyAsync(out, ctx->xio, sizeof(float) * ctx->nimg,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && out && !on_device) e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return fail(ctx, TVS_EDEVICE, std::string("initial fbp (no-alloc): ") + hipGetErrorString(e));
     reset_state(ctx);
     ctx->batch.valid = false;
     return TVS_OK;

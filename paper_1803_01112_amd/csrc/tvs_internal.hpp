@@ -184,6 +184,8 @@ hipError_t launch_fbp_backproject(const GridDev &g, const double *q, const doubl
                                   double tau, int32_t nt, int clip, double *x, hipStream_t stream);
 hipError_t launch_median(const GridDev &g, const double *x, int radius, float *out,
                          hipStream_t stream);
+// cos and sin of the A beam angles a * 2 pi / A into cs (2 A doubles).
+hipError_t launch_fbp_angles(int32_t A, double *cs, hipStream_t stream);
 hipError_t launch_pick(const int64_t *src, int64_t stride, int64_t n, int64_t *dst,
                        hipStream_t stream);
 // Fills the entry-side table of m for depths j = 0 .. nj - 1 (3 doubles each).

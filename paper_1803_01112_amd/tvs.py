@@ -26,7 +26,8 @@ EXPORTED = ("tvs_config_default", "tvs_create", "tvs_destroy", "tvs_load_histori
             "tvs_debug_rows", "tvs_strerror", "tvs_last_error", "tvs_iterate_batch",
             "tvs_get_batch_image", "tvs_server_config_default", "tvs_server_create",
             "tvs_server_footprint", "tvs_server_submit", "tvs_server_query", "tvs_server_wait",
-            "tvs_server_get_counters", "tvs_server_destroy", "tvs_autotune", "tvs_initial_fbp")
+            "tvs_server_get_counters", "tvs_server_destroy", "tvs_autotune", "tvs_initial_fbp",
+            "tvs_initial_fbp_noalloc")
 
 
 class TvsError(RuntimeError):
@@ -152,6 +153,8 @@ def load_library(path: str = LIB):
     L.tvs_iterate_batch.argtypes = [C.c_void_p, P(Params), C.c_int32, C.c_int32, C.c_void_p]
     L.tvs_get_batch_image.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int, C.c_void_p]
     L.tvs_initial_fbp.argtypes = [C.c_void_p, P(FbpParams), C.c_void_p, C.c_int, C.c_void_p]
+    L.tvs_initial_fbp_noalloc.argtypes = [C.c_void_p, P(FbpParams), C.c_void_p, C.c_int,
+                                          C.c_void_p]
     L.tvs_get_step_log.argtypes = [C.c_void_p, P(StepLog), C.c_int64, P(C.c_int64)]
     L.tvs_debug_rows.argtypes = [C.c_void_p, C.c_int64, C.c_int64, P(C.c_int64), P(C.c_int32),
                                  _FP, _FP, C.c_int64]
@@ -177,7 +180,8 @@ def load_library(path: str = LIB):
         getattr(L, name).restype = C.c_int
     for name in ("tvs_create", "tvs_load_histories", "tvs_set_image", "tvs_iterate",
                  "tvs_get_image", "tvs_get_stats", "tvs_get_step_log", "tvs_debug_rows",
-                 "tvs_iterate_batch", "tvs_get_batch_image", "tvs_initial_fbp"):
+                 "tvs_iterate_batch", "tvs_get_batch_image", "tvs_initial_fbp",
+                 "tvs_initial_fbp_noalloc"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -408,6 +412,21 @@ class Context:
             out = np.zeros(self.nvox, np.float32)
         p, d, st, wait = _out_ptr(out, self.nvox, stream)
         self._check(self._L.tvs_initial_fbp(self._h, C.byref(prm), p, d, st), "tvs_initial_fbp")
+        _settle(out, wait)
+        return out
+
+    def initial_fbp_noalloc(self, n_angles, median_radius=2, t_bin_mm=0.0, clip_negative=True,
+                            out=None, stream=None):
+        """initial_fbp through tvs_initial_fbp_noalloc: the library's fixed
+        per-device workspace instead of allocations; with a device `out` the
+        work is queued on torch's current stream (or waited for, when that is
+        torch's default stream, whose null handle names the context's stream)."""
+        prm = FbpParams(int(n_angles), int(median_radius), float(t_bin_mm), int(bool(clip_negative)), 0)
+        if out is None:
+            out = np.zeros(self.nvox, np.float32)
+        p, d, st, wait = _out_ptr(out, self.nvox, stream)
+        self._check(self._L.tvs_initial_fbp_noalloc(self._h, C.byref(prm), p, d, st),
+                    "tvs_initial_fbp_noalloc")
         _settle(out, wait)
         return out
 
