@@ -1,0 +1,137 @@
+"""GPU parity on the shapes of the benchmark configurations, through the C ABI.
+
+  * the 24-setting parameter study (lambda in {1e-4, 2e-4} x N in {1, 3, 6} x
+    alpha in {0.5, 0.75, 0.85, 0.95}; arXiv 1803.01112, Section III-E) as one
+    batch: more than 8 settings, so the batched DROP step runs its settings in
+    several groups per tile; every image against its own single run, one
+    setting of each group against the oracle;
+  * the two-slice sub-problem of the 256x256x32 phantom (256x256x2, 3.75M
+    histories at 360 angles, B = 3200, three cycles at lambda = 1e-4, N = 5,
+    alpha = 0.75): every path form against the oracle, the float16 chord
+    store bounded near its measured error;
+  * the 200x200x16 volume's shape: a 1M-history prefix of its scan at
+    B = 3200, lambda = 1e-4, N = 5 (313 DROP blocks).
+Images: max |x - x_oracle| / max(|x_oracle|, 0.1) <= 1e-4 unless stated.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1803_01112_amd import synth, tvs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def rel_err(x, ref):
+    ref = np.asarray(ref, np.float64)
+    return float(np.max(np.abs(np.asarray(x, np.float64) - ref) / np.maximum(np.abs(ref), 0.1)))
+
+
+def study_settings():
+    out = []
+    for lam in (1e-4, 2e-4):
+        for N in (1, 3, 6):
+            for alpha in (0.5, 0.75, 0.85, 0.95):
+                out.append(dict(lam=lam, N=N, alpha=alpha, seed=1803 + len(out)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def slice64_full():
+    w = synth.workload("slice64")
+    h = w.histories()
+    rows = oracle.build_rows(w.grid, h, 2.0)
+    return w, h, rows
+
+
+@pytest.mark.parametrize("path_mode", ["f32", "otf"])
+def test_batch_of_24_study_settings(slice64_full, path_mode):
+    w, h, rows = slice64_full
+    x0 = w.initial_image()
+    sets = study_settings()
+    K = 3
+    print(f"24-setting batch, slice64, {path_mode}", flush=True)
+    with tvs.Context(w.grid, block_size=3200, mlp_step_mm=2.0, path_mode=path_mode,
+                     chunk_histories=19200) as ctx:
+        ctx.load_histories(h)
+        ctx.set_image(x0)
+        ctx.iterate_batch(K, sets)
+        assert ctx.stats()["batch_size"] == 24
+        imgs = [ctx.get_batch_image(q) for q in range(24)]
+        worst = 0.0
+        for q, st in enumerate(sets):
+            ctx.set_image(x0)
+            ctx.iterate(K, st["lam"], st["N"], st["alpha"], seed=st["seed"])
+            e = rel_err(imgs[q], ctx.get_image())
+            worst = max(worst, e)
+            assert e <= 1e-5, q
+    print(f"batch vs single runs: max {worst:.2e}")
+    moved = [float(np.max(np.abs(imgs[q] - x0))) for q in range(24)]
+    assert min(moved) > 1e-3                               # every setting changed its image
+    for q in (3, 12, 21):                                  # one setting of each group of 8
+        st = sets[q]
+        S = oracle.Superiorizer(w.grid, rows, x0, 3200)
+        S.iterate(K, st["lam"], st["N"], st["alpha"], seed=st["seed"])
+        e = rel_err(imgs[q], S.x)
+        print(f"setting {q} {st}: vs oracle {e:.2e}")
+        assert e <= TOL, q
+
+
+@pytest.fixture(scope="module")
+def slab256():
+    w = synth.workload("slab256")
+    h = w.histories()
+    print(f"slab256: {w.n_hist} histories; oracle rows", flush=True)
+    rows = oracle.build_rows(w.grid, h, 1.0)
+    x0 = w.initial_image()
+    S = oracle.Superiorizer(w.grid, rows, x0, 3200)
+    S.iterate(3, 1e-4, 5, 0.75, seed=1803011121)
+    del rows
+    return w, h, x0, S.x
+
+
+@pytest.mark.parametrize("path_mode,bound", [("f32", TOL), ("otf", TOL), ("f16", 1e-3)])
+def test_two_slice_subproblem_of_the_256_volume(slab256, path_mode, bound):
+    """The mixed-precision configuration's error is stated on this
+    sub-problem: the float32 chord store and on-the-fly rows meet 1e-4;
+    the float16 chord store (2^-11 relative rounding per chord) measured
+    6.3e-4 and is held to 1e-3, so a regression of it shows."""
+    import torch
+    w, h, x0, ref = slab256
+    dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in h.items()}
+    with tvs.Context(w.grid, block_size=3200, path_mode=path_mode) as ctx:
+        ctx.load_histories(dev)
+        ctx.set_image(x0)
+        ctx.iterate(3, 1e-4, 5, 0.75, seed=1803011121)
+        x = ctx.get_image()
+    e = rel_err(x, ref)
+    d = np.abs(x.astype(np.float64) - ref) / np.maximum(np.abs(ref), 0.1)
+    print(f"slab256 {path_mode}: max {e:.3e}, rms {np.sqrt(np.mean(d * d)):.3e}")
+    assert np.max(np.abs(ref - x0)) > 1e-3                  # the image moved
+    assert e <= bound
+
+
+def test_volume_shape_prefix_of_the_200_scan():
+    import torch
+    w = synth.workload("vol200")
+    n = 1_000_000
+    h = w.histories(count=n)
+    print(f"vol200 prefix: {n} histories, B = 3200; oracle rows", flush=True)
+    rows = oracle.build_rows(w.grid, h, 1.0)
+    x0 = w.initial_image()
+    S = oracle.Superiorizer(w.grid, rows, x0, 3200)
+    S.iterate(2, 1e-4, 5, 0.75, seed=7)
+    del rows
+    dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in h.items()}
+    for mode in ("otf", "f32"):
+        with tvs.Context(w.grid, block_size=3200, path_mode=mode) as ctx:
+            ctx.load_histories(dev)
+            ctx.set_image(x0)
+            ctx.iterate(2, 1e-4, 5, 0.75, seed=7)
+            x = ctx.get_image()
+            st = ctx.stats()
+        e = rel_err(x, S.x)
+        print(f"vol200 prefix {mode}: max {e:.3e}, ell {st['ell']} (oracle {S.state.ell})")
+        assert st["ell"] == S.state.ell
+        assert e <= TOL

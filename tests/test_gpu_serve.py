@@ -1,10 +1,12 @@
 """Serving on the GPU: requests of different grids, history counts and
 parameters run concurrently on their own contexts; each result must equal
 the same request run alone (within 1e-5 relative: only the order of float
-atomics differs), and a failing request must fail alone."""
+atomics differs) and, for requests of two grids, the oracle (1e-4), and a
+failing request must fail alone."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_1803_01112_amd import synth, tvs
 
 pytestmark = pytest.mark.gpu
@@ -47,6 +49,16 @@ def test_mix_equals_alone():
     for q, ((img, info), ref) in enumerate(zip(res, alone)):
         assert info["status"] == 0, q
         assert rel_err(img, ref) <= 1e-5, q
+    # two requests of the mix, of different grids, against the oracle
+    for q in (1, 2):
+        r = reqs[q]
+        rows = oracle.build_rows(r["w"].grid, r["h"], 1.0)
+        S = oracle.Superiorizer(r["w"].grid, rows, r["x0"], 3200)
+        S.iterate(r["K"], r["lam"], r["N"], r["alpha"], seed=r["seed"])
+        e = rel_err(res[q][0], S.x)
+        print(f"served request {q} ({r['w'].name}, {len(r['h']['ex'])} histories): "
+              f"vs oracle {e:.2e}")
+        assert e <= 1e-4, q
 
 
 def test_failing_request_fails_alone():
