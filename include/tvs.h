@@ -67,7 +67,15 @@ typedef struct {
 enum tvs_path_mode {
     TVS_PATH_ON_THE_FLY = 0, /* MLP walked for every history on every sweep */
     TVS_PATH_STORE_F32 = 1,  /* rows formed once: 32-bit entry tag + float32 chord */
-    TVS_PATH_STORE_F16 = 2   /* rows formed once: 32-bit entry tag + float16 chord */
+    TVS_PATH_STORE_F16 = 2,  /* rows formed once: 32-bit entry tag + float16 chord */
+    TVS_PATH_STORE_Q16 = 3   /* rows formed once, 6 bytes per entry like float16: a 32-bit
+                                entry tag + a 16-bit word; the chord is a fixed-point code
+                                (a multiple of the longest chord of the loaded rows / the
+                                largest code) of 16 + 24 - ceil(log2 B) bits (at most 30):
+                                its low 16 bits in the word, the rest in the tag bits that
+                                the row index of a block of B histories leaves free (28 bits
+                                at B = 3200: 1e-8 mm steps for 1 x 1 x 2.5 mm voxels);
+                                B <= 2^20 */
 };
 
 typedef struct {

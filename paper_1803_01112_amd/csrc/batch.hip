@@ -17,7 +17,8 @@ namespace tvs {
 namespace {
 
 constexpr int kThreads = 256;
-using dev::chord_at;
+using dev::entry_chord;
+using dev::row_of;
 using dev::kNoRow;
 
 constexpr double kDotUnit = 1.0 / kDotScale;
@@ -196,14 +197,6 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
         c1 = A.C.toff[T + 1];
     }
     if (p0 == p1 && c0 == c1) return;
-    const CH *chp = nullptr, *chc = nullptr;
-    if constexpr (sizeof(CH) == 4) {
-        chp = A.P.ch32;
-        chc = A.C.ch32;
-    } else {
-        chp = A.P.ch16;
-        chc = A.C.ch16;
-    }
     double *xt = A.x + (T << kTileShift) * S;
     // the first round of both lists and the finished rows' data, loaded once
     // for all setting groups
@@ -212,15 +205,15 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
     const bool pok = p0 + t < p1, cok = c0 + t < c1;
     if (pok) {
         pm = A.P.meta[p0 + t - A.P.base];
-        pa = (double)chord_at(chp, p0 + t - A.P.base);
+        pa = (double)entry_chord<CH>(A.P, p0 + t - A.P.base, pm);
     }
     if (cok) {
         cm = A.C.meta[c0 + t - A.C.base];
-        ca = (double)chord_at(chc, c0 + t - A.C.base);
+        ca = (double)entry_chord<CH>(A.C, c0 + t - A.C.base, cm);
     }
-    if (pok && (pm >> kTileShift) < A.P.rows) {
-        pw = (double)A.P.wepl[pm >> kTileShift];
-        pn2 = (double)A.P.n2[pm >> kTileShift];
+    if (pok && row_of(A.P, pm) < A.P.rows) {
+        pw = (double)A.P.wepl[row_of(A.P, pm)];
+        pn2 = (double)A.P.n2[row_of(A.P, pm)];
     }
     // one group of settings per workgroup (the grid's second dimension)
     {
@@ -241,12 +234,12 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
                 const bool first = e == p0 + t;
                 const uint32_t m = first ? pm : A.P.meta[e - A.P.base];
                 const int w = (int)(m & (kTileWords - 1));
-                const uint32_t q = m >> kTileShift;
+                const uint32_t q = row_of(A.P, m);
                 if (q >= A.P.rows) {
                     atomicOr(A.err, 2u);
                     continue;
                 }
-                const double a = first ? pa : (double)chord_at(chp, e - A.P.base);
+                const double a = first ? pa : (double)entry_chord<CH>(A.P, e - A.P.base, m);
                 const double wp = first ? pw : (double)A.P.wepl[q];
                 const double n2 = first ? pn2 : (double)A.P.n2[q];
                 const double an2 = a / n2;   // one division for all settings
@@ -291,9 +284,9 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
             if (e < c1) {
                 const bool first = r0 == c0;
                 const uint32_t m = first ? cm : A.C.meta[e - A.C.base];
-                q = m >> kTileShift;
+                q = row_of(A.C, m);
                 w = (int)(m & (kTileWords - 1));
-                a = first ? ca : (double)chord_at(chc, e - A.C.base);
+                a = first ? ca : (double)entry_chord<CH>(A.C, e - A.C.base, m);
                 if (q >= A.C.rows) {
                     atomicOr(A.err, 2u);
                     q = kNoRow;
@@ -392,9 +385,12 @@ hipError_t launch_drop_tiles_batch(const DropTileArgs &a, const BatchBuffers &b,
                                    hipStream_t stream)
 {
     if (ntiles <= 0 || (!a.P.valid && !a.C.valid)) return hipSuccess;
-    const bool half = a.P.valid ? (a.P.ch16 != nullptr) : (a.C.ch16 != nullptr);
+    const TileBlock &v = a.P.valid ? a.P : a.C;
     const dim3 grid((unsigned)(a.tiles ? a.nact : ntiles), (unsigned)((b.S + kGroup - 1) / kGroup));
-    if (half)
+    if (v.chq)
+        hipLaunchKernelGGL(k_drop_tile_batch<uint16_t>, grid, dim3(kThreads), 0, stream, a, b.S,
+                           (const double *)b.lambda);
+    else if (v.ch16)
         hipLaunchKernelGGL(k_drop_tile_batch<__half>, grid, dim3(kThreads), 0, stream, a, b.S,
                            (const double *)b.lambda);
     else

@@ -6,6 +6,7 @@
 #include <hip/hip_fp16.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "tvs_internal.hpp"
 
@@ -14,11 +15,26 @@ namespace dev {
 
 constexpr uint32_t kNoRow = 0xffffffffu;
 
-template <typename CH>
-__device__ inline float chord_at(const CH *p, int64_t e)
+// Row (within its block) of an entry tag.
+__device__ inline uint32_t row_of(const TileBlock &t, uint32_t m)
 {
-    if constexpr (sizeof(CH) == 4) return p[e];
-    else return __half2float(p[e]);
+    return (m >> kTileShift) & t.rowmask;
+}
+
+// Chord of entry e (index into the block's arrays) with tag m: float32,
+// float16, or fixed point (the low 16 bits of the code in chq, the high bits
+// in the tag above the row field) in units of qunit mm.
+template <typename CH>
+__device__ inline float entry_chord(const TileBlock &t, int64_t e, uint32_t m)
+{
+    if constexpr (sizeof(CH) == 4) {
+        return t.ch32[e];
+    } else if constexpr (std::is_same<CH, uint16_t>::value) {
+        const uint32_t code = ((m >> t.qshift) << 16) | (uint32_t)t.chq[e];
+        return (float)((double)code * t.qunit);
+    } else {
+        return __half2float(t.ch16[e]);
+    }
 }
 
 // Wavefront bookkeeping for sums over runs of equal keys: lanes holding the

@@ -36,18 +36,12 @@
 namespace tvs {
 namespace {
 
-using dev::chord_at;
+using dev::entry_chord;
 using dev::kNoRow;
+using dev::row_of;
 
 constexpr double kDotUnit = 1.0 / kDotScale;
 constexpr double kCorrUnit = 1.0 / kCorrScale;
-
-template <typename CH>
-__device__ inline const CH *chords(const TileBlock &t);
-template <>
-__device__ inline const float *chords<float>(const TileBlock &t) { return t.ch32; }
-template <>
-__device__ inline const __half *chords<__half>(const TileBlock &t) { return t.ch16; }
 
 // LDS of one tile workgroup.
 struct TileLds {
@@ -71,7 +65,7 @@ __device__ inline Ent load_ent(const TileBlock &B, int64_t e, int64_t end)
     Ent r;
     if (e < end) {
         r.m = B.meta[e - B.base];
-        r.a = chord_at(chords<CH>(B), e - B.base);
+        r.a = entry_chord<CH>(B, e - B.base, r.m);
         r.ok = true;
     }
     return r;
@@ -86,7 +80,7 @@ struct RowData {
 __device__ inline RowData load_row(const TileBlock &P, const Ent &en)
 {
     RowData d;
-    const uint32_t q = en.m >> kTileShift;
+    const uint32_t q = row_of(P, en.m);
     if (en.ok && q < P.rows) {
         d.wepl = (double)P.wepl[q];
         d.n2 = (double)P.n2[q];
@@ -100,7 +94,7 @@ __device__ inline void finish_one(const TileBlock &P, const Ent &en, const RowDa
                                   double big, uint32_t *err)
 {
     if (!en.ok) return;
-    const uint32_t q = en.m >> kTileShift;
+    const uint32_t q = row_of(P, en.m);
     if (q >= P.rows) {
         atomicOr(err, 2u);
         return;
@@ -149,7 +143,6 @@ __device__ void tile_dots(const TileBlock &C, int64_t c0, int64_t c1, const Ent 
                           const TileLds &L, double dot_max, uint32_t *err)
 {
     // every thread runs the same number of rounds (the shuffles are uniform)
-    const CH *ch = chords<CH>(C);
     uint32_t m = e0.m;
     float a = e0.a;
     bool ok = e0.ok;
@@ -159,13 +152,13 @@ __device__ void tile_dots(const TileBlock &C, int64_t c0, int64_t c1, const Ent 
             ok = e < c1;
             if (ok) {
                 m = C.meta[e - C.base];
-                a = chord_at(ch, e - C.base);
+                a = entry_chord<CH>(C, e - C.base, m);
             }
         }
         uint32_t q = kNoRow;
         long long f = 0;
         if (ok) {
-            q = m >> kTileShift;
+            q = row_of(C, m);
             const double p = (double)a * L.x[m & (kTileWords - 1)];
             if (q >= C.rows) {
                 atomicOr(err, 2u);
@@ -348,9 +341,10 @@ hipError_t launch_drop_tiles(const DropTileArgs &a, int64_t ntiles, int threads,
     if (ntiles <= 0 || (!a.P.valid && !a.C.valid)) return hipSuccess;
     const KTimer none{};
     const KTimer &t = kt ? *kt : none;
-    const bool half = a.P.valid ? (a.P.ch16 != nullptr) : (a.C.ch16 != nullptr);
-    return half ? drop_tiles_nt<__half>(a, ntiles, threads, split, stream, t)
-                : drop_tiles_nt<float>(a, ntiles, threads, split, stream, t);
+    const TileBlock &v = a.P.valid ? a.P : a.C;
+    if (v.chq) return drop_tiles_nt<uint16_t>(a, ntiles, threads, split, stream, t);
+    if (v.ch16) return drop_tiles_nt<__half>(a, ntiles, threads, split, stream, t);
+    return drop_tiles_nt<float>(a, ntiles, threads, split, stream, t);
 }
 
 hipError_t launch_tile_active(const int64_t *bt_off, int64_t nblocks, int64_t ntiles,

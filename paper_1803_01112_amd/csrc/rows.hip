@@ -14,6 +14,8 @@
 // Decisions that pick voxel indices are taken in float64; chords are
 // rounded to float32 (or float16) only when written.  This file must be
 // compiled with -ffp-contract=off so that no multiply-add is fused.
+#include <type_traits>
+
 #include "tvs_internal.hpp"
 
 namespace tvs {
@@ -117,6 +119,15 @@ __device__ inline void mvec(const M2 &A, double x0, double x1, double &y0, doubl
 //   kTiled    writes every entry into its tile list at the reserved place.
 enum EmitMode { kCount = 0, kSeg = 1, kRowMajor = 2, kTiled = 3 };
 
+// A chord as an unsigned multiple of the fixed-point store's unit (1 / qinv
+// mm), rounded to nearest; the unit is the longest chord of the loaded rows
+// / qmax, rounded up, so the clamp only catches rounding at the top.
+__device__ inline uint32_t encode_fixed(double len, double qinv, uint32_t qmax)
+{
+    const double u = rint(len * qinv);
+    return u > (double)qmax ? qmax : (uint32_t)u;
+}
+
 template <int MODE, typename CH>
 struct Emit {
     int32_t cur = -1;
@@ -128,6 +139,10 @@ struct Emit {
     uint32_t seg_len = 0;        // kSeg: entries of the open segment
     int32_t *idx = nullptr;      // kRowMajor
     CH *chord = nullptr;         // kRowMajor, kTiled
+    double qinv = 0.0;           // kTiled, fixed-point chords: units per mm
+    uint32_t qmax = 0;           // kTiled, fixed-point chords: largest code
+    uint32_t qshift = 31;        // kTiled, fixed-point chords: tag bit of the code's bit 16
+    double maxc = 0.0;           // kSeg: longest entry of the row
     uint32_t *btc = nullptr;     // kSeg: list lengths of this row's block
     uint64_t *segtab = nullptr;  // kSeg: (tile, place) of this row's segments
     const int64_t *segdst = nullptr;  // kTiled: first entry of this row's segments
@@ -189,14 +204,25 @@ struct Emit {
             if (ok && (dst < 0 || dst >= cap)) bad();
             if (ok) {
                 const int slot = ns * kThreads + (int)threadIdx.x;
-                stage_meta()[slot] = (uint32_t)(cur & (kTileWords - 1)) | (q << kTileShift);
-                if constexpr (sizeof(CH) == 4) stage_chord()[slot] = (float)cur_len;
-                else stage_chord()[slot] = __float2half((float)cur_len);
+                uint32_t tag = (uint32_t)(cur & (kTileWords - 1)) | (q << kTileShift);
+                if constexpr (sizeof(CH) == 4) {
+                    stage_chord()[slot] = (float)cur_len;
+                } else if constexpr (std::is_same<CH, uint16_t>::value) {
+                    const uint32_t code = encode_fixed(cur_len, qinv, qmax);
+                    tag |= (code >> 16) << qshift;
+                    stage_chord()[slot] = (uint16_t)(code & 0xffffu);
+                } else {
+                    stage_chord()[slot] = __float2half((float)cur_len);
+                }
+                stage_meta()[slot] = tag;
                 dst++;
                 if (++ns == kStage) drain();
             }
         }
-        if constexpr (MODE == kSeg) seg_len++;
+        if constexpr (MODE == kSeg) {
+            seg_len++;
+            maxc = fmax(maxc, cur_len);
+        }
         norm2 += cur_len * cur_len;
         n++;
         cur = -1;
@@ -504,18 +530,31 @@ k_rows_count(GridDev g, HistDev H, MlpCfg m, int64_t first, int64_t n, int32_t *
 __global__ void __launch_bounds__(kThreads, kRowWaves)
 k_rows_seg(GridDev g, HistDev H, MlpCfg m, int64_t n, int64_t B, int64_t ntiles,
            const int64_t *seg_off, uint32_t *btc, uint64_t *segtab, uint32_t *err,
-           const int32_t *order)
+           uint32_t *chmax, const int32_t *order)
 {
     int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    if (order) i = order[i];
-    Emit<kSeg, float> e;
-    e.btc = btc + (i / B) * ntiles;
-    e.segtab = segtab + seg_off[i];
-    e.seg_cap = (int32_t)(seg_off[i + 1] - seg_off[i]);
-    e.err = err;
-    form_row<kSeg, float>(g, H, m, i, e);
-    e.finish();
+    uint32_t bits = 0u;
+    if (i < n) {
+        if (order) i = order[i];
+        Emit<kSeg, float> e;
+        e.btc = btc + (i / B) * ntiles;
+        e.segtab = segtab + seg_off[i];
+        e.seg_cap = (int32_t)(seg_off[i + 1] - seg_off[i]);
+        e.err = err;
+        form_row<kSeg, float>(g, H, m, i, e);
+        e.finish();
+        // longest chord as float32 bits, rounded up (non-negative floats
+        // order as their bit patterns)
+        float mf = (float)e.maxc;
+        if ((double)mf < e.maxc) mf = nextafterf(mf, INFINITY);
+        bits = __float_as_uint(mf);
+    }
+    // the wavefront's maximum (every lane takes part), one atomic per wavefront
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(bits, d, 64);
+        bits = o > bits ? o : bits;
+    }
+    if ((threadIdx.x & 63) == 0 && chmax && bits) atomicMax(chmax, bits);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -554,6 +593,9 @@ k_rows_fill_tiled(GridDev g, HistDev H, MlpCfg m, TileFill f, CH *chord)
         e.meta = f.meta;
         e.chord = chord;
         e.base = f.base;
+        e.qinv = f.qinv;
+        e.qmax = f.qmax;
+        e.qshift = f.qshift;
         e.q = (uint32_t)(i % f.B);
         form_row<kTiled, CH>(g, H, m, i, e);
         e.finish();
@@ -702,12 +744,13 @@ hipError_t launch_rows_count(const GridDev &g, const HistDev &h, const MlpCfg &m
 
 hipError_t launch_rows_seg(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t n,
                            int64_t B, const int64_t *seg_off, uint32_t *btc, uint64_t *segtab,
-                           uint32_t *err, const int32_t *order, hipStream_t stream)
+                           uint32_t *err, uint32_t *chmax, const int32_t *order,
+                           hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
     dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(k_rows_seg, grid, dim3(kThreads), 0, stream, g, h, m, n, B, num_tiles(g),
-                       seg_off, btc, segtab, err, order);
+                       seg_off, btc, segtab, err, chmax, order);
     return hipGetLastError();
 }
 
@@ -729,7 +772,10 @@ hipError_t launch_rows_fill_tiled(const GridDev &g, const HistDev &h, const MlpC
     int64_t wgs = (f.n + kThreads - 1) / kThreads;
     if (f.max_wgs > 0 && wgs > f.max_wgs) wgs = f.max_wgs;
     dim3 grid((unsigned)wgs);
-    if (f.ch16)
+    if (f.chq)
+        hipLaunchKernelGGL(k_rows_fill_tiled<uint16_t>, grid, dim3(kThreads), 0, stream, g, h, m,
+                           f, f.chq);
+    else if (f.ch16)
         hipLaunchKernelGGL(k_rows_fill_tiled<__half>, grid, dim3(kThreads), 0, stream, g, h, m, f,
                            f.ch16);
     else

@@ -61,7 +61,8 @@ uint64_t footprint(const tvs_request &r, int64_t chunk)
     if (r.path_mode == TVS_PATH_ON_THE_FLY) rows_held = 3 * std::min<uint64_t>(n, (uint64_t)chunk);  // ring of 3
     else rows_held = n;
     // entries: 32-bit tag + chord (float32, or float16 for the f16 store)
-    const uint64_t entry = (r.path_mode == TVS_PATH_STORE_F16) ? 6 : 8;
+    const uint64_t entry =
+        (r.path_mode == TVS_PATH_STORE_F16 || r.path_mode == TVS_PATH_STORE_Q16) ? 6 : 8;
     const uint64_t per_hist = 52 /* streams */ + 8 + 4 + 8 /* row_off, norm2, seg_off */ +
                               8 /* load-time counts */ + 8 * seg_est /* segment places */;
     const uint64_t lists = 12 * (nblocks * ntiles + 1) /* list starts + load-time counts */;
@@ -238,7 +239,7 @@ int tvs_server_submit(tvs_server *sv, const tvs_request *r, int64_t *id)
 {
     if (!sv || !r || !id) return TVS_EINVAL;
     if (!finite_grid(r->grid) || r->n < 0 || r->K < 0) return TVS_EINVAL;
-    if (r->path_mode < 0 || r->path_mode > 2) return TVS_EINVAL;
+    if (r->path_mode < 0 || r->path_mode > 3) return TVS_EINVAL;
     auto q = std::make_unique<Req>();
     q->r = *r;
     if (r->x0) {

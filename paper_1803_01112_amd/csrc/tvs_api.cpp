@@ -30,6 +30,7 @@ using tvs::TileBlock;
 namespace {
 
 constexpr int kNumStreams = 13;
+constexpr uint32_t kTileShiftHost = (uint32_t)tvs::kTileShift;
 
 // On the fly, rows are formed into a ring of chunk buffers: with three, the
 // formation stream can form the next sweep's first chunk while the DROP
@@ -37,8 +38,15 @@ constexpr int kNumStreams = 13;
 constexpr int kChunkBuffers = 3;
 
 // Flags on the device: DROP fixed-point range, tile-list consistency,
-// history validation.
-enum { kFlagRange = 0, kFlagLists = 1, kFlagInvalid = 2, kFlagJmax = 3, kNumFlags = 4 };
+// history validation, longest vertex count, longest chord (float32 bits).
+enum {
+    kFlagRange = 0,
+    kFlagLists = 1,
+    kFlagInvalid = 2,
+    kFlagJmax = 3,
+    kFlagChordMax = 4,
+    kNumFlags = 5
+};
 
 // SplitMix64 (Steele, Lea, Flood 2014): golden-gamma Weyl state, variant-13
 // output mixer.
@@ -143,6 +151,13 @@ struct tvs_ctx {
     uint32_t *meta[kChunkBuffers] = {};
     float *ch32[kChunkBuffers] = {};
     __half *ch16 = nullptr;
+    uint16_t *chq = nullptr;        // fixed-point store: low 16 bits of the chord codes
+    float chord_max = 0.0f;         // longest chord of the loaded rows (float32, rounded up)
+    double qunit = 0.0;             // fixed-point store: mm per code unit
+    double qinv = 0.0;              // 1 / qunit
+    uint32_t qmax = 0;              // largest code (2^bits - 1)
+    uint32_t qshift = 31;           // tag bit that holds the code's bit 16
+    uint32_t rowmask = 0xffffffu;   // row field of the tags
     int64_t cap = 0;                // entries per buffer
     int nbuf = 0;
     int64_t cbase = 0;              // ring position of the next sweep's first chunk
@@ -264,6 +279,12 @@ void free_histories(tvs_ctx *ctx)
         dfree(ctx, &ctx->ch32[q], (size_t)ctx->cap);
     }
     dfree(ctx, &ctx->ch16, (size_t)ctx->cap);
+    dfree(ctx, &ctx->chq, (size_t)ctx->cap);
+    ctx->chord_max = 0.0f;
+    ctx->qunit = ctx->qinv = 0.0;
+    ctx->qmax = 0;
+    ctx->qshift = 31;
+    ctx->rowmask = 0xffffffu;
     ctx->loaded = false;
     ctx->nh = 0;
     ctx->nseg = 0;
@@ -368,7 +389,7 @@ bool ktimer(tvs_ctx *ctx, tvs::KTimer &kt, bool two)
 // work queued on st).
 int check_flags(tvs_ctx *ctx, hipStream_t st)
 {
-    uint32_t f[kNumFlags] = {0, 0, 0, 0};
+    uint32_t f[kNumFlags] = {};
     HIPCHK(hipMemcpyAsync(f, ctx->flags, sizeof(f), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (f[kFlagLists] || (f[kFlagRange] & 2u))
@@ -391,6 +412,10 @@ TileBlock block_view(tvs_ctx *ctx, int64_t b, long long *dot_base, int64_t dot_s
     t.meta = ctx->meta[buf];
     t.ch32 = ctx->ch32[buf];
     t.ch16 = ctx->ch16;
+    t.chq = ctx->chq;
+    t.qunit = ctx->qunit;
+    t.qshift = ctx->qshift;
+    t.rowmask = ctx->rowmask;
     t.toff = ctx->bt_off + b * ctx->ntiles;
     t.base = otf ? ctx->chunk_base[(size_t)c] : 0;
     t.wepl = ctx->hist + 12 * ctx->nh + b * B;
@@ -697,7 +722,8 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
     if (e == hipSuccess) e = hipMemsetAsync(ctx->flags, 0, sizeof(uint32_t) * kNumFlags, st);
     if (e == hipSuccess)
         e = tvs::launch_rows_seg(ctx->gd, hd, ctx->mlp, n, B, ctx->seg_off, btc, ctx->segtab,
-                                 ctx->flags + kFlagLists, ctx->order, st);
+                                 ctx->flags + kFlagLists, ctx->flags + kFlagChordMax, ctx->order,
+                                 st);
     if (e == hipSuccess)
         e = tvs::launch_scan(reinterpret_cast<const int32_t *>(btc), nbt, ctx->bt_off, tmp, st);
     if (e == hipSuccess)
@@ -711,7 +737,7 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
     if (e == hipSuccess && ctx->nblocks > 0)
         e = hipMemcpyAsync(starts.data(), tmp, sizeof(int64_t) * (ctx->nblocks + 1),
                            hipMemcpyDeviceToHost, st);
-    uint32_t fl[kNumFlags] = {0, 0, 0, 0};
+    uint32_t fl[kNumFlags] = {};
     if (e == hipSuccess)
         e = hipMemcpyAsync(fl, ctx->flags, sizeof(fl), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -719,6 +745,7 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
     if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("tile lists: ") + hipGetErrorString(e));
     if (fl[kFlagLists])
         return fail(ctx, TVS_EDEVICE, "tile lists: a row walk disagreed with the count pass");
+    std::memcpy(&ctx->chord_max, &fl[kFlagChordMax], sizeof(float));
     for (int64_t b = 0; b <= ctx->nblocks && ctx->nblocks > 0; b++) {
         const int64_t want = (b < ctx->nblocks) ? off[(size_t)(b * B)] : total;
         if (starts[(size_t)b] != want)
@@ -749,6 +776,7 @@ int form_entries(tvs_ctx *ctx, hipStream_t st)
         rc = dalloc(ctx, &ctx->meta[q], (size_t)ctx->cap);
         if (!rc) {
             if (ctx->cfg.path_mode == TVS_PATH_STORE_F16) rc = dalloc(ctx, &ctx->ch16, (size_t)ctx->cap);
+            else if (ctx->cfg.path_mode == TVS_PATH_STORE_Q16) rc = dalloc(ctx, &ctx->chq, (size_t)ctx->cap);
             else rc = dalloc(ctx, &ctx->ch32[q], (size_t)ctx->cap);
         }
         // entries start as (row 0, word 0, chord 0): never an index out of range
@@ -756,7 +784,25 @@ int form_entries(tvs_ctx *ctx, hipStream_t st)
         if (!rc && ctx->ch32[q]) HIPCHK(hipMemsetAsync(ctx->ch32[q], 0, sizeof(float) * ctx->cap, st));
     }
     if (!rc && ctx->ch16) HIPCHK(hipMemsetAsync(ctx->ch16, 0, sizeof(__half) * ctx->cap, st));
+    if (!rc && ctx->chq) HIPCHK(hipMemsetAsync(ctx->chq, 0, sizeof(uint16_t) * ctx->cap, st));
     if (rc) return rc;
+    if (ctx->chq) {
+        // fixed-point chords: rb bits of a tag hold the row within its block
+        // (B rows), the 24 - rb above them the code's high bits, so a code
+        // has 16 + 24 - rb bits (at most 30); the unit is the longest chord /
+        // the largest code, made a little larger so that the longest chord's
+        // code stays in range after rounding
+        const uint32_t B = (uint32_t)ctx->cfg.block_size;
+        uint32_t rb = 0;
+        while (rb < 24 && ((uint32_t)1 << rb) < B) rb++;
+        const uint32_t bits = std::min<uint32_t>(30, 16 + (24 - rb));
+        ctx->rowmask = rb ? (((uint32_t)1 << rb) - 1u) : 0u;
+        ctx->qshift = kTileShiftHost + rb;
+        ctx->qmax = (uint32_t)(((uint64_t)1 << bits) - 1u);
+        const double m = ctx->chord_max > 0.0f ? (double)ctx->chord_max : 1.0;
+        ctx->qunit = m * (1.0 + 1.0 / 1048576.0) / (double)ctx->qmax;
+        ctx->qinv = 1.0 / ctx->qunit;
+    }
     if (otf) {
         // the first sweep's row formation runs on the fill stream: it must
         // not start before these clears, or they overwrite formed entries
@@ -774,6 +820,10 @@ int form_entries(tvs_ctx *ctx, hipStream_t st)
     f.meta = ctx->meta[0];
     f.ch32 = ctx->ch32[0];
     f.ch16 = ctx->ch16;
+    f.chq = ctx->chq;
+    f.qinv = ctx->qinv;
+    f.qmax = ctx->qmax;
+    f.qshift = ctx->qshift;
     f.cap = ctx->cap;
     f.norm2 = ctx->norm2;
     f.err = ctx->flags + kFlagLists;
@@ -870,7 +920,9 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     const int64_t nvox = tvs::padded_voxels(gdev);     // device image words (tiled layout)
     if (nvox >= ((int64_t)1 << 31)) return TVS_EINVAL;
     if (cfg.block_size < 1 || cfg.block_size > (1 << 24)) return TVS_EINVAL;
-    if (cfg.path_mode < 0 || cfg.path_mode > 2) return TVS_EINVAL;
+    if (cfg.path_mode < 0 || cfg.path_mode > 3) return TVS_EINVAL;
+    // the fixed-point store keeps at least 4 code bits in each tag
+    if (cfg.path_mode == TVS_PATH_STORE_Q16 && cfg.block_size > (1 << 20)) return TVS_EINVAL;
     if (!std::isfinite(cfg.mlp_step_mm)) return TVS_EINVAL;
     if (cfg.chunk_histories < 0 || cfg.max_tries < 0) return TVS_EINVAL;
     if (cfg.sweep_kernel < 0 || cfg.sweep_kernel > 2) return TVS_EINVAL;

@@ -117,7 +117,11 @@ struct RowSet {
 // grouped by image tile: list (b, T) holds, for every row of the block that
 // crosses tile T, its entries inside T, each as
 //   meta  = (word within the tile) | (row within the block) << 8,
-//   chord = float32 or float16.
+//   chord = float32, float16, or fixed point: an unsigned code times a unit
+//           (the longest chord of the loaded rows / the largest code,
+//           rounded up), its low 16 bits in a 16-bit word and its high bits
+//           in the tag bits above the row field, which a block of B rows
+//           leaves free (24 - ceil(log2 B) of them: 12 at B = 3200).
 // A row's entries inside one tile form a segment (a run of consecutive
 // entries of its walk); the place of every segment in its list is fixed
 // once, when the histories are loaded, so rows formed again on every sweep
@@ -131,6 +135,10 @@ struct TileFill {
     uint32_t *meta = nullptr;
     float *ch32 = nullptr;
     __half *ch16 = nullptr;
+    uint16_t *chq = nullptr;        // fixed-point store: low 16 bits of each chord's code
+    double qinv = 0.0;              // fixed-point store: code = rint(length * qinv)
+    uint32_t qmax = 0;              // fixed-point store: largest code
+    uint32_t qshift = 31;           // fixed-point store: tag bit of the code's bit 16
     int64_t cap = 0;                // entries meta / chord can hold
     float *norm2 = nullptr;         // per history (global index)
     uint32_t *err = nullptr;        // raised if a walk disagrees with the load-time lists
@@ -149,9 +157,12 @@ struct TileFill {
 // A walk that disagrees with the count pass writes nothing and raises *err.
 hipError_t launch_rows_count(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t first,
                              int64_t n, int32_t *nnz, int32_t *nseg, hipStream_t stream);
+// seg also raises *chmax to the float32 bits of the longest chord (rounded
+// up to float32).
 hipError_t launch_rows_seg(const GridDev &g, const HistDev &h, const MlpCfg &m, int64_t n,
                            int64_t B, const int64_t *seg_off, uint32_t *btc, uint64_t *segtab,
-                           uint32_t *err, const int32_t *order, hipStream_t stream);
+                           uint32_t *err, uint32_t *chmax, const int32_t *order,
+                           hipStream_t stream);
 hipError_t launch_seg_dest(const GridDev &g, int64_t n, int64_t B, const int64_t *seg_off,
                            const int64_t *bt_off, uint64_t *segtab, uint32_t *err,
                            hipStream_t stream);
@@ -197,6 +208,10 @@ struct TileBlock {
     const uint32_t *meta = nullptr;   // entry e (global index) at meta[e - base]
     const float *ch32 = nullptr;
     const __half *ch16 = nullptr;
+    const uint16_t *chq = nullptr;    // fixed-point store: low 16 bits of each chord's code
+    double qunit = 0.0;               // fixed-point store: mm per unit of the code
+    uint32_t qshift = 31;             // fixed-point store: the code's bits 16.. sit in tag bits qshift..
+    uint32_t rowmask = 0xffffffu;     // row field of a tag: (tag >> 8) & rowmask
     const int64_t *toff = nullptr;    // ntiles + 1 list starts (global entry index)
     int64_t base = 0;
     const float *wepl = nullptr;      // per row of the block

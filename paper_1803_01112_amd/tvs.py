@@ -18,7 +18,7 @@ from ._build import LIB
 HIST_FIELDS = ("ex", "ey", "ez", "qx", "qy", "qz", "eth", "eps", "qth", "qps", "ux", "uy", "wepl")
 
 TVS_OK, TVS_EINVAL, TVS_ENOMEM, TVS_EDEVICE, TVS_ESTATE, TVS_ERANGE = 0, -1, -2, -3, -4, -5
-PATH_MODES = {"otf": 0, "f32": 1, "f16": 2}
+PATH_MODES = {"otf": 0, "f32": 1, "f16": 2, "q16": 3}
 VARIANTS = {"ntvs": 0, "otvs": 1, "decoupled": 2}
 
 EXPORTED = ("tvs_config_default", "tvs_create", "tvs_destroy", "tvs_load_histories",

@@ -165,21 +165,32 @@ def test_path_modes_agree(slice64):
     w, h, rows = slice64
     x0 = w.initial_image()
     imgs = {}
-    for mode in ("otf", "f32", "f16"):
+    for mode in ("otf", "f32", "f16", "q16"):
         with tvs.Context(w.grid, block_size=64, mlp_step_mm=2.0, path_mode=mode) as ctx:
             ctx.load_histories(h)
             ctx.set_image(x0)
             ctx.iterate(3, 0.05, 3, 0.75, seed=2)
             imgs[mode] = ctx.get_image()
+            if mode == "q16":
+                ctx.set_image(x0)
+                ctx.iterate_batch(3, [dict(lam=0.05, N=3, alpha=0.75, seed=2)])
+                imgs["q16 batch"] = ctx.get_batch_image(0)
     assert rel_err(imgs["f32"], imgs["otf"].astype(np.float64)) <= 1e-5
+    assert rel_err(imgs["q16 batch"], imgs["q16"].astype(np.float64)) <= 1e-5
     S = oracle.Superiorizer(w.grid, rows, x0, 64)
     S.iterate(3, 0.05, 3, 0.75, seed=2)
     e16 = rel_err(imgs["f16"], S.x)
-    # the float16 store is a precision form: its error is measured and
-    # reported, and only bounded loosely here (chords carry 2^-11 relative
-    # error, which the scale-free TV subgradient amplifies)
-    print(f"float16 chord store: max relative error vs oracle {e16:.3e}")
-    assert e16 <= 1e-2
+    eq = rel_err(imgs["q16"], S.x)
+    # the float16 store is a precision form: its error against the oracle is
+    # measured (3.5e-3 in this stress case, B = 64 and lambda = 0.05, which
+    # moves the image 500 times more per block than the paper's lambda; the
+    # TV subgradient's direction amplifies chord rounding) and held near it;
+    # the fixed-point store (28-bit codes at 6 bytes per entry, 1.2e-7
+    # measured) meets the image tolerance
+    print(f"16-bit chord stores: max relative error vs oracle float16 {e16:.3e}, "
+          f"fixed point {eq:.3e}")
+    assert e16 <= 5e-3
+    assert eq <= TOL
 
 
 @pytest.mark.parametrize("n,B", [(1001, 64), (777, 1), (5, 3200)])
