@@ -209,6 +209,12 @@ int tvs_set_image(tvs_ctx *ctx, const float *x0, int on_device, void *stream);
  * current state.  The first cycle after tvs_set_image / tvs_load_histories
  * seeds the RNG from p->seed; later calls continue the same stream, so K
  * cycles in one call equal the same K cycles split over several calls.
+ * The work is queued on the stream and the call returns without waiting,
+ * with or without the TV-reduction check: a checked step is decided on the
+ * device (its tries, ell and the RNG state stay there), and its records
+ * reach the step log when tvs_get_step_log or tvs_get_stats is called, an
+ * unchecked call follows, or more than 4096 records are pending (then the
+ * call waits once for the work queued so far).
  * TVS_EINVAL for lambda <= 0, alpha outside (0,1), N < 0, tv_eps < 0;
  * TVS_ESTATE before tvs_load_histories. */
 int tvs_iterate(tvs_ctx *ctx, const tvs_params *p, int32_t K, void *stream);

@@ -32,6 +32,10 @@ namespace {
 constexpr int kNumStreams = 13;
 constexpr uint32_t kTileShiftHost = (uint32_t)tvs::kTileShift;
 
+// Step records of checked cycles held on the device before they are copied
+// back (once per call, or when the buffer fills).
+constexpr int64_t kDevLogCap = 4096;
+
 // On the fly, rows are formed into a ring of chunk buffers: with three, the
 // formation stream can form the next sweep's first chunk while the DROP
 // chain still reads the last two of this sweep.
@@ -178,6 +182,16 @@ struct tvs_ctx {
     bool seeded = false;
     std::vector<tvs_step_log> log;
     int64_t tries = 0;
+    // checked cycles keep ell and the RNG state on the device (sched) and
+    // write their step records there (dlog); dev_sched: the device copy is
+    // the current one, to be copied back (after ev_sched) before the host
+    // uses ell again or reports the log
+    tvs::SchedDev *sched = nullptr;
+    tvs_step_log *dlog = nullptr;
+    int64_t dlog_n = 0;
+    bool dev_sched = false;
+    hipEvent_t ev_sched = nullptr;
+    double *cpart = nullptr;        // partial sums of the device-side check
 
     // timing: HIP events recorded on the launch stream around every phase of
     // the last tvs_iterate call, resolved lazily by tvs_get_stats
@@ -336,6 +350,31 @@ void reset_state(tvs_ctx *ctx)
     ctx->seeded = false;
     ctx->log.clear();
     ctx->tries = 0;
+    ctx->dev_sched = false;
+    ctx->dlog_n = 0;
+}
+
+// Copies the schedule and step records of checked cycles back from the
+// device (waits for the work of the last checked call).
+int settle_sched(tvs_ctx *ctx)
+{
+    if (!ctx->dev_sched) return TVS_OK;
+    HIPCHK(hipEventSynchronize(ctx->ev_sched));
+    tvs::SchedDev sd{};
+    HIPCHK(hipMemcpy(&sd, ctx->sched, sizeof(sd), hipMemcpyDeviceToHost));
+    std::vector<tvs_step_log> recs((size_t)ctx->dlog_n);
+    if (ctx->dlog_n > 0)
+        HIPCHK(hipMemcpy(recs.data(), ctx->dlog, sizeof(tvs_step_log) * (size_t)ctx->dlog_n,
+                         hipMemcpyDeviceToHost));
+    for (const auto &r : recs) {
+        ctx->log.push_back(r);
+        ctx->tries += r.tries;
+    }
+    ctx->ell = sd.ell;
+    ctx->rng = sd.rng;
+    ctx->dlog_n = 0;
+    ctx->dev_sched = false;
+    return TVS_OK;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -537,13 +576,6 @@ int validate_params(tvs_ctx *ctx, const tvs_params *p)
         return fail(ctx, TVS_EINVAL, "tv_eps must be finite and >= 0");
     if (p->variant == TVS_DECOUPLED && !(p->gamma > 0.0 && p->gamma < 1.0))
         return fail(ctx, TVS_EINVAL, "gamma must lie in (0, 1)");
-    return TVS_OK;
-}
-
-int read_scalars(tvs_ctx *ctx, hipStream_t st, double out[2])
-{
-    HIPCHK(hipMemcpyAsync(out, ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
     return TVS_OK;
 }
 
@@ -890,6 +922,10 @@ void tvs_destroy(tvs_ctx *ctx)
     dfree(ctx, &ctx->part, (size_t)ctx->nparts);
     dfree(ctx, &ctx->scal, (size_t)4);
     dfree(ctx, &ctx->ticket, (size_t)4);
+    dfree(ctx, &ctx->sched, (size_t)1);
+    dfree(ctx, &ctx->dlog, (size_t)kDevLogCap);
+    dfree(ctx, &ctx->cpart, (size_t)tvs::tv_check_parts(ctx->gd));
+    if (ctx->ev_sched) (void)hipEventDestroy(ctx->ev_sched);
     for (auto &e : ctx->tev)
         if (e) (void)hipEventDestroy(e);
     for (int q = 0; q < kChunkBuffers; q++) {
@@ -982,9 +1018,16 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     if (!rc) rc = dalloc(ctx, &ctx->part, (size_t)ctx->nparts);
     if (!rc) rc = dalloc(ctx, &ctx->scal, (size_t)4);
     if (!rc) rc = dalloc(ctx, &ctx->ticket, (size_t)4);
+    if (!rc) rc = dalloc(ctx, &ctx->sched, (size_t)1);
+    if (!rc) rc = dalloc(ctx, &ctx->dlog, (size_t)kDevLogCap);
+    if (!rc) rc = dalloc(ctx, &ctx->cpart, (size_t)tvs::tv_check_parts(ctx->gd));
     if (rc) {
         tvs_destroy(ctx);
         return rc;
+    }
+    if (hipEventCreateWithFlags(&ctx->ev_sched, hipEventDisableTiming) != hipSuccess) {
+        tvs_destroy(ctx);
+        return TVS_EDEVICE;
     }
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->fill_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -1334,24 +1377,46 @@ int tvs_iterate(tvs_ctx *ctx, const tvs_params *p, int32_t K, void *stream)
     }
     const bool checked = (p->variant == TVS_OTVS) || (p->variant == TVS_NTVS && p->tv_check);
     const int32_t nsteps = (p->variant == TVS_OTVS) ? 1 : p->N;
+    // unchecked steps take ell from the host: bring a device-held schedule back
+    if (!checked) {
+        rc = settle_sched(ctx);
+        if (rc) return rc;
+    }
     if (K > 0) {
         ctx->tev_used = 0;
         ctx->spans.clear();
         ctx->timed = true;
     }
+    const tvs::CheckBuffers cb{ctx->cpart, ctx->ticket + 1, ctx->scal + 2};
+    const double check_alpha = (p->variant == TVS_OTVS) ? 0.5 : p->alpha;
+    if (checked && K > 0 && !ctx->dev_sched) {
+        HIPCHK(tvs::launch_sched_set(ctx->sched, ctx->ell, ctx->rng, st));
+        ctx->dev_sched = true;
+    }
     for (int32_t kk = 0; kk < K; kk++) {
         const int64_t k = ctx->k;
-        if (p->variant == TVS_NTVS) ctx->ell = draw_ell(k, ctx->ell, ctx->rng);
+        if (checked && ctx->dlog_n + nsteps > kDevLogCap) {
+            // the record buffer is full: copy it back and go on
+            HIPCHK(hipEventRecord(ctx->ev_sched, st));
+            rc = settle_sched(ctx);
+            if (rc) return rc;
+            HIPCHK(tvs::launch_sched_set(ctx->sched, ctx->ell, ctx->rng, st));
+            ctx->dev_sched = true;
+        }
+        if (p->variant == TVS_NTVS) {
+            if (checked) HIPCHK(tvs::launch_sched_draw(ctx->sched, k, st));
+            else ctx->ell = draw_ell(k, ctx->ell, ctx->rng);
+        }
         const long c0 = mark(ctx, st);
         for (int32_t n = 0; n < nsteps; n++) {
-            tvs_step_log rec;
-            std::memset(&rec, 0, sizeof(rec));
-            rec.k = (int32_t)k;
-            rec.n = n;
-            rec.ell_start = ctx->ell;
-            rec.gnorm = -1.0;
             HIPCHK(tvs::launch_tv_grad(ctx->gd, ctx->x, p->tv_eps, tb, st));
             if (!checked) {
+                tvs_step_log rec;
+                std::memset(&rec, 0, sizeof(rec));
+                rec.k = (int32_t)k;
+                rec.n = n;
+                rec.ell_start = ctx->ell;
+                rec.gnorm = -1.0;
                 double beta = (p->variant == TVS_DECOUPLED)
                                   ? std::pow(p->alpha, (double)(n + 1)) * std::pow(p->gamma, (double)k)
                                   : std::pow(p->alpha, (double)ctx->ell);
@@ -1360,34 +1425,15 @@ int tvs_iterate(tvs_ctx *ctx, const tvs_params *p, int32_t K, void *stream)
                 rec.tries = 1;
                 rec.accepted = 1;
                 ctx->tries += 1;
+                ctx->log.push_back(rec);
             } else {
-                double sc[2];
-                HIPCHK(tvs::launch_tv_phi(ctx->gd, ctx->x, 0.0, p->tv_eps, tb, st));
-                rc = read_scalars(ctx, st, sc);
-                if (rc) return rc;
-                const double phx = sc[1];
-                rec.phi_x = phx;
-                rec.gnorm = std::sqrt(sc[0]);
-                int32_t tries = 0;
-                while (tries < ctx->cfg.max_tries) {
-                    double beta = (p->variant == TVS_OTVS) ? std::pow(0.5, (double)ctx->ell)
-                                                           : std::pow(p->alpha, (double)ctx->ell);
-                    HIPCHK(tvs::launch_tv_phi(ctx->gd, ctx->x, beta, p->tv_eps, tb, st));
-                    rc = read_scalars(ctx, st, sc);
-                    if (rc) return rc;
-                    tries++;
-                    ctx->ell += 1;
-                    if (sc[1] <= phx) {
-                        HIPCHK(tvs::launch_tv_step(ctx->gd, ctx->x, beta, tb, st));
-                        rec.phi_z = sc[1];
-                        rec.accepted = 1;
-                        break;
-                    }
-                }
-                rec.tries = tries;
-                ctx->tries += tries;
+                // decided on the device: no host round trip
+                HIPCHK(tvs::launch_tv_check(ctx->gd, ctx->x, p->tv_eps, check_alpha,
+                                            ctx->cfg.max_tries, (int32_t)k, n, ctx->sched,
+                                            ctx->dlog + ctx->dlog_n, cb, tb, st));
+                HIPCHK(tvs::launch_tv_apply(ctx->gd, ctx->x, tb, cb, st));
+                ctx->dlog_n += 1;
             }
-            ctx->log.push_back(rec);
         }
         const long c1 = mark(ctx, st);
         span(ctx, 0, c0, c1);
@@ -1396,6 +1442,7 @@ int tvs_iterate(tvs_ctx *ctx, const tvs_params *p, int32_t K, void *stream)
         span(ctx, 1, c1, mark(ctx, st));
         ctx->k += 1;
     }
+    if (checked && K > 0) HIPCHK(hipEventRecord(ctx->ev_sched, st));
     return TVS_OK;
 }
 
@@ -1420,6 +1467,8 @@ int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out)
     if (!ctx || !out) return TVS_EINVAL;
     ctx->err.clear();
     HIPCHK(hipSetDevice(ctx->cfg.device));
+    int src = settle_sched(ctx);
+    if (src) return src;
     if (ctx->timed && !ctx->spans.empty()) {
         HIPCHK(hipEventSynchronize(ctx->tev[ctx->spans.back().b]));
         HIPCHK(hipStreamSynchronize(ctx->fill_stream));
@@ -1483,6 +1532,10 @@ int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out)
 int tvs_get_step_log(tvs_ctx *ctx, tvs_step_log *out, int64_t cap, int64_t *n)
 {
     if (!ctx || !n || cap < 0 || (cap > 0 && !out)) return TVS_EINVAL;
+    ctx->err.clear();
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    int rc = settle_sched(ctx);
+    if (rc) return rc;
     *n = (int64_t)ctx->log.size();
     int64_t m = std::min<int64_t>(cap, *n);
     if (m > 0) std::memcpy(out, ctx->log.data(), sizeof(tvs_step_log) * (size_t)m);

@@ -269,6 +269,34 @@ struct TvBuffers {
     int64_t nparts;
 };
 int64_t tv_num_parts(const GridDev &g);
+// Schedule of checked cycles, held on the device while a checked
+// tvs_iterate call runs (ell and the SplitMix64 state).
+struct SchedDev {
+    int64_t ell;
+    uint64_t rng;
+};
+// Scratch of the device-side TV check: partial sums of TV(x) and of the
+// trial images per tile workgroup (tv_check_parts doubles), a last-workgroup
+// ticket, and the decision {scale, accepted}.
+struct CheckBuffers {
+    double *part;
+    uint32_t *ticket;
+    double *dec;
+};
+int64_t tv_check_parts(const GridDev &g);
+// One checked step: decides on the device (first try t with
+// TV(x + s_t g) <= TV(x), s_t = -alpha^(ell + t) / sqrt(scal[0]), at most
+// max_tries tries), advances sd->ell by the tries and writes *rec.
+hipError_t launch_tv_check(const GridDev &g, const double *x, double eps, double alpha,
+                           int32_t max_tries, int32_t k, int32_t n, SchedDev *sd,
+                           tvs_step_log *rec, const CheckBuffers &c, const TvBuffers &t,
+                           hipStream_t stream);
+// x += s g with the decided scale (nothing when the step gave up).
+hipError_t launch_tv_apply(const GridDev &g, double *x, const TvBuffers &t, const CheckBuffers &c,
+                           hipStream_t stream);
+// ell = rand(k, ell) with the device SplitMix64 state; sets the state.
+hipError_t launch_sched_draw(SchedDev *sd, int64_t k, hipStream_t stream);
+hipError_t launch_sched_set(SchedDev *sd, int64_t ell, uint64_t rng, hipStream_t stream);
 // g = grad TV(x); scal[0] = ||g||^2 (fixed-order reduction).
 hipError_t launch_tv_grad(const GridDev &g, const double *x, double eps, const TvBuffers &t,
                           hipStream_t stream);
