@@ -2,14 +2,23 @@
 
 A step is one TVS cycle of NTVS (arXiv 1803.01112, Appendix C): N
 perturbation steps followed by one DROP feasibility sweep over every
-history, whose rows (MLP + voxel walk) are formed on the fly inside the
-sweep.  The metric is histories processed per second per cycle.
+history; the metric is histories processed per second per cycle.
 
-Default workload: 200x200x16 voxels of 1x1x2.5 mm, a 150 mm cylinder
-phantom with six inserts, 20M synthetic histories at 180 angles, DROP
-blocks of 3200 histories, lambda = 1e-4, N = 5, alpha = 0.75, TV check off.
-Inputs are generated (seeded), copied to HBM, and loaded before the timed
-region starts.
+Default workload (the largest single-GPU configuration): 256x256x32 voxels
+of 1x1x2.5 mm, a 192 mm cylinder phantom with six inserts, 60M synthetic
+histories at 360 angles, DROP blocks of 3200 histories (18,750 per sweep),
+lambda = 1e-4, N = 5, alpha = 0.75, TV check off, rows (MLP + voxel walk)
+formed on the fly inside every sweep.  Beside it, on the same histories:
+the path stores (float32 chords, float16 chords, the 6-byte fixed-point
+store) and the check-on cycle.  Further legs: the store forms' image error
+against the oracle on the two-slice sub-problem, the 24-setting batched
+parameter study on the 200x200x16 volume's 20M histories, and a stream of
+serving requests.  Inputs are generated (seeded), copied to HBM and loaded
+before any timed region starts.
+
+HBM accounting: algorithmic bytes of one sweep are 16 B per history (WEPL,
+||a||^2, row offset) plus (4 + chord bytes) per row entry of a path store,
+or 52 B per history (the 13 float32 streams) on the fly, read once.
 
 Prints one JSON line.  Only one GPU is supported: --gpus above 1 exits.
 """
@@ -30,22 +39,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-# float64 operations of one MLP vertex and its segment walk, counted on the
-# algorithm as implemented (moments, 2x2 conditioning, position, Siddon walk)
-FP64_FLOPS_PER_VERTEX = 320.0
+# float64 operations of one MLP vertex (scattering moments, two 2x2
+# conditionings, vertex position and its segment's voxel walk), the count of
+# the hot-path scope's measurement plan
+FP64_FLOPS_PER_VERTEX = 250.0
+CHORD_BYTES = {"otf": 4, "f32": 4, "f16": 2, "q16": 2}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def tile_step_bytes(nnz, nblocks, chord_bytes, nvox, block):
-    """Algorithmic HBM bytes of one DROP step (one launch per block): the tile
-    lists of two blocks read once (block b - 1 finished, block b's dot
-    products formed), 4-byte tag + chord per entry; the image read and written
-    once (float64); per row of both blocks WEPL, ||a||^2 (float32) and the
-    64-bit dot product."""
-    return 2.0 * (4.0 + chord_bytes) * nnz / max(nblocks, 1) + 16.0 * nvox + 32.0 * block
+def sweep_bytes(H, nnz, mode):
+    """Algorithmic HBM bytes of one sweep: path stores read 16 B per history
+    and (4 + chord bytes) per entry once; on the fly the 52-byte history
+    streams are read once (the row entries are formed on the device)."""
+    if mode == "otf":
+        return 52.0 * H
+    return 16.0 * H + (4.0 + CHORD_BYTES[mode]) * nnz
 
 
 # sources of each measured kernel: a counter record taken on other sources
@@ -92,67 +103,113 @@ def mlp_vertices(h, step):
     return float(np.sum(np.where(L > 0, J - 1, 0)))
 
 
-def run_form(tvs, torch, w, dev_hist, x0, args, path_mode, K, W):
-    ctx = tvs.Context(w.grid, block_size=args.block, path_mode=path_mode,
+def percentiles(lat):
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+            "cycles": len(lat)}
+
+
+def timed_cycles(torch, ctx, K, kw):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.iterate(K, **kw)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def latency(torch, ctx, n, kw):
+    """Per-cycle wall time, each cycle synchronised on its own (ms)."""
+    out = []
+    for _ in range(n):
+        out.append(1e3 * timed_cycles(torch, ctx, 1, kw))
+    return out
+
+
+def run_form(tvs, torch, w, dev_hist, x0, args, mode, K, W, n_lat, check=False):
+    """Loads the histories in path mode `mode`, runs W untimed and K timed
+    cycles, then n_lat cycles one at a time; returns figures and stats."""
+    ctx = tvs.Context(w.grid, block_size=args.block, path_mode=mode,
                       time_sample=args.time_sample)
     t0 = time.perf_counter()
     ctx.load_histories(dev_hist)
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t0
     ctx.set_image(x0)
-    kw = dict(lam=args.lam, N=args.N, alpha=args.alpha, tv_check=args.check, seed=args.seed)
+    kw = dict(lam=args.lam, N=args.N, alpha=args.alpha, tv_check=check, seed=args.seed)
     if W > 0:
         ctx.iterate(W, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.iterate(K, **kw)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt = timed_cycles(torch, ctx, K, kw)
     st = ctx.stats()
-    return ctx, st, dt, load_s
+    lat = latency(torch, ctx, n_lat, kw) if n_lat > 0 else []
+    steps = ctx.step_log() if check else None
+    ctx.close()
+    H = w.n_hist
+    T = math.ceil(H / args.block)
+    sweep_ms = st["drop_ms_total"] / max(st["drop_launches"], 1)
+    ns = max(st["k_samples"], 1)
+    out = dict(value=H * K / dt, unit="histories/s", ms_per_step=1e3 * dt / K,
+               load_s=load_s, nnz=st["nnz"],
+               phases_ms_per_cycle={"tv": st["tv_ms_total"] / max(st["cycles_timed"], 1),
+                                    "sweep": st["sweep_ms_total"] / max(st["cycles_timed"], 1),
+                                    "rows": st["rows_ms_total"] / max(st["cycles_timed"], 1),
+                                    "drop": sweep_ms},
+               drop_step_us=1e3 * sweep_ms / (T + 1),
+               drop_launch_us=1e3 * st["k1_ms_total"] / ns)
+    b = sweep_bytes(H, st["nnz"], mode)
+    out["hbm"] = dict(algorithmic_bytes_per_sweep=b,
+                      gbs=b / (sweep_ms * 1e-3) / 1e9,
+                      frac=b / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      what="algorithmic bytes of one sweep over the DROP chain's device time")
+    if lat:
+        out["latency_ms"] = percentiles(lat)
+    if steps is not None:
+        tries = [r["tries"] for r in steps]
+        out["check"] = dict(steps=len(steps), tries_total=int(sum(tries)),
+                            tries_max=int(max(tries) if tries else 0),
+                            accepted=int(sum(r["accepted"] for r in steps)))
+    return out, st
 
 
 def cpu_baseline(w, args, cores):
-    """The oracle (plain float64 CPU code) on a bounded prefix of the same scan:
-    rows formed (MLP + walk, OpenMP over histories) and one cycle per repeat."""
+    """The oracle (plain float64 CPU code) on a bounded prefix of the same
+    scan, one cycle as the library runs it on the fly: rows formed (MLP +
+    walk; OpenMP over histories on all host threads, and on one thread for a
+    tenth of the prefix), then N TV steps and one DROP sweep (one thread)."""
     import oracle
     n = args.cpu_sample
     h = w.histories(count=n)
     x0 = w.initial_image()
+    oracle.set_threads(cores)
     t0 = time.perf_counter()
-    reps = 0
-    x = x0
-    state = None
-    t_rows = t_cycle = 0.0
-    while True:
-        ta = time.perf_counter()
-        rows = oracle.build_rows(w.grid, h, min(w.grid.vx, w.grid.vy))
-        tb = time.perf_counter()
-        S = oracle.Superiorizer(w.grid, rows, x, args.block)
-        if state is not None:
-            S.state = state
-        S.iterate(1, args.lam, args.N, args.alpha, tv_check=args.check, seed=args.seed)
-        x, state = S.x.copy(), S.state
-        t_rows += tb - ta
-        t_cycle += time.perf_counter() - tb
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > args.cpu_seconds or reps >= 20:
-            break
-    return dict(value=n * reps / el, unit="histories/s", cores=cores, kind="oracle",
-                phases_s_per_cycle={"rows_mlp_walk": t_rows / reps,
-                                    "tv_steps_and_drop_sweep": t_cycle / reps},
-                sample=f"first {n} histories of the {w.name} scan ({w.n_hist}), {reps} cycle(s) "
-                       f"each re-forming rows (MLP+walk, OpenMP {cores} threads) then "
-                       f"N={args.N} TV steps and one DROP sweep (single thread); {el:.1f} s")
+    rows = oracle.build_rows(w.grid, h, min(w.grid.vx, w.grid.vy))
+    t_rows = time.perf_counter() - t0
+    n1 = max(n // 10, 1)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.build_rows(w.grid, {k: v[:n1] for k, v in h.items()}, min(w.grid.vx, w.grid.vy))
+    t_rows1 = (time.perf_counter() - t0) * n / n1
+    oracle.set_threads(cores)
+    S = oracle.Superiorizer(w.grid, rows, x0, args.block)
+    t0 = time.perf_counter()
+    S.iterate(1, args.lam, args.N, args.alpha, seed=args.seed)
+    t_cycle = time.perf_counter() - t0
+    el = t_rows + t_cycle
+    return dict(value=n / el, unit="histories/s", cores=cores, kind="oracle",
+                single_thread_value=n / (t_rows1 + t_cycle),
+                phases_s_per_cycle={"rows_mlp_walk_all_cores": t_rows,
+                                    "rows_mlp_walk_one_thread": t_rows1,
+                                    "tv_steps_and_drop_sweep_one_thread": t_cycle},
+                sample=f"first {n} histories of the {w.name} scan ({w.n_hist}); one cycle: rows "
+                       f"(MLP + walk) on {cores} threads, then N={args.N} TV steps and one DROP "
+                       f"sweep on one thread ({el:.1f} s); the one-thread row time is measured "
+                       f"on the first {n1} histories and scaled")
 
 
 def precision_report(tvs, torch, args):
     """Image error of each path form against the oracle on the two-slice
-    sub-problem of the 256x256x32 phantom (slab256: 256x256x2 voxels of
-    1x1x2.5 mm, 3.75M histories at 360 angles, B = 3200), K cycles at the
-    benchmark's lambda, N, alpha: max and RMS of |x - x_oracle| /
-    max(|x_oracle|, 0.1), and the largest change of a 7 mm insert ROI mean."""
+    sub-problem of the 256x256x32 phantom (256x256x2 voxels of 1x1x2.5 mm,
+    3.75M histories at 360 angles, B = 3200), K cycles at the benchmark's
+    lambda, N, alpha: max and RMS of |x - x_oracle| / max(|x_oracle|, 0.1),
+    and the largest change of a 7 mm insert ROI mean."""
     import oracle
     from paper_1803_01112_amd import quality, synth
     w = synth.workload("slab256", n_hist=args.precision_hist)
@@ -170,8 +227,8 @@ def precision_report(tvs, torch, args):
     roi_ref = [q["mean"] for q in quality.measure(ref, w.grid, w.phantom)["rois"]]
     dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in h.items()}
     out = dict(workload=f"{w.name}: {w.grid.nx}x{w.grid.ny}x{w.grid.nz}, {w.n_hist} histories",
-               cycles=K, oracle_seconds=t_or, forms={})
-    for form in ("f32", "f16", "otf"):
+               cycles=K, oracle_seconds=t_or, tolerance=1e-4, forms={})
+    for form in ("f32", "q16", "f16", "otf"):
         with tvs.Context(w.grid, block_size=args.block, path_mode=form) as ctx:
             ctx.load_histories(dev)
             ctx.set_image(x0)
@@ -180,7 +237,8 @@ def precision_report(tvs, torch, args):
         e = np.abs(x - ref) / np.maximum(np.abs(ref), 0.1)
         roi = [q["mean"] for q in quality.measure(x, w.grid, w.phantom)["rois"]]
         out["forms"][form] = dict(max_rel=float(e.max()), rms_rel=float(np.sqrt(np.mean(e * e))),
-                                  max_roi_mean_delta=float(np.max(np.abs(np.subtract(roi, roi_ref)))))
+                                  max_roi_mean_delta=float(np.max(np.abs(np.subtract(roi, roi_ref)))),
+                                  meets_tolerance=bool(e.max() <= 1e-4))
         log(f"precision {form}: {out['forms'][form]}")
     return out
 
@@ -195,29 +253,57 @@ def batch_settings():
     return out
 
 
-def run_batch(tvs, torch, w, dev, x0, args):
-    """All 24 settings of the parameter study advanced together (one row stream)."""
+def run_batch(tvs, torch, args):
+    """The 24-setting parameter study advanced together on the 200x200x16
+    volume's 20M histories (one row stream per cycle for all settings),
+    against the same store's single-setting cycle."""
+    from paper_1803_01112_amd import synth
+    w = synth.workload("vol200")
+    log(f"batch leg: generating {w.n_hist} histories of {w.name}")
+    h = w.histories()
+    dev = {k: torch.from_numpy(v).to("cuda:0") for k, v in h.items()}
+    del h
+    x0 = torch.from_numpy(w.initial_image()).to("cuda:0")
     sets = batch_settings()
+    S = len(sets)
     ctx = tvs.Context(w.grid, block_size=args.block, path_mode=args.batch_path)
     ctx.load_histories(dev)
+    ctx.set_image(x0)
+    # the plain single-setting cycle of the same store, for comparison
+    kw = dict(lam=1e-4, N=3, alpha=0.75, seed=args.seed)
+    ctx.iterate(1, **kw)
+    dt1 = timed_cycles(torch, ctx, args.batch_steps, kw) / args.batch_steps
     ctx.set_image(x0)
     ctx.iterate_batch(1, sets)                     # warm-up cycle (captures the graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.iterate_batch(args.steps, sets)
+    ctx.iterate_batch(args.batch_steps, sets)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt = (time.perf_counter() - t0) / args.batch_steps
     st = ctx.stats()
+    lat = []
+    for _ in range(args.batch_latency):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.iterate_batch(1, sets)
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - t0))
     ctx.close()
-    S = len(sets)
-    return dict(settings=S, value=w.n_hist * S * args.steps / dt,
-                unit="history-settings/s", ms_per_cycle=1e3 * dt / args.steps,
+    del dev
+    H = w.n_hist
+    return dict(workload=f"{w.name}: 200x200x16, {H} histories", settings=S,
+                value=H * S / dt, unit="history-settings/s", ms_per_cycle=1e3 * dt,
                 device_ms_per_cycle=st["batch_ms_total"] / max(st["batch_cycles"], 1),
-                path_mode=args.batch_path)
+                latency_ms=percentiles(lat) if lat else None,
+                single_setting=dict(value=H / dt1, ms_per_cycle=1e3 * dt1, N=3, alpha=0.75),
+                speedup_vs_separate_runs=(S * dt1) / dt, path_mode=args.batch_path)
 
 
 def run_serving(tvs, args):
-    """Poisson stream of reconstruction requests of mixed grids and sizes."""
+    """Poisson stream of reconstruction requests: grids drawn from 64x64x4 ..
+    256x256x32, history counts log-uniform in [serve_hmin, serve_hmax], the
+    paper's equal-accuracy (lambda, K) pairs, N in 1..6, alpha from the
+    paper's grid; offered at fractions of the measured serial capacity."""
     from paper_1803_01112_amd import synth
     rng = np.random.default_rng(1803011124)
     grids = ["vol64", "vol128", "vol200", "vol256"]
@@ -243,7 +329,6 @@ def run_serving(tvs, args):
         return s.submit(w.grid, hh, lam=r["lam"], N=r["N"], alpha=r["alpha"], K=r["K"],
                         path_mode=args.serve_path, x0=x0, seed=7)
 
-    # capacity: the same requests back to back, one at a time
     with tvs.Server(max_active=1) as s:
         t0 = time.perf_counter()
         for r in reqs:
@@ -251,8 +336,9 @@ def run_serving(tvs, args):
         t_alone = time.perf_counter() - t0
     cap_rate = len(reqs) / t_alone
     log(f"serving: {len(reqs)} requests one at a time in {t_alone:.1f} s")
-    out = dict(requests=len(reqs), history_cycles=work, serial_s=t_alone,
-               serial_value=work / t_alone, loads={})
+    out = dict(requests=len(reqs), histories=f"log-uniform in [{args.serve_hmin}, {hmax}]",
+               history_cycles=work, serial_s=t_alone, serial_value=work / t_alone,
+               slots=args.serve_slots, path_mode=args.serve_path, loads={})
     for rho in [float(v) for v in args.serve_loads.split(",")]:
         gaps = rng.exponential(1.0 / (rho * cap_rate), len(reqs))
         with tvs.Server(max_active=args.serve_slots) as s:
@@ -266,7 +352,7 @@ def run_serving(tvs, args):
             c = s.counters()
         lat = np.array([i["done_ms"] - i["submit_ms"] for _, i in res])
         ok = sum(1 for _, i in res if i["status"] == 0)
-        out["loads"][str(rho)] = dict(value=work / dt, unit="histories/s", makespan_s=dt,
+        out["loads"][str(rho)] = dict(value=work / dt, unit="history-cycles/s", makespan_s=dt,
                                       p50_ms=float(np.percentile(lat, 50)),
                                       p99_ms=float(np.percentile(lat, 99)), completed=ok,
                                       peak_active=c["peak_active"],
@@ -275,41 +361,74 @@ def run_serving(tvs, args):
     return out
 
 
+def references(torch):
+    """A STREAM-like copy on this device and a unique-address float atomic
+    rate (the roofline keeps the published peak; these say what plain
+    kernels reach here)."""
+    src = torch.ones(512 << 20, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    n_at = 64 << 20
+    acc = torch.zeros(n_at, dtype=torch.float32, device="cuda:0")
+    idx = torch.arange(n_at, dtype=torch.int64, device="cuda:0")
+    val = torch.ones(n_at, dtype=torch.float32, device="cuda:0")
+    acc.index_add_(0, idx, val)
+    e0.record()
+    for _ in range(3):
+        acc.index_add_(0, idx, val)
+    e1.record()
+    torch.cuda.synchronize()
+    at_ms = e0.elapsed_time(e1) / 3
+    del acc, idx, val
+    return ({"copy_gbs": copy_gbs, "frac_of_published": copy_gbs / HBM_PEAK_GBS,
+             "what": "device-to-device copy of 2 GiB, bytes read + written / time"},
+            {"what": "torch index_add_, float32, 64M unique consecutive addresses",
+             "lane_atomics_per_s": n_at / (at_ms * 1e-3), "ms": at_ms})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="vol200")
+    ap.add_argument("--workload", default="vol256")
     ap.add_argument("--n-hist", type=int, default=None)
     ap.add_argument("--block", type=int, default=3200)
     ap.add_argument("--lam", type=float, default=1e-4)
     ap.add_argument("--N", type=int, default=5)
     ap.add_argument("--alpha", type=float, default=0.75)
-    ap.add_argument("--check", type=int, default=0)
     ap.add_argument("--seed", type=int, default=1803011121)
     ap.add_argument("--path-mode", default="otf")
     ap.add_argument("--time-sample", type=int, default=16,
-                    help="HIP events around both launches of every k-th DROP block")
-    ap.add_argument("--forms", default="f32,f16", help="extra path-store forms to time")
-    ap.add_argument("--latency-cycles", type=int, default=6)
-    ap.add_argument("--cpu-sample", type=int, default=400_000)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+                    help="kernel-stamped HIP events on the launch of every k-th DROP block")
+    ap.add_argument("--latency-cycles", type=int, default=50)
+    ap.add_argument("--forms", default="f32,f16,q16", help="path-store forms timed beside")
+    ap.add_argument("--form-steps", type=int, default=10)
+    ap.add_argument("--form-latency", type=int, default=50)
+    ap.add_argument("--legs", default="check,precision,batch,serve",
+                    help="further legs: check, precision, batch, serve")
+    ap.add_argument("--check-steps", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--batch", action="store_true", help="also time the 24-setting batch")
     ap.add_argument("--batch-path", default="f32")
-    ap.add_argument("--serve", action="store_true", help="also run the serving stream")
-    ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-hmin", type=int, default=200_000)
-    ap.add_argument("--serve-hmax", type=int, default=4_000_000)
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-latency", type=int, default=10)
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-hmin", type=int, default=1_000_000)
+    ap.add_argument("--serve-hmax", type=int, default=8_000_000)
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
-    ap.add_argument("--serve-path", default="f32")
+    ap.add_argument("--serve-path", default="q16")
     ap.add_argument("--fbp", action="store_true",
                     help="also time the initial iterate (FBP + median) of all histories")
-    ap.add_argument("--precision", action="store_true",
-                    help="also report each path form's image error against the oracle on the "
-                         "two-slice sub-problem of the 256x256x32 phantom")
     ap.add_argument("--precision-hist", type=int, default=3_750_000)
     ap.add_argument("--precision-cycles", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -332,6 +451,7 @@ def main():
     from paper_1803_01112_amd import synth, tvs
 
     tvs.load_library()
+    legs = {l for l in args.legs.split(",") if l}
     w = synth.workload(args.workload, n_hist=args.n_hist)
     log(f"generating {w.n_hist} histories of {w.name}")
     t0 = time.perf_counter()
@@ -342,59 +462,23 @@ def main():
     torch.cuda.synchronize()
     step_mm = min(w.grid.vx, w.grid.vy)
     vertices = mlp_vertices(h, step_mm)
-    if not args.fbp:
-        del h
-
-    log(f"timing {args.path_mode}: warmup {args.warmup}, steps {args.steps}")
-    ctx, st, dt, load_s = run_form(tvs, torch, w, dev, x0, args, args.path_mode, args.steps,
-                                   args.warmup)
+    fbp_h = h if args.fbp else None
+    del h
     H = w.n_hist
-    value = H * args.steps / dt
-    ms_per_step = 1e3 * dt / args.steps
-    log(f"{args.path_mode}: {value:.4g} histories/s, {ms_per_step:.2f} ms/cycle; stats {st}")
+    T = math.ceil(H / args.block)
 
-    # per-cycle latency (each cycle synchronised on its own)
-    lat = []
-    for _ in range(args.latency_cycles):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.iterate(1, args.lam, args.N, args.alpha, tv_check=args.check, seed=args.seed)
-        torch.cuda.synchronize()
-        lat.append(1e3 * (time.perf_counter() - t0))
-
-    # initial iterate: FBP of all histories + radius-2 median, timed on the
-    # device (returned to the host), the oracle's on a bounded prefix
-    fbp = None
-    if args.fbp:
-        tms = []
-        for _ in range(3):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ctx.initial_fbp(w.n_angles, median_radius=2)
-            tms.append(time.perf_counter() - t0)
-        fbp = dict(ms=1e3 * min(tms), unit="ms per initial iterate", histories=H,
-                   n_angles=w.n_angles, median_radius=2)
-        if not args.no_cpu:
-            import oracle
-            n = min(H, args.cpu_sample * 10)
-            hs = {k: v[:n] for k, v in h.items()}
-            t0 = time.perf_counter()
-            oracle.fbp_initial(w.grid, hs, w.n_angles, median_r=2)
-            fbp["cpu_oracle"] = dict(seconds=time.perf_counter() - t0, histories=n, cores=1,
-                                     kind="oracle")
-        log(f"fbp: {fbp}")
-        del h
-    ctx.close()
+    log(f"timing {args.path_mode}: warmup {args.warmup}, steps {args.steps}, "
+        f"latency cycles {args.latency_cycles}")
+    head, st = run_form(tvs, torch, w, dev, x0, args, args.path_mode, args.steps, args.warmup,
+                        args.latency_cycles)
+    log(f"{args.path_mode}: {head}")
 
     # dominant kernel of the timed region: the DROP step (one launch per
-    # block, timed with kernel-stamped HIP events on every k-th block) or the
-    # row formation on the second stream
+    # block, kernel-stamped events on every k-th block) or the row formation
+    # on the second stream (events around every launch)
     nnz = st["nnz"]
-    T = math.ceil(H / args.block)
-    ns = max(st["k_samples"], 1)
-    k1_ms = st["k1_ms_total"] / ns
+    k1_ms = st["k1_ms_total"] / max(st["k_samples"], 1)
     rows_ms = st["rows_ms_total"] / max(st["rows_launches"], 1)
-    chord_b = {"otf": 4, "f32": 4, "f16": 2}[args.path_mode]
     per_cycle = {"k_drop_tile": k1_ms * (T + 1)}
     if args.path_mode == "otf":
         per_cycle["k_rows_fill_tiled"] = st["rows_ms_total"] / max(st["cycles_timed"], 1)
@@ -405,41 +489,66 @@ def main():
         achieved = per_launch / (rows_ms * 1e-3) / 1e12
         roof = dict(bound="alu", kernel=dom, achieved=achieved, peak=FP64_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS, traffic=None,
-                    avg_launch_ms=rows_ms, algorithmic_per_launch=per_launch)
+                    avg_launch_ms=rows_ms, algorithmic_per_launch=per_launch,
+                    unit_of_work=f"{FP64_FLOPS_PER_VERTEX:.0f} FP64 flops per MLP vertex, "
+                                 f"{vertices / launches:.4g} vertices per launch")
     else:
-        per_launch = tile_step_bytes(nnz, T, chord_b, w.grid.nvox, args.block)
+        per_launch = sweep_bytes(H, nnz, args.path_mode) / T
         achieved = per_launch / (k1_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_ms=k1_ms,
-                    algorithmic_per_launch=per_launch)
+                    algorithmic_per_launch=per_launch,
+                    unit_of_work="16 B per history + (4 + chord bytes) per entry of one block")
     roof["per_cycle_ms"] = per_cycle
     roof["traffic"] = measured_traffic(dom, f"{w.name}/{H}/B{args.block}/{args.path_mode}")
 
     forms = {}
     for form in [f for f in args.forms.split(",") if f]:
         log(f"timing form {form}")
-        c2, s2, d2, l2 = run_form(tvs, torch, w, dev, x0, args, form, args.steps, 1)
-        dms = s2["drop_ms_total"] / max(s2["drop_launches"], 1)
-        cb = 2 if form == "f16" else 4
-        gbs = (T + 1) * tile_step_bytes(s2["nnz"], T, cb, w.grid.nvox, args.block) / (dms * 1e-3) / 1e9
-        forms[form] = dict(value=H * args.steps / d2, ms_per_step=1e3 * d2 / args.steps,
-                           drop_ms=dms, drop_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
-                           store_build_s=l2)
-        c2.close()
+        forms[form], _ = run_form(tvs, torch, w, dev, x0, args, form, args.form_steps, 1,
+                                  args.form_latency)
+        forms[form]["store_build_s"] = forms[form].pop("load_s")
         log(f"{form}: {forms[form]}")
 
+    check = None
+    if "check" in legs:
+        log("timing the check-on cycle")
+        check, _ = run_form(tvs, torch, w, dev, x0, args, args.path_mode, args.check_steps, 1, 0,
+                            check=True)
+        check["vs_check_off"] = check["value"] / head["value"]
+        log(f"check on: {check}")
+
+    fbp = None
+    if fbp_h is not None:
+        ctx = tvs.Context(w.grid, block_size=args.block)
+        ctx.load_histories(dev)
+        tms = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.initial_fbp(w.n_angles, median_radius=2)
+            tms.append(time.perf_counter() - t0)
+        ctx.close()
+        fbp = dict(ms=1e3 * min(tms), unit="ms per initial iterate", histories=H,
+                   n_angles=w.n_angles, median_radius=2)
+        log(f"fbp: {fbp}")
+        del fbp_h
+    del dev
+    torch.cuda.empty_cache()
+
+    precision = None
+    if "precision" in legs:
+        log("precision leg")
+        precision = precision_report(tvs, torch, args)
     batch = None
-    if args.batch:
-        log("timing the 24-setting batch")
-        batch = run_batch(tvs, torch, w, dev, x0, args)
+    if "batch" in legs:
+        batch = run_batch(tvs, torch, args)
         log(f"batch: {batch}")
-    serving = None
-    if args.serve:
-        del dev
         torch.cuda.empty_cache()
-        log("serving stream")
+    serving = None
+    if "serve" in legs:
+        log("serving leg")
         serving = run_serving(tvs, args)
-        log(f"serving: {serving}")
 
     if args.copy_calibration:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
@@ -448,60 +557,20 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 268435456 bytes read, 268435456 bytes written")
         del a, b
-
-    # a STREAM-like reference on this device: a plain device-to-device copy
-    # of 2 GiB, read plus written bytes over its time (the roofline keeps the
-    # published peak; this says how much of it a plain copy reaches here)
-    src = torch.ones(512 << 20, dtype=torch.float32, device="cuda:0")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    hbm_measured = {"copy_gbs": copy_gbs, "frac_of_published": copy_gbs / HBM_PEAK_GBS,
-                    "what": "device-to-device copy of 2 GiB, bytes read + written / time"}
-    del src, dst
-    log(f"plain copy: {copy_gbs:.0f} GB/s")
-    # reference rate of unique-address float32 global atomic adds (torch's
-    # index_add_, one atomic per element, consecutive addresses), against
-    # which the DROP step's atomic requests are set in the committed counter
-    # record (there is no published atomic peak)
-    n_at = 64 << 20
-    acc = torch.zeros(n_at, dtype=torch.float32, device="cuda:0")
-    idx = torch.arange(n_at, dtype=torch.int64, device="cuda:0")
-    val = torch.ones(n_at, dtype=torch.float32, device="cuda:0")
-    acc.index_add_(0, idx, val)
-    e0.record()
-    for _ in range(3):
-        acc.index_add_(0, idx, val)
-    e1.record()
-    torch.cuda.synchronize()
-    at_ms = e0.elapsed_time(e1) / 3
-    atomic_reference = {"what": "torch index_add_, float32, 64M unique consecutive addresses",
-                        "lane_atomics_per_s": n_at / (at_ms * 1e-3), "ms": at_ms}
-    del acc, idx, val
-    log(f"atomic reference: {atomic_reference}")
-
-    precision = None
-    if args.precision:
-        log("precision report")
-        precision = precision_report(tvs, torch, args)
+    hbm_measured, atomic_reference = references(torch)
+    log(f"references: {hbm_measured} {atomic_reference}")
 
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cpu = None if args.no_cpu else cpu_baseline(w, args, cores)
 
     out = {
         "metric": "proton histories/s per TVS iteration (MLP+DROP+TV)",
-        "value": value,
+        "value": head["value"],
         "unit": "histories/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -510,24 +579,22 @@ def main():
         "config": {"workload": f"{w.name}: {w.grid.nx}x{w.grid.ny}x{w.grid.nz} voxels of "
                                f"{w.grid.vx}x{w.grid.vy}x{w.grid.vz} mm, {w.diameter:.0f} mm "
                                f"cylinder with 6 inserts, {H} histories at {w.n_angles} angles",
-                   "block_size": args.block, "lambda": args.lam, "N": args.N,
-                   "alpha": args.alpha, "tv_check": bool(args.check),
+                   "block_size": args.block, "blocks_per_sweep": T, "lambda": args.lam,
+                   "N": args.N, "alpha": args.alpha, "tv_check": False,
                    "path_mode": args.path_mode, "nnz": nnz, "parallelism": "1 GPU"},
-        "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                        "cycles": len(lat)} if lat else None),
-        "phases_ms_per_cycle": {"tv": st["tv_ms_total"] / max(st["cycles_timed"], 1),
-                                "sweep": st["sweep_ms_total"] / max(st["cycles_timed"], 1),
-                                "rows": st["rows_ms_total"] / max(st["cycles_timed"], 1),
-                                "drop": st["drop_ms_total"] / max(st["cycles_timed"], 1)},
-        "load_s": load_s,
+        "latency_ms": head.get("latency_ms"),
+        "phases_ms_per_cycle": head["phases_ms_per_cycle"],
+        "hbm": head["hbm"],
+        "load_s": head["load_s"],
         "roofline": roof,
         "hbm_measured": hbm_measured,
         "atomic_reference": atomic_reference,
         "forms": forms,
-        "batch": batch,
-        "fbp": fbp,
+        "check": check,
         "precision": precision,
+        "batch": batch,
         "serving": serving,
+        "fbp": fbp,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

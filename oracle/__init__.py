@@ -116,6 +116,10 @@ def lib():
         L.or_fbp_backproject.argtypes = [C.POINTER(OrGrid), dp, C.c_int32, C.c_double, C.c_int32,
                                          dp]
         L.or_median_slices.argtypes = [C.POINTER(OrGrid), dp, C.c_int32, dp]
+        L.or_set_threads.argtypes = [C.c_int32]
+        L.or_set_threads.restype = None
+        L.or_max_threads.argtypes = []
+        L.or_max_threads.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -238,6 +242,15 @@ def rand_ell(k: int, ell: int, state: int):
     s = C.c_uint64(state)
     r = lib().or_rand_ell(k, ell, C.byref(s))
     return r, s.value
+
+
+def set_threads(n: int) -> None:
+    """Threads of the row formation (OpenMP); results do not depend on it."""
+    lib().or_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().or_max_threads())
 
 
 # --------------------------------------------------------------------------- driver

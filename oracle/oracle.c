@@ -33,9 +33,22 @@
  * Parity pins live in tests/ (closed forms, invariants, brute force).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the row formation (the only parallel loop); rows are
+ * independent, so the results do not depend on it. */
+void or_set_threads(int32_t n)
+{
+    omp_set_num_threads(n > 0 ? n : 1);
+}
+
+int32_t or_max_threads(void)
+{
+    return (int32_t)omp_get_max_threads();
+}
 
 /* ------------------------------------------------------------------------ */
 /* Grid.  Voxel (i,j,k) occupies [ox+i*vx, ox+(i+1)*vx) x ... ; x fastest.   */

@@ -10,9 +10,10 @@
 // The image and the subgradient are float64 on the device: DROP increments
 // with a small relaxation are tiny next to the RSP itself, and the
 // subgradient only sees the direction of (dx, dy), so a float32 image would
-// turn its rounding into order-one changes of v.  Each workgroup stages a
-// 64x4 tile of one slice plus a one-voxel halo in LDS, evaluates the
-// stencil, and writes a float64 partial sum.  The last workgroup to finish (ticket counter) adds
+// turn its rounding into order-one changes of v.  A workgroup stages 64x4
+// tiles of one slice plus a one-voxel halo in LDS (a grid of at most 1024
+// workgroups strides over the tiles), evaluates the stencil, and writes a
+// float64 partial sum.  The last workgroup to finish (ticket counter) adds
 // the partials in a fixed order, so every reduction is deterministic and no
 // host round trip is needed between the gradient and the update.
 #include "tvs_internal.hpp"
@@ -23,21 +24,15 @@ namespace {
 constexpr int TX = 64, TY = 4, kThreads = TX * TY;
 constexpr int HX = TX + 2, HY = TY + 2;
 
-// Loads the tile of slice z (origin i0, j0) with a one-voxel halo.  With
-// g != nullptr the staged values are z = x + s*g (the trial image of a
-// checked step), computed exactly as the accepting update computes them.
-__device__ inline void load_tile(double (*t)[HX], const double *x, const double *g, double s,
-                                 const GridDev &G, int z, int i0, int j0)
+// Loads the tile of slice z (origin i0, j0) with a one-voxel halo.
+__device__ inline void load_tile(double (*t)[HX], const double *x, const GridDev &G, int z, int i0,
+                                 int j0)
 {
     for (int q = threadIdx.x; q < HX * HY; q += kThreads) {
         int ly = q / HX, lx = q - ly * HX;
         int i = i0 + lx - 1, j = j0 + ly - 1;
         double v = 0.0;
-        if (i >= 0 && i < G.nx && j >= 0 && j < G.ny) {
-            int64_t p = vaddr(G, i, j, z);
-            v = x[p];
-            if (g) v = fma(s, g[p], v);
-        }
+        if (i >= 0 && i < G.nx && j >= 0 && j < G.ny) v = x[vaddr(G, i, j, z)];
         t[ly][lx] = v;
     }
     __syncthreads();
@@ -78,15 +73,17 @@ __device__ inline double block_sum(double v)
 }
 
 // Writes this workgroup's partial; the last workgroup reduces all partials
-// in a fixed order into *out and re-arms the ticket.
+// in a fixed order into *out and re-arms the ticket.  The partials are read
+// with plain loads after the acquire that observed the last ticket (every
+// writer released its partial before taking a ticket), four in flight per
+// lane.
 __device__ inline void finish_reduction(double partial, double *part, uint32_t *ticket,
                                         double *out)
 {
     __shared__ uint32_t last;
-    const uint32_t nwg = gridDim.x * gridDim.y * gridDim.z;
-    const uint32_t wg = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const uint32_t nwg = gridDim.x;
     if (threadIdx.x == 0) {
-        part[wg] = partial;
+        part[blockIdx.x] = partial;
         __threadfence();
         uint32_t old = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL,
                                               __HIP_MEMORY_SCOPE_AGENT);
@@ -96,8 +93,8 @@ __device__ inline void finish_reduction(double partial, double *part, uint32_t *
     if (!last) return;
     __threadfence();
     double v = 0.0;
-    for (uint32_t q = threadIdx.x; q < nwg; q += kThreads)
-        v += __hip_atomic_load(part + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll 4
+    for (uint32_t q = threadIdx.x; q < nwg; q += kThreads) v += part[q];
     double tot = block_sum(v);
     if (threadIdx.x == 0) {
         *out = tot;
@@ -105,49 +102,58 @@ __device__ inline void finish_reduction(double partial, double *part, uint32_t *
     }
 }
 
+// Tiles of TX x TY voxels of one slice; a capped grid of workgroups strides
+// over them (tile T of workgroup w: T = w, w + gridDim.x, ...), so the
+// reductions have few partial sums.
+constexpr int kMaxWgs = 1024;
+
+struct TileGrid {
+    int tx, ty, nz;
+    __device__ int64_t count() const { return (int64_t)tx * ty * nz; }
+    __device__ void at(int64_t T, int &i0, int &j0, int &zz) const
+    {
+        i0 = (int)(T % tx) * TX;
+        j0 = (int)((T / tx) % ty) * TY;
+        zz = (int)(T / ((int64_t)tx * ty));
+    }
+};
+
+__device__ inline TileGrid tile_grid(const GridDev &G)
+{
+    return TileGrid{(G.nx + TX - 1) / TX, (G.ny + TY - 1) / TY, G.nz};
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_tv_grad(GridDev G, const double *x, double eps, double *gout, double *part, uint32_t *ticket,
           double *out)
 {
     __shared__ double tile[HY][HX];
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    load_tile(tile, x, nullptr, 0.0, G, (int)blockIdx.z, i0, j0);
-    const int i = i0 + (threadIdx.x % TX), j = j0 + (threadIdx.x / TX);
+    const TileGrid TG = tile_grid(G);
     double sq = 0.0;
-    if (i < G.nx && j < G.ny) {
-        Stencil S{tile, G.nx, G.ny, i0, j0, eps * eps};
-        double gv = 0.0;
-        double m = S.m(i, j);
-        if (m > 0.0) gv -= (S.dx(i, j) + S.dy(i, j)) / m;
-        if (i > 0) {
-            double mm = S.m(i - 1, j);
-            if (mm > 0.0) gv += S.dx(i - 1, j) / mm;
+    for (int64_t T = blockIdx.x; T < TG.count(); T += gridDim.x) {
+        int i0, j0, zz;
+        TG.at(T, i0, j0, zz);
+        __syncthreads();
+        load_tile(tile, x, G, zz, i0, j0);
+        const int i = i0 + (threadIdx.x % TX), j = j0 + (threadIdx.x / TX);
+        if (i < G.nx && j < G.ny) {
+            Stencil S{tile, G.nx, G.ny, i0, j0, eps * eps};
+            double gv = 0.0;
+            double m = S.m(i, j);
+            if (m > 0.0) gv -= (S.dx(i, j) + S.dy(i, j)) / m;
+            if (i > 0) {
+                double mm = S.m(i - 1, j);
+                if (mm > 0.0) gv += S.dx(i - 1, j) / mm;
+            }
+            if (j > 0) {
+                double mm = S.m(i, j - 1);
+                if (mm > 0.0) gv += S.dy(i, j - 1) / mm;
+            }
+            gout[vaddr(G, i, j, zz)] = gv;
+            sq += gv * gv;
         }
-        if (j > 0) {
-            double mm = S.m(i, j - 1);
-            if (mm > 0.0) gv += S.dy(i, j - 1) / mm;
-        }
-        gout[vaddr(G, i, j, blockIdx.z)] = gv;
-        sq = gv * gv;
     }
     finish_reduction(block_sum(sq), part, ticket, out);
-}
-
-__global__ void __launch_bounds__(kThreads)
-k_tv_phi(GridDev G, const double *x, const double *g, double beta, const double *n2, double eps,
-         double *part, uint32_t *ticket, double *out)
-{
-    __shared__ double tile[HY][HX];
-    const double s = g ? step_scale(beta, n2) : 0.0;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    load_tile(tile, x, (s != 0.0) ? g : nullptr, s, G, (int)blockIdx.z, i0, j0);
-    const int i = i0 + (threadIdx.x % TX), j = j0 + (threadIdx.x / TX);
-    double v = 0.0;
-    if (i < G.nx && j < G.ny) {
-        Stencil S{tile, G.nx, G.ny, i0, j0, eps * eps};
-        v = S.m(i, j) - eps;
-    }
-    finish_reduction(block_sum(v), part, ticket, out);
 }
 
 // ---------------------------------------------------------------- checked step
@@ -251,20 +257,25 @@ k_tv_check(GridDev G, const double *x, const double *g, const double *n2, double
     __shared__ double sc[kTries];
     __shared__ double tot[kTries + 1];
     __shared__ uint32_t last;
+    const TileGrid TG = tile_grid(G);
     const int64_t ell0 = sd->ell;
     const double gn2 = *n2;
     const int cnt0 = max_tries < kTries ? max_tries : kTries;
     if (threadIdx.x < kTries) sc[threadIdx.x] = trial_scale(alpha, ell0 + threadIdx.x, gn2);
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    load_pair(tx, tg, x, g, G, (int)blockIdx.z, i0, j0);
     double acc[kTries + 1];
 #pragma unroll
     for (int t = 0; t <= kTries; t++) acc[t] = 0.0;
-    trial_terms(tx, tg, sc, cnt0, G, i0, j0, eps, true, acc, acc[kTries]);
+    for (int64_t T = blockIdx.x; T < TG.count(); T += gridDim.x) {
+        int i0, j0, zz;
+        TG.at(T, i0, j0, zz);
+        __syncthreads();
+        load_pair(tx, tg, x, g, G, zz, i0, j0);
+        trial_terms(tx, tg, sc, cnt0, G, i0, j0, eps, true, acc, acc[kTries]);
+    }
     block_sums(acc, tot);
     // partials of this workgroup; the last one to finish decides
-    const uint32_t nwg = gridDim.x * gridDim.y * gridDim.z;
-    const uint32_t wg = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const uint32_t nwg = gridDim.x;
+    const uint32_t wg = blockIdx.x;
     if (threadIdx.x == 0) {
         for (int t = 0; t <= kTries; t++) part[(int64_t)t * nwg + wg] = tot[t];
         __threadfence();
@@ -275,13 +286,14 @@ k_tv_check(GridDev G, const double *x, const double *g, const double *n2, double
     __syncthreads();
     if (!last) return;
     __threadfence();
+    // plain loads after the acquire above (every writer released its
+    // partials before taking a ticket), kTries + 1 in flight per lane
     double v[kTries + 1];
 #pragma unroll
-    for (int t = 0; t <= kTries; t++) {
-        v[t] = 0.0;
-        for (uint32_t q = threadIdx.x; q < nwg; q += kThreads)
-            v[t] += __hip_atomic_load(part + (int64_t)t * nwg + q, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
+    for (int t = 0; t <= kTries; t++) v[t] = 0.0;
+    for (uint32_t q = threadIdx.x; q < nwg; q += kThreads) {
+#pragma unroll
+        for (int t = 0; t <= kTries; t++) v[t] += part[(int64_t)t * nwg + q];
     }
     block_sums(v, tot);
     const double phx = tot[kTries];
@@ -292,7 +304,6 @@ k_tv_check(GridDev G, const double *x, const double *g, const double *n2, double
     double s_acc = found >= 0 ? sc[found] : 0.0;
     int32_t tries = found >= 0 ? found + 1 : cnt0;
     // further rounds, this workgroup alone, over every tile
-    const int tiles_x = gridDim.x, tiles_y = gridDim.y;
     for (int base = kTries; found < 0 && base < max_tries; base += kTries) {
         const int cnt = (max_tries - base < kTries) ? max_tries - base : kTries;
         __syncthreads();
@@ -300,12 +311,12 @@ k_tv_check(GridDev G, const double *x, const double *g, const double *n2, double
         double a[kTries + 1];
 #pragma unroll
         for (int t = 0; t <= kTries; t++) a[t] = 0.0;
-        for (uint32_t T = 0; T < nwg; T++) {
-            const int bx = (int)(T % tiles_x), by = (int)((T / tiles_x) % tiles_y);
-            const int bz = (int)(T / ((uint32_t)tiles_x * tiles_y));
+        for (int64_t T = 0; T < TG.count(); T++) {
+            int i0, j0, zz;
+            TG.at(T, i0, j0, zz);
             __syncthreads();
-            load_pair(tx, tg, x, g, G, bz, bx * TX, by * TY);
-            trial_terms(tx, tg, sc, cnt, G, bx * TX, by * TY, eps, false, a, a[kTries]);
+            load_pair(tx, tg, x, g, G, zz, i0, j0);
+            trial_terms(tx, tg, sc, cnt, G, i0, j0, eps, false, a, a[kTries]);
         }
         block_sums(a, tot);
         for (int t = 0; t < cnt; t++)
@@ -401,13 +412,6 @@ __global__ void __launch_bounds__(kThreads) k_narrow(GridDev G, const double *sr
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_fill_zero(float *p, int64_t n)
-{
-    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * kThreads)
-        p[q] = 0.0f;
-}
-
 unsigned elem_grid(int64_t n)
 {
     int64_t wgs = (n + kThreads - 1) / kThreads;
@@ -416,9 +420,11 @@ unsigned elem_grid(int64_t n)
     return (unsigned)wgs;
 }
 
+// workgroups of the TV kernels: one per tile, at most kMaxWgs
 dim3 tv_grid(const GridDev &g)
 {
-    return dim3((unsigned)((g.nx + TX - 1) / TX), (unsigned)((g.ny + TY - 1) / TY), (unsigned)g.nz);
+    const int64_t tiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * g.nz;
+    return dim3((unsigned)(tiles < kMaxWgs ? tiles : kMaxWgs));
 }
 
 }  // namespace
@@ -460,12 +466,6 @@ hipError_t launch_narrow(const GridDev &g, const double *src, float *dst, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream)
-{
-    hipLaunchKernelGGL(k_fill_zero, dim3(elem_grid(n)), dim3(kThreads), 0, stream, p, n);
-    return hipGetLastError();
-}
-
 int64_t tv_check_parts(const GridDev &g) { return tv_num_parts(g) * (kTries + 1); }
 
 hipError_t launch_tv_check(const GridDev &g, const double *x, double eps, double alpha,
@@ -497,15 +497,6 @@ hipError_t launch_sched_draw(SchedDev *sd, int64_t k, hipStream_t stream)
 hipError_t launch_sched_set(SchedDev *sd, int64_t ell, uint64_t rng, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_sched_set, dim3(1), dim3(64), 0, stream, sd, ell, rng);
-    return hipGetLastError();
-}
-
-hipError_t launch_tv_phi(const GridDev &g, const double *x, double beta, double eps,
-                         const TvBuffers &t, hipStream_t stream)
-{
-    hipLaunchKernelGGL(k_tv_phi, tv_grid(g), dim3(kThreads), 0, stream, g, x,
-                       (beta != 0.0) ? t.g : nullptr, beta, t.scal, eps, t.part, t.ticket,
-                       t.scal + 1);
     return hipGetLastError();
 }
 

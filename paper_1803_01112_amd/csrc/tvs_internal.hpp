@@ -303,11 +303,6 @@ hipError_t launch_tv_grad(const GridDev &g, const double *x, double eps, const T
 // x = x + s * g with s = -beta / sqrt(scal[0]) (0 when the norm is 0).
 hipError_t launch_tv_step(const GridDev &g, double *x, double beta, const TvBuffers &t,
                           hipStream_t stream);
-// scal[1] = TV(x + s g) with s = -beta / sqrt(scal[0]) rounded as in
-// launch_tv_step, so an accepted trial image equals the stepped image
-// (beta = 0: TV(x)).
-hipError_t launch_tv_phi(const GridDev &g, const double *x, double beta, double eps,
-                         const TvBuffers &t, hipStream_t stream);
 // Image conversion between the ABI's x-fastest float32 and the device's
 // float64 tiled layout (the padding of dst is left untouched by widen).
 hipError_t launch_widen(const GridDev &g, const float *src, double *dst, hipStream_t stream);
