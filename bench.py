@@ -124,10 +124,12 @@ def latency(torch, ctx, n, kw):
     return out
 
 
-def run_form(tvs, torch, w, dev_hist, x0, args, mode, K, W, n_lat, check=False):
-    """Loads the histories in path mode `mode`, runs W untimed and K timed
-    cycles, then n_lat cycles one at a time; returns figures and stats."""
-    ctx = tvs.Context(w.grid, block_size=args.block, path_mode=mode,
+def run_form(tvs, torch, w, dev_hist, x0, args, mode, K, W, n_lat, check=False, block=None):
+    """Loads the histories in path mode `mode` (DROP blocks of `block`
+    histories, default the benchmark's), runs W untimed and K timed cycles,
+    then n_lat cycles one at a time; returns figures and stats."""
+    block = block or args.block
+    ctx = tvs.Context(w.grid, block_size=block, path_mode=mode,
                       time_sample=args.time_sample)
     t0 = time.perf_counter()
     ctx.load_histories(dev_hist)
@@ -143,7 +145,7 @@ def run_form(tvs, torch, w, dev_hist, x0, args, mode, K, W, n_lat, check=False):
     steps = ctx.step_log() if check else None
     ctx.close()
     H = w.n_hist
-    T = math.ceil(H / args.block)
+    T = math.ceil(H / block)
     sweep_ms = st["drop_ms_total"] / max(st["drop_launches"], 1)
     ns = max(st["k_samples"], 1)
     out = dict(value=H * K / dt, unit="histories/s", ms_per_step=1e3 * dt / K,
@@ -152,6 +154,7 @@ def run_form(tvs, torch, w, dev_hist, x0, args, mode, K, W, n_lat, check=False):
                                     "sweep": st["sweep_ms_total"] / max(st["cycles_timed"], 1),
                                     "rows": st["rows_ms_total"] / max(st["cycles_timed"], 1),
                                     "drop": sweep_ms},
+               block_size=block, drop_steps=T + 1,
                drop_step_us=1e3 * sweep_ms / (T + 1),
                drop_launch_us=1e3 * st["k1_ms_total"] / ns)
     b = sweep_bytes(H, st["nnz"], mode)
@@ -410,7 +413,8 @@ def main():
     ap.add_argument("--time-sample", type=int, default=16,
                     help="kernel-stamped HIP events on the launch of every k-th DROP block")
     ap.add_argument("--latency-cycles", type=int, default=50)
-    ap.add_argument("--forms", default="f32,f16,q16", help="path-store forms timed beside")
+    ap.add_argument("--forms", default="f32,f16,q16,q16@25600",
+                    help="path-store forms timed beside (mode or mode@block size)")
     ap.add_argument("--form-steps", type=int, default=10)
     ap.add_argument("--form-latency", type=int, default=50)
     ap.add_argument("--legs", default="check,precision,batch,serve",
@@ -505,8 +509,9 @@ def main():
     forms = {}
     for form in [f for f in args.forms.split(",") if f]:
         log(f"timing form {form}")
-        forms[form], _ = run_form(tvs, torch, w, dev, x0, args, form, args.form_steps, 1,
-                                  args.form_latency)
+        mode, _, blk = form.partition("@")
+        forms[form], _ = run_form(tvs, torch, w, dev, x0, args, mode, args.form_steps, 1,
+                                  args.form_latency, block=int(blk) if blk else None)
         forms[form]["store_build_s"] = forms[form].pop("load_s")
         log(f"{form}: {forms[form]}")
 
