@@ -289,6 +289,36 @@ int tvs_initial_fbp(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_de
 int tvs_initial_fbp_noalloc(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, int on_device,
                             void *stream);
 
+/* Hull detection of the object from the loaded histories, before the MLP is
+ * relied on (the paper's preprocessing, Section III-D, bounds the object and
+ * cites earlier work for how).  The textbook straight-line detectors on each
+ * history's line from its entry to its exit point, voxels taken by the same
+ * midpoint walk as the rows:
+ *   space modelling: a line whose WEPL is at least wepl_in_mm counts every
+ *     voxel it crosses (protons that lost energy crossed the object);
+ *   space carving: a line whose WEPL is below wepl_out_mm carves every voxel
+ *     it crosses (a proton that lost no energy crossed no object);
+ *   a voxel is inside when at least min_in lines count it and at most
+ *   max_out lines carve it.
+ * hull receives nx*ny*nz bytes (x fastest, 1 inside, 0 outside; host or
+ * device, may be NULL).  With mask_image set, the context image is set to
+ * itself times the hull (as by tvs_set_image: schedule and batch reset), so
+ * that an initial iterate from tvs_initial_fbp or tvs_set_image is bounded
+ * by the hull.  Waits for the work.  TVS_EINVAL for min_in < 0, max_out < 0
+ * or a NaN threshold; TVS_ESTATE before tvs_load_histories; TVS_ENOMEM when
+ * the two counters (4 bytes per voxel each) do not fit the budget. */
+typedef struct {
+    double wepl_in_mm;      /* space modelling threshold */
+    double wepl_out_mm;     /* space carving threshold (0: no carving) */
+    int32_t min_in;         /* counting lines needed inside (0: space modelling off) */
+    int32_t max_out;        /* carving lines tolerated inside */
+    int32_t mask_image;     /* 1: the context image is multiplied by the hull */
+    int32_t pad;
+} tvs_hull_params;
+
+int tvs_hull_detect(tvs_ctx *ctx, const tvs_hull_params *p, uint8_t *hull, int on_device,
+                    void *stream);
+
 /* Counters and timings of the context. */
 int tvs_get_stats(tvs_ctx *ctx, tvs_stats *out);
 

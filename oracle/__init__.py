@@ -116,6 +116,14 @@ def lib():
         L.or_fbp_backproject.argtypes = [C.POINTER(OrGrid), dp, C.c_int32, C.c_double, C.c_int32,
                                          dp]
         L.or_median_slices.argtypes = [C.POINTER(OrGrid), dp, C.c_int32, dp]
+        L.or_hull_counts.argtypes = [C.POINTER(OrGrid), C.POINTER(OrHist), C.c_int64, C.c_double,
+                                     C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.or_hull_counts.restype = None
+        L.or_hull_decide.argtypes = [C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.c_int32, C.c_int32, C.POINTER(C.c_uint8)]
+        L.or_hull_decide.restype = None
+        L.or_log.argtypes = [C.c_double]
+        L.or_log.restype = C.c_double
         L.or_set_threads.argtypes = [C.c_int32]
         L.or_set_threads.restype = None
         L.or_max_threads.argtypes = []
@@ -242,6 +250,37 @@ def rand_ell(k: int, ell: int, state: int):
     s = C.c_uint64(state)
     r = lib().or_rand_ell(k, ell, C.byref(s))
     return r, s.value
+
+
+def hull_counts(grid, hist, wepl_in, wepl_out):
+    """Per voxel (x fastest): (in_count, out_count) -- histories whose straight
+    entry-exit line crosses the voxel with WEPL >= wepl_in (space modelling)
+    and with WEPL < wepl_out (space carving)."""
+    hs, keep = _hist_struct(hist)
+    n = len(keep["ex"])
+    nvox = int(grid.nx) * int(grid.ny) * int(grid.nz)
+    cin = np.zeros(nvox, np.int32)
+    cout = np.zeros(nvox, np.int32)
+    lib().or_hull_counts(C.byref(_grid(grid)), C.byref(hs), n, float(wepl_in), float(wepl_out),
+                         cin.ctypes.data_as(C.POINTER(C.c_int32)),
+                         cout.ctypes.data_as(C.POINTER(C.c_int32)))
+    return cin, cout
+
+
+def hull(grid, hist, wepl_in=1.0, wepl_out=1.0, min_in=1, max_out=0):
+    """Hull mask (uint8 per voxel, x fastest): in_count >= min_in and
+    out_count <= max_out."""
+    cin, cout = hull_counts(grid, hist, wepl_in, wepl_out)
+    out = np.zeros(len(cin), np.uint8)
+    lib().or_hull_decide(len(cin), cin.ctypes.data_as(C.POINTER(C.c_int32)),
+                         cout.ctypes.data_as(C.POINTER(C.c_int32)), int(min_in), int(max_out),
+                         out.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return out
+
+
+def log(x: float) -> float:
+    """The oracle's natural logarithm (the MLP's Highland factor uses it)."""
+    return float(lib().or_log(float(x)))
 
 
 def set_threads(n: int) -> None:

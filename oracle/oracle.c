@@ -100,10 +100,43 @@ static double or_ipow(double base, int e)
     return r;
 }
 
+/*
+ * Natural logarithm of a positive, finite, normal x, by the textbook
+ * reduction x = m 2^e with m in [sqrt(1/2), sqrt(2)) and the series
+ *   ln m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ... + s^21/21),
+ *   s = (m - 1) / (m + 1), |s| <= 0.1716,
+ * whose first omitted term is below 2e-19.  Written out here rather than
+ * taken from the C library so that the MLP's Highland factor is the same
+ * double on every platform (libraries round their logarithms differently).
+ */
+double or_log(double x)
+{
+    int e = 0;
+    double m = frexp(x, &e);            /* x = m 2^e, m in [0.5, 1) */
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    double s = (m - 1.0) / (m + 1.0);
+    double z = s * s;
+    double p = 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    p = p * z + 1.0;
+    return (double)e * 0.69314718055994530942 + 2.0 * s * p;
+}
+
 static double or_highland_scale(double depth_mm, int log_term)
 {
     double f = 1.0;
-    if (log_term) f = 1.0 + 0.038 * log(depth_mm / OR_X0_MM);
+    if (log_term) f = 1.0 + 0.038 * or_log(depth_mm / OR_X0_MM);
     return OR_E0_MEV * OR_E0_MEV * f * f / OR_X0_MM;
 }
 
@@ -145,10 +178,13 @@ void or_mlp_sigmas(double d1, double L, const or_mlp_cfg *cfg,
         }
         c[k] = (k % 2) ? -acc : acc;
     }
+    /* integral_0^d2 s^m s^k ds = d2^(m+k+1) / (m+k+1) */
+    double q[9];
+    for (int n = 1; n <= 8; n++) q[n] = or_ipow(d2, n) / (double)n;
     double j[3] = {0.0, 0.0, 0.0};
     for (int m = 0; m < 3; m++)
         for (int k = 0; k < 6; k++)
-            j[m] += c[k] * or_ipow(d2, m + k + 1) / (double)(m + k + 1);
+            j[m] += c[k] * q[m + k + 1];
     double A2 = or_highland_scale(d2, cfg->log_term);
     S2[0] = A2 * j[2];
     S2[1] = A2 * j[1];
@@ -164,10 +200,12 @@ static void m2_mul(const double A[4], const double B[4], double C[4])
     double c3 = A[2] * B[1] + A[3] * B[3];
     C[0] = c0; C[1] = c1; C[2] = c2; C[3] = c3;
 }
+/* Inverse as the adjugate times the reciprocal of the determinant. */
 static void m2_inv(const double A[4], double R[4])
 {
     double det = A[0] * A[3] - A[1] * A[2];
-    double r0 = A[3] / det, r1 = -A[1] / det, r2 = -A[2] / det, r3 = A[0] / det;
+    double rd = 1.0 / det;
+    double r0 = A[3] * rd, r1 = -A[1] * rd, r2 = -A[2] * rd, r3 = A[0] * rd;
     R[0] = r0; R[1] = r1; R[2] = r2; R[3] = r3;
 }
 static void m2_transpose(const double A[4], double R[4])
@@ -857,4 +895,48 @@ void or_median_slices(const or_grid *g, const double *x, int32_t r, double *y)
                 y[i + g->nx * (j + g->ny * k)] = buf[(n - 1) / 2];
             }
     free(buf);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hull detection.  The paper's preprocessing (Section III-D, citing earlier */
+/* work) bounds the object before the MLP is formed; how is not given.       */
+/* Reading: the textbook straight-line hull detectors, on each history's     */
+/* straight line from its entry to its exit point, voxels taken by the same  */
+/* midpoint walk as the rows:                                                */
+/*   space modelling: in_count[j] = histories with WEPL >= wepl_in whose     */
+/*     line crosses voxel j (the object is where protons lost energy);       */
+/*   space carving: out_count[j] = histories with WEPL < wepl_out whose line */
+/*     crosses j (a proton that lost no energy crossed no object);           */
+/*   hull[j] = in_count[j] >= min_in and out_count[j] <= max_out.            */
+/* ------------------------------------------------------------------------ */
+void or_hull_counts(const or_grid *g, const or_hist *H, int64_t nh, double wepl_in,
+                    double wepl_out, int32_t *in_count, int32_t *out_count)
+{
+    int64_t nvox = (int64_t)g->nx * g->ny * g->nz;
+    memset(in_count, 0, sizeof(int32_t) * (size_t)nvox);
+    memset(out_count, 0, sizeof(int32_t) * (size_t)nvox);
+    int64_t cap = (int64_t)g->nx + g->ny + g->nz + 8;
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    double *chord = (double *)malloc(sizeof(double) * (size_t)cap);
+    for (int64_t i = 0; i < nh; i++) {
+        double w = H->wepl[i];
+        int in = (w >= wepl_in), out = (w < wepl_out);
+        if (!in && !out) continue;
+        double pts[6] = {H->ex[i], H->ey[i], H->ez[i], H->qx[i], H->qy[i], H->qz[i]};
+        int64_t n = or_walk_polyline(g, pts, 2, idx, chord, cap, NULL);
+        if (n > cap) n = cap;
+        for (int64_t q = 0; q < n; q++) {
+            if (in) in_count[idx[q]] += 1;
+            if (out) out_count[idx[q]] += 1;
+        }
+    }
+    free(idx);
+    free(chord);
+}
+
+void or_hull_decide(int64_t nvox, const int32_t *in_count, const int32_t *out_count,
+                    int32_t min_in, int32_t max_out, uint8_t *hull)
+{
+    for (int64_t j = 0; j < nvox; j++)
+        hull[j] = (uint8_t)(in_count[j] >= min_in && out_count[j] <= max_out);
 }

@@ -71,10 +71,40 @@ __device__ inline double div_int(double a, int n)
     return div_rn(a, (double)n, 1.0 / (double)n);
 }
 
+// Natural logarithm of a positive, finite, normal x: x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^21/21),
+// s = (m - 1) / (m + 1), |s| <= 0.1716 (first omitted term below 2e-19).
+// A fixed sequence of float64 operations (no library logarithm, whose last
+// bit differs between math libraries), so the Highland factor, and with it
+// every vertex, is the same double wherever the rows are formed.
+__device__ inline double series_log(double x)
+{
+    int e = 0;
+    double m = frexp(x, &e);
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    p = p * z + 1.0;
+    return (double)e * 0.69314718055994530942 + 2.0 * s * p;
+}
+
 __device__ inline double highland(double depth, int log_term)
 {
     double f = 1.0;
-    if (log_term) f = 1.0 + 0.038 * log(div_rn(depth, kX0, 1.0 / kX0));
+    if (log_term) f = 1.0 + 0.038 * series_log(div_rn(depth, kX0, 1.0 / kX0));
     return div_rn(kE0 * kE0 * f * f, kX0, 1.0 / kX0);
 }
 
@@ -97,10 +127,12 @@ __device__ inline M2 mul(const M2 &A, const M2 &B)
     return {A.a * B.a + A.b * B.c, A.a * B.b + A.b * B.d,
             A.c * B.a + A.d * B.c, A.c * B.b + A.d * B.d};
 }
+// Inverse as the adjugate times the reciprocal of the determinant.
 __device__ inline M2 inv(const M2 &A)
 {
-    double det = A.a * A.d - A.b * A.c;
-    return {A.d / det, -A.b / det, -A.c / det, A.a / det};
+    const double det = A.a * A.d - A.b * A.c;
+    const double r = 1.0 / det;
+    return {A.d * r, -A.b * r, -A.c * r, A.a * r};
 }
 __device__ inline void mvec(const M2 &A, double x0, double x1, double &y0, double &y1)
 {
@@ -117,7 +149,8 @@ __device__ inline void mvec(const M2 &A, double x0, double x1, double &y0, doubl
 //   kSeg      reserves each segment's place in its (block, tile) list;
 //   kRowMajor writes the entries in walk order (tvs_debug_rows);
 //   kTiled    writes every entry into its tile list at the reserved place.
-enum EmitMode { kCount = 0, kSeg = 1, kRowMajor = 2, kTiled = 3 };
+//   kHull     counts each voxel of a straight line once in in_cnt / out_cnt.
+enum EmitMode { kCount = 0, kSeg = 1, kRowMajor = 2, kTiled = 3, kHull = 4 };
 
 // A chord as an unsigned multiple of the fixed-point store's unit (1 / qinv
 // mm), rounded to nearest; the unit is the longest chord of the loaded rows
@@ -143,6 +176,8 @@ struct Emit {
     uint32_t qmax = 0;           // kTiled, fixed-point chords: largest code
     uint32_t qshift = 31;        // kTiled, fixed-point chords: tag bit of the code's bit 16
     double maxc = 0.0;           // kSeg: longest entry of the row
+    uint32_t *in_cnt = nullptr;  // kHull: this line counts (space modelling) into in_cnt,
+    uint32_t *out_cnt = nullptr; //        carves (space carving) into out_cnt
     uint32_t *btc = nullptr;     // kSeg: list lengths of this row's block
     uint64_t *segtab = nullptr;  // kSeg: (tile, place) of this row's segments
     const int64_t *segdst = nullptr;  // kTiled: first entry of this row's segments
@@ -182,6 +217,14 @@ struct Emit {
     __device__ inline void flush()
     {
         if (cur < 0) return;
+        if constexpr (MODE == kHull) {
+            if (in_cnt) atomicAdd(in_cnt + cur, 1u);
+            if (out_cnt) atomicAdd(out_cnt + cur, 1u);
+            cur = -1;
+            cur_len = 0.0;
+            n++;
+            return;
+        }
         const int32_t t = cur >> kTileShift;
         if (t != tile) {
             close_seg();
@@ -422,16 +465,20 @@ __device__ void form_row(const GridDev &g, const HistDev &H, const MlpCfg &m, in
         miss |= !in_tab;
         const double *tab = m.nj > 0 ? m.s1i + 3 * (in_tab ? j : m.nj - 1) : kZero3;
         double s1[3] = {tab[0], tab[1], tab[2]};
-        double pw[9];
-        pw[0] = 1.0;
+        // integral_0^d2 s^(mm+k) ds = d2^n / n, n = mm + k + 1 (powers of
+        // d2 as running products, which equal repeated multiplication)
+        double pw = 1.0, q[9];
 #pragma unroll
-        for (int q = 1; q <= 8; q++) pw[q] = pw[q - 1] * d2;
+        for (int n = 1; n <= 8; n++) {
+            pw = pw * d2;
+            q[n] = div_int(pw, n);
+        }
         double j2[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int mm = 0; mm < 3; mm++)
 #pragma unroll
             for (int k = 0; k < 6; k++)
-                j2[mm] += div_int(c[k] * pw[mm + k + 1], mm + k + 1);
+                j2[mm] += c[k] * q[mm + k + 1];
         double A2 = highland(d2, m.log_term);
         M2 S2 = {A2 * j2[2], A2 * j2[1], A2 * j2[1], A2 * j2[0]};
         M2 R0 = {1.0, d1, 0.0, 1.0};
@@ -644,6 +691,49 @@ k_validate(HistDev H, int64_t n, double step, uint32_t *bad, uint32_t *jmax)
     if (!ok) atomicAdd(bad, 1u);
 }
 
+// Hull detection: every history's straight line from its entry to its exit
+// point, walked like a row segment; a line whose WEPL reaches wepl_in counts
+// its voxels (space modelling), one whose WEPL is below wepl_out carves them
+// (space carving).  One lane per history; the counters are in the tiled
+// layout.
+__global__ void __launch_bounds__(kThreads)
+k_hull_counts(GridDev g, HistDev H, int64_t n, double wepl_in, double wepl_out, uint32_t *in_cnt,
+              uint32_t *out_cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const double w = H.s(kWepl)[i];
+    const bool in = w >= wepl_in, out = w < wepl_out;
+    if (!in && !out) return;
+    const double p0[3] = {H.s(kEx)[i], H.s(kEy)[i], H.s(kEz)[i]};
+    const double p1[3] = {H.s(kQx)[i], H.s(kQy)[i], H.s(kQz)[i]};
+    double g0[3], g1[3];
+    to_grid(g, p0, g0);
+    to_grid(g, p1, g1);
+    Emit<kHull, float> e;
+    e.in_cnt = in ? in_cnt : nullptr;
+    e.out_cnt = out ? out_cnt : nullptr;
+    walk_segment<kHull, float>(g, p0, p1, g0, g1, e);
+    e.flush();
+}
+
+// hull[p] (x-fastest) = in_cnt >= min_in and out_cnt <= max_out; with mask,
+// the image x (tiled layout) is multiplied by the hull.
+__global__ void __launch_bounds__(kThreads)
+k_hull_decide(GridDev g, const uint32_t *in_cnt, const uint32_t *out_cnt, uint32_t min_in,
+              uint32_t max_out, uint8_t *hull, double *mask)
+{
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * kThreads) {
+        const int64_t ii = p % g.nx, t = p / g.nx, jj = t % g.ny, kk = t / g.ny;
+        const int64_t a = vaddr(g, ii, jj, kk);
+        const bool inside = in_cnt[a] >= min_in && out_cnt[a] <= max_out;
+        hull[p] = inside ? 1u : 0u;
+        if (mask && !inside) mask[a] = 0.0;
+    }
+}
+
 // dst[b] = src[b * stride] for b = 0 .. n - 1
 __global__ void __launch_bounds__(kThreads)
 k_pick(const int64_t *src, int64_t stride, int64_t n, int64_t *dst)
@@ -802,6 +892,28 @@ hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *b
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_validate, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
                        0, stream, h, n, step, bad, jmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_hull_counts(const GridDev &g, const HistDev &h, int64_t n, double wepl_in,
+                              double wepl_out, uint32_t *in_cnt, uint32_t *out_cnt,
+                              hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hull_counts, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, stream, g, h, n, wepl_in, wepl_out, in_cnt, out_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_hull_decide(const GridDev &g, const uint32_t *in_cnt, const uint32_t *out_cnt,
+                              uint32_t min_in, uint32_t max_out, uint8_t *hull, double *mask,
+                              hipStream_t stream)
+{
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    int64_t wgs = (n + kThreads - 1) / kThreads;
+    if (wgs > 4096) wgs = 4096;
+    hipLaunchKernelGGL(k_hull_decide, dim3((unsigned)wgs), dim3(kThreads), 0, stream, g, in_cnt,
+                       out_cnt, min_in, max_out, hull, mask);
     return hipGetLastError();
 }
 

@@ -706,15 +706,17 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
     ctx->chunk = std::max<int64_t>(chunk, 1);
     for (int64_t f = 0; f < n; f += ctx->chunk) ctx->chunk_base.push_back(off[(size_t)f]);
     ctx->chunk_base.push_back(total);
-    // processing order of the row passes: within each chunk, histories by
-    // decreasing row length (a counting sort), so that the lanes of a
-    // wavefront walk rows of similar length; each segment's place is fixed
-    // below, so the order changes no result
+    // processing order of the row passes: within each DROP block, histories
+    // by decreasing row length (a counting sort), so that the lanes of a
+    // wavefront walk rows of similar length while a block's tile lists are
+    // still written together (their partly written lines meet in the L2
+    // before they are evicted); blocks never straddle a chunk.  Each
+    // segment's place is fixed below, so the order changes no result
     {
         std::vector<int32_t> ord((size_t)n);
         std::vector<int64_t> cnt_len((size_t)mx + 2);
-        for (int64_t f0 = 0; f0 < n; f0 += ctx->chunk) {
-            const int64_t f1 = std::min(n, f0 + ctx->chunk);
+        for (int64_t f0 = 0; f0 < n; f0 += B) {
+            const int64_t f1 = std::min(n, f0 + B);
             std::fill(cnt_len.begin(), cnt_len.end(), 0);
             for (int64_t i = f0; i < f1; i++) cnt_len[(size_t)(mx - (off[(size_t)i + 1] - off[(size_t)i]))]++;
             int64_t pos = f0;
@@ -1357,6 +1359,51 @@ int tvs_initial_fbp_noalloc(tvs_ctx *ctx, const tvs_fbp_params *p, float *out, i
         return fail(ctx, TVS_EDEVICE, std::string("initial fbp (no-alloc): ") + hipGetErrorString(e));
     reset_state(ctx);
     ctx->batch.valid = false;
+    return TVS_OK;
+}
+
+int tvs_hull_detect(tvs_ctx *ctx, const tvs_hull_params *p, uint8_t *hull, int on_device,
+                    void *stream)
+{
+    if (!ctx) return TVS_EINVAL;
+    ctx->err.clear();
+    if (!p) return fail(ctx, TVS_EINVAL, "params is NULL");
+    if (p->min_in < 0 || p->max_out < 0) return fail(ctx, TVS_EINVAL, "min_in and max_out must be >= 0");
+    if (std::isnan(p->wepl_in_mm) || std::isnan(p->wepl_out_mm))
+        return fail(ctx, TVS_EINVAL, "WEPL thresholds must not be NaN");
+    if (!ctx->loaded) return fail(ctx, TVS_ESTATE, "tvs_hull_detect before tvs_load_histories");
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    uint32_t *cnt = nullptr;
+    uint8_t *hd = nullptr;
+    int rc = dalloc(ctx, &cnt, (size_t)(2 * ctx->nvox));
+    if (!rc) rc = dalloc(ctx, &hd, (size_t)ctx->nimg);
+    if (rc) {
+        dfree(ctx, &cnt, (size_t)(2 * ctx->nvox));
+        return rc;
+    }
+    // the counting threshold -inf when space modelling is off makes every
+    // line count; min_in = 0 then accepts every voxel on that side
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * 2 * ctx->nvox, st);
+    if (e == hipSuccess)
+        e = tvs::launch_hull_counts(ctx->gd, hist_dev(ctx), ctx->nh, p->wepl_in_mm, p->wepl_out_mm,
+                                    cnt, cnt + ctx->nvox, st);
+    if (e == hipSuccess)
+        e = tvs::launch_hull_decide(ctx->gd, cnt, cnt + ctx->nvox, (uint32_t)p->min_in,
+                                    (uint32_t)p->max_out, hd, p->mask_image ? ctx->x : nullptr, st);
+    if (e == hipSuccess && p->mask_image)
+        e = hipMemcpyAsync(ctx->x0, ctx->x, sizeof(double) * ctx->nvox, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && hull)
+        e = hipMemcpyAsync(hull, hd, (size_t)ctx->nimg,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(ctx, &cnt, (size_t)(2 * ctx->nvox));
+    dfree(ctx, &hd, (size_t)ctx->nimg);
+    if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("hull: ") + hipGetErrorString(e));
+    if (p->mask_image) {
+        reset_state(ctx);
+        ctx->batch.valid = false;
+    }
     return TVS_OK;
 }
 

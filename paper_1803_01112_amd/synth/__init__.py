@@ -165,6 +165,36 @@ def generate(grid: Grid, phantom: Phantom, n_hist: int, n_angles: int, seed: int
     return out
 
 
+def line_histories(p0, p1, wepl) -> dict:
+    """Histories from explicit straight entry / exit points (mm) and WEPL:
+    zero slopes, the beam axis along each line's in-plane direction."""
+    p0 = np.asarray(p0, np.float64)
+    p1 = np.asarray(p1, np.float64)
+    d = p1[:, :2] - p0[:, :2]
+    u = d / np.linalg.norm(d, axis=1, keepdims=True)
+    z = np.zeros(len(p0))
+    h = dict(ex=p0[:, 0], ey=p0[:, 1], ez=p0[:, 2], qx=p1[:, 0], qy=p1[:, 1], qz=p1[:, 2],
+             eth=z, eps=z, qth=z, qps=z, ux=u[:, 0], uy=u[:, 1], wepl=np.asarray(wepl, np.float64))
+    return {k: np.ascontiguousarray(v, np.float32) for k in HIST_FIELDS for v in [h[k]]}
+
+
+def miss_histories(grid: Grid, radius: float, n: int, seed: int, noise_mm: float = 0.3) -> dict:
+    """Protons that pass beside a cylinder of the given radius (axis z
+    through the origin): straight lines across the grid's slab at uniform
+    angles with lateral offsets between radius + 0.5 mm and the grid's
+    corner, their WEPL only the detector noise N(0, noise_mm)."""
+    rng = np.random.default_rng(seed)
+    half = 0.5 * math.hypot(grid.nx * grid.vx, grid.ny * grid.vy)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    t = rng.uniform(radius + 0.5, max(half, radius + 1.0), n) * rng.choice([-1.0, 1.0], n)
+    v = rng.uniform(grid.oz, grid.oz + grid.nz * grid.vz, n)
+    u = np.stack([np.cos(phi), np.sin(phi)], 1)
+    c = t[:, None] * np.stack([-np.sin(phi), np.cos(phi)], 1)
+    p0 = np.concatenate([c - (half + 5.0) * u, v[:, None]], 1)
+    p1 = np.concatenate([c + (half + 5.0) * u, v[:, None]], 1)
+    return line_histories(p0, p1, rng.normal(0.0, noise_mm, n))
+
+
 # --------------------------------------------------------------------------- workloads
 @dataclass
 class Workload:

@@ -27,7 +27,7 @@ EXPORTED = ("tvs_config_default", "tvs_create", "tvs_destroy", "tvs_load_histori
             "tvs_get_batch_image", "tvs_server_config_default", "tvs_server_create",
             "tvs_server_footprint", "tvs_server_submit", "tvs_server_query", "tvs_server_wait",
             "tvs_server_get_counters", "tvs_server_destroy", "tvs_autotune", "tvs_initial_fbp",
-            "tvs_initial_fbp_noalloc")
+            "tvs_initial_fbp_noalloc", "tvs_hull_detect")
 
 
 class TvsError(RuntimeError):
@@ -81,6 +81,11 @@ class Stats(C.Structure):
                 ("k1_ms_total", C.c_double), ("k2_ms_total", C.c_double),
                 ("k_samples", C.c_int64), ("batch_ms_total", C.c_double), ("batch_cycles", C.c_int64),
                 ("batch_size", C.c_int32), ("pad", C.c_int32)]
+
+
+class HullParams(C.Structure):
+    _fields_ = [("wepl_in_mm", C.c_double), ("wepl_out_mm", C.c_double), ("min_in", C.c_int32),
+                ("max_out", C.c_int32), ("mask_image", C.c_int32), ("pad", C.c_int32)]
 
 
 class StepLog(C.Structure):
@@ -156,6 +161,8 @@ def load_library(path: str = LIB):
     L.tvs_initial_fbp_noalloc.argtypes = [C.c_void_p, P(FbpParams), C.c_void_p, C.c_int,
                                           C.c_void_p]
     L.tvs_get_step_log.argtypes = [C.c_void_p, P(StepLog), C.c_int64, P(C.c_int64)]
+    L.tvs_hull_detect.argtypes = [C.c_void_p, P(HullParams), C.c_void_p, C.c_int, C.c_void_p]
+    L.tvs_hull_detect.restype = C.c_int
     L.tvs_debug_rows.argtypes = [C.c_void_p, C.c_int64, C.c_int64, P(C.c_int64), P(C.c_int32),
                                  _FP, _FP, C.c_int64]
     L.tvs_strerror.argtypes = [C.c_int]
@@ -428,6 +435,20 @@ class Context:
         self._check(self._L.tvs_initial_fbp_noalloc(self._h, C.byref(prm), p, d, st),
                     "tvs_initial_fbp_noalloc")
         _settle(out, wait)
+        return out
+
+    def hull_detect(self, wepl_in_mm=1.0, wepl_out_mm=0.0, min_in=1, max_out=0,
+                    mask_image=False, stream=None):
+        """Hull of the object from the straight entry-exit lines of the loaded
+        histories (tvs_hull_detect): space modelling (lines of WEPL >=
+        wepl_in_mm count their voxels) and space carving (lines below
+        wepl_out_mm carve them); returns the uint8 mask (x fastest).  With
+        mask_image the context image is multiplied by it."""
+        prm = HullParams(float(wepl_in_mm), float(wepl_out_mm), int(min_in), int(max_out),
+                         int(bool(mask_image)), 0)
+        out = np.zeros(self.nvox, np.uint8)
+        self._check(self._L.tvs_hull_detect(self._h, C.byref(prm), C.c_void_p(out.ctypes.data), 0,
+                                            _stream_handle(stream)), "tvs_hull_detect")
         return out
 
     def stats(self) -> dict:

@@ -206,3 +206,24 @@ def test_short_path_has_no_interior_vertex():
     h = [0.0, 0, 0, 0.5, 0.1, 0, 0, 0, 0, 0, 1.0, 0.0]
     pts = oracle.mlp_polyline(h, 1.0)
     assert len(pts) == 2
+
+
+def test_oracle_log_against_the_math_library():
+    """The Highland factor's logarithm (written out in the oracle from the
+    atanh series) agrees with the C library's to a few ulp over the depths
+    the MLP evaluates (d / X0 from 1e-7 to 3), across the reduction's
+    boundary at sqrt(1/2) and at exact powers of two."""
+    rng = np.random.default_rng(2)
+    xs = np.concatenate([np.exp(rng.uniform(np.log(1e-7), np.log(3.0), 20000)),
+                         [0.5, 1.0, 2.0, 0.25, 2.0 ** -20],
+                         np.nextafter(math.sqrt(0.5), 0.0) * np.array([1.0, 1.0 + 1e-15]),
+                         [math.sqrt(0.5), 1.0 - 1e-15, 1.0 + 1e-15]])
+    worst = 0.0
+    for x in xs:
+        got, want = oracle.log(float(x)), math.log(float(x))
+        ulp = max(np.spacing(abs(want)), np.spacing(1e-300))
+        if want != 0.0:
+            worst = max(worst, abs(got - want) / ulp)
+        else:
+            assert got == 0.0
+    assert worst <= 4.0, worst
