@@ -51,11 +51,11 @@ def log(msg):
 
 
 def sweep_bytes(H, nnz, mode):
-    """Algorithmic HBM bytes of one sweep: path stores read 16 B per history
-    and (4 + chord bytes) per entry once; on the fly the 52-byte history
-    streams are read once (the row entries are formed on the device)."""
-    if mode == "otf":
-        return 52.0 * H
+    """Algorithmic HBM bytes of the DROP chain in one sweep: 16 B per history
+    (WEPL, ||a||^2, row offset) and (4 + chord bytes) per row entry, read
+    once.  On the fly the entries the row formation wrote (4-byte tag +
+    float32 chord) are what the chain reads; the history streams themselves
+    are 52 B per history (on_the_fly_stream_bytes)."""
     return 16.0 * H + (4.0 + CHORD_BYTES[mode]) * nnz
 
 
@@ -162,6 +162,8 @@ def run_form(tvs, torch, w, dev_hist, x0, args, mode, K, W, n_lat, check=False, 
                       gbs=b / (sweep_ms * 1e-3) / 1e9,
                       frac=b / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                       what="algorithmic bytes of one sweep over the DROP chain's device time")
+    if mode == "otf":
+        out["hbm"]["on_the_fly_stream_bytes"] = 52.0 * H
     if lat:
         out["latency_ms"] = percentiles(lat)
     if steps is not None:
@@ -487,24 +489,32 @@ def main():
     if args.path_mode == "otf":
         per_cycle["k_rows_fill_tiled"] = st["rows_ms_total"] / max(st["cycles_timed"], 1)
     dom = max(per_cycle, key=per_cycle.get)
-    if dom == "k_rows_fill_tiled":
-        launches = max(st["rows_launches"] / max(st["cycles_timed"], 1), 1)
-        per_launch = FP64_FLOPS_PER_VERTEX * vertices / launches
-        achieved = per_launch / (rows_ms * 1e-3) / 1e12
-        roof = dict(bound="alu", kernel=dom, achieved=achieved, peak=FP64_PEAK_TFLOPS,
-                    unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS, traffic=None,
-                    avg_launch_ms=rows_ms, algorithmic_per_launch=per_launch,
-                    unit_of_work=f"{FP64_FLOPS_PER_VERTEX:.0f} FP64 flops per MLP vertex, "
-                                 f"{vertices / launches:.4g} vertices per launch")
-    else:
-        per_launch = sweep_bytes(H, nnz, args.path_mode) / T
-        achieved = per_launch / (k1_ms * 1e-3) / 1e9
-        roof = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_ms=k1_ms,
-                    algorithmic_per_launch=per_launch,
-                    unit_of_work="16 B per history + (4 + chord bytes) per entry of one block")
+
+    def roofline_of(kernel):
+        if kernel == "k_rows_fill_tiled":
+            launches = max(st["rows_launches"] / max(st["cycles_timed"], 1), 1)
+            per_launch = FP64_FLOPS_PER_VERTEX * vertices / launches
+            achieved = per_launch / (rows_ms * 1e-3) / 1e12
+            r = dict(bound="alu", kernel=kernel, achieved=achieved, peak=FP64_PEAK_TFLOPS,
+                     unit="TFLOP/s", frac=achieved / FP64_PEAK_TFLOPS, traffic=None,
+                     avg_launch_ms=rows_ms, algorithmic_per_launch=per_launch,
+                     unit_of_work=f"{FP64_FLOPS_PER_VERTEX:.0f} FP64 flops per MLP vertex, "
+                                  f"{vertices / launches:.4g} vertices per launch")
+        else:
+            per_launch = sweep_bytes(H, nnz, args.path_mode) / T
+            achieved = per_launch / (k1_ms * 1e-3) / 1e9
+            r = dict(bound="hbm", kernel=kernel, achieved=achieved, peak=HBM_PEAK_GBS,
+                     unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
+                     avg_launch_ms=k1_ms, algorithmic_per_launch=per_launch,
+                     unit_of_work="16 B per history + (4 + chord bytes) per entry of one block")
+        r["traffic"] = measured_traffic(kernel, f"{w.name}/{H}/B{args.block}/{args.path_mode}")
+        return r
+
+    roof = roofline_of(dom)
     roof["per_cycle_ms"] = per_cycle
-    roof["traffic"] = measured_traffic(dom, f"{w.name}/{H}/B{args.block}/{args.path_mode}")
+    # the other kernel of the cycle (on the fly the row formation runs beside
+    # the chain on its own stream)
+    others = {k: roofline_of(k) for k in per_cycle if k != dom}
 
     forms = {}
     for form in [f for f in args.forms.split(",") if f]:
@@ -592,6 +602,7 @@ def main():
         "hbm": head["hbm"],
         "load_s": head["load_s"],
         "roofline": roof,
+        "roofline_other_kernels": others,
         "hbm_measured": hbm_measured,
         "atomic_reference": atomic_reference,
         "forms": forms,
