@@ -435,6 +435,29 @@ typedef struct {
 int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_result *out,
                  void *stream);
 
+/* Autotuning of the batched sweep's step (tvs_iterate_batch) for S settings
+ * p[0..S-1]: threads per workgroup (128, 256) x settings applied per pass
+ * through LDS (4, 8, 16), each timed on the first DROP blocks (on the fly,
+ * of the first chunk, formed for the purpose) with S images started from
+ * the initial image; keeps the fastest for the context and appends it to
+ * cache_path (reused for the same device, grid, history count, B, path mode
+ * and S).  The next tvs_iterate_batch starts its settings afresh from the
+ * initial image.  Errors as tvs_iterate_batch (settings validated the same
+ * way) and tvs_autotune. */
+typedef struct {
+    int32_t threads;         /* chosen threads per workgroup */
+    int32_t group;           /* chosen settings per LDS pass */
+    double ms_per_block;     /* its measured time per DROP block */
+    int32_t from_cache;
+    int32_t n_candidates;
+    int32_t cand_threads[8];
+    int32_t cand_group[8];
+    double cand_ms[8];       /* per block, per candidate */
+} tvs_batch_tune_result;
+
+int tvs_autotune_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, const char *cache_path,
+                       tvs_batch_tune_result *out, void *stream);
+
 /* Static description of a status code. */
 const char *tvs_strerror(int status);
 

@@ -4,9 +4,9 @@
 //
 // The S images are interleaved by voxel, x[p*S + s], so that the S values an
 // entry reads are contiguous.  The DROP sweep is the tile-wise chain of
-// drop.hip with S images at once: one workgroup per (tile, group of 8
-// settings) applies each entry of the tile's lists to its 8 settings
-// through LDS; hit counts depend only on the rows.  The TV steps of every
+// drop.hip with S images at once: one workgroup per (tile, group of up to
+// 16 settings) applies each entry of the tile's lists to the settings of its
+// group through LDS; hit counts depend only on the rows.  The TV steps of every
 // setting run in one kernel per step index n, with per-setting beta read
 // from a device table indexed by a device cycle counter, so the launches of
 // one cycle can be captured once in a hipGraph and replayed for every cycle.
@@ -156,18 +156,21 @@ unsigned elem_grid(int64_t n)
 }
 
 // ------------------------------------------------------------- DROP, S images
-constexpr int kGroup = 8;   // settings per pass through LDS
+// Settings per pass through LDS (GP: 4, 8 or 16) and threads per workgroup
+// (NT: 128 or 256) are template parameters, picked by the batch autotuner.
 
 // LDS index of (voxel word w, setting s of the group): the settings of a
 // voxel are XOR-swizzled by w so that lanes holding different voxels and the
 // same setting fall into different banks (without it every voxel's setting s
 // shares one bank pair).
-__device__ inline int sx(int w, int s) { return w * kGroup + (s ^ (w & (kGroup - 1))); }
+template <int GP>
+__device__ inline int sx(int w, int s) { return w * GP + (s ^ (w & (GP - 1))); }
 
+template <int GP>
 struct BatchLds {
-    double x[kTileWords * kGroup];
-    long long cf[kTileWords * kGroup];
-    double cb[kTileWords * kGroup];
+    double x[kTileWords * GP];
+    long long cf[kTileWords * GP];
+    double cb[kTileWords * GP];
     uint32_t hits[kTileWords];
 };
 
@@ -176,15 +179,15 @@ struct BatchLds {
 // per-entry quotient a_ij / ||a_i||^2 and the per-voxel 1 / s_j are formed
 // once and shared by the settings (a rounding apart from the single-image
 // kernel, which divides per value).
-template <typename CH>
-__global__ void __launch_bounds__(kThreads)
+template <int NT, int GP, typename CH>
+__global__ void __launch_bounds__(NT)
 k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
 {
-    __shared__ BatchLds L;
+    __shared__ BatchLds<GP> L;
     const int t = threadIdx.x;
     if (A.zero)
-        for (int64_t q = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kThreads + t;
-             q < A.B * S; q += (int64_t)gridDim.x * gridDim.y * kThreads)
+        for (int64_t q = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * NT + t;
+             q < A.B * S; q += (int64_t)gridDim.x * gridDim.y * NT)
             A.zero[q] = 0;
     const int64_t T = A.tiles ? (int64_t)A.tiles[blockIdx.x] : (int64_t)blockIdx.x;
     int64_t p0 = 0, p1 = 0, c0 = 0, c1 = 0;
@@ -217,20 +220,20 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
     }
     // one group of settings per workgroup (the grid's second dimension)
     {
-        const int g0 = (int)blockIdx.y * kGroup;
-        const int G = (S - g0 < kGroup) ? S - g0 : kGroup;
-        for (int i = t; i < kTileWords * G; i += kThreads) {
+        const int g0 = (int)blockIdx.y * GP;
+        const int G = (S - g0 < GP) ? S - g0 : GP;
+        for (int i = t; i < kTileWords * G; i += NT) {
             const int w = i / G, s = i - w * G;
-            L.x[sx(w, s)] = xt[(int64_t)w * S + g0 + s];
+            L.x[sx<GP>(w, s)] = xt[(int64_t)w * S + g0 + s];
         }
         if (p1 > p0) {
-            for (int i = t; i < kTileWords * kGroup; i += kThreads) {
+            for (int i = t; i < kTileWords * GP; i += NT) {
                 L.cf[i] = 0;
                 L.cb[i] = 0.0;
             }
-            for (int w = t; w < kTileWords; w += kThreads) L.hits[w] = 0u;
+            for (int w = t; w < kTileWords; w += NT) L.hits[w] = 0u;
             __syncthreads();
-            for (int64_t e = p0 + t; e < p1; e += kThreads) {
+            for (int64_t e = p0 + t; e < p1; e += NT) {
                 const bool first = e == p0 + t;
                 const uint32_t m = first ? pm : A.P.meta[e - A.P.base];
                 const int w = (int)(m & (kTileWords - 1));
@@ -248,19 +251,19 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
                     const double res = wp - (double)A.P.dot[(int64_t)q * S + g0 + s] * kDotUnit;
                     const double v = res * an2;
                     if (fabs(v) <= A.big)
-                        atomicAdd(reinterpret_cast<unsigned long long *>(&L.cf[sx(w, s)]),
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&L.cf[sx<GP>(w, s)]),
                                   (unsigned long long)__double2ll_rn(v * kCorrScale));
                     else
-                        atomicAdd(&L.cb[sx(w, s)], v);
+                        atomicAdd(&L.cb[sx<GP>(w, s)], v);
                 }
             }
             __syncthreads();
-            for (int w = t; w < kTileWords; w += kThreads) {
+            for (int w = t; w < kTileWords; w += NT) {
                 const uint32_t h = L.hits[w];
                 if (!h) continue;
                 const double inv_h = 1.0 / (double)h;   // one division for all settings
                 for (int s = 0; s < G; s++) {
-                    const int k = sx(w, s);
+                    const int k = sx<GP>(w, s);
                     const double c = (double)L.cf[k] * kCorrUnit + L.cb[k];
                     const double nx = L.x[k] + lambda[g0 + s] * c * inv_h;
                     L.x[k] = nx;
@@ -271,12 +274,12 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
         __syncthreads();
         // every thread runs the same rounds and settings (the shuffles are
         // uniform).  The run sums of the group's settings are staged in LDS
-        // (in the finish sums' space, free by now) and leave as atomics of 8
-        // settings of one row each: one 64-byte line per run instead of 8.
+        // (in the finish sums' space, free by now) and leave as atomics of GP
+        // settings of one row each: one line per run instead of GP.
         const int wave = t >> 6, lane = t & 63;
-        long long *stg_v = reinterpret_cast<long long *>(L.cb) + wave * 64 * kGroup;
+        long long *stg_v = reinterpret_cast<long long *>(L.cb) + wave * 64 * GP;
         uint32_t *stg_q = L.hits + wave * 64;
-        for (int64_t r0 = c0; r0 < c1; r0 += kThreads) {
+        for (int64_t r0 = c0; r0 < c1; r0 += NT) {
             const int64_t e = r0 + t;
             uint32_t q = kNoRow;
             int w = 0;
@@ -299,23 +302,23 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
             for (int s = 0; s < G; s++) {
                 long long f = 0;
                 if (q != kNoRow) {
-                    const double p = a * L.x[sx(w, s)];
+                    const double p = a * L.x[sx<GP>(w, s)];
                     if (fabs(p) <= A.dot_max) f = __double2ll_rn(p * kDotScale);
                     else atomicOr(A.err, 1u);
                 }
                 f = dev::run_sum(f, runs);
-                if (emit) stg_v[k * kGroup + s] = f;
+                if (emit) stg_v[k * GP + s] = f;
             }
             if (emit) stg_q[k] = q;
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             const int n = __popcll(tails);
-            for (int b = 0; b < n; b += 64 / kGroup) {
-                const int j = b + (lane >> 3), s = lane & (kGroup - 1);
+            for (int b = 0; b < n; b += 64 / GP) {
+                const int j = b + lane / GP, s = lane & (GP - 1);
                 if (j < n && s < G)
                     atomicAdd(reinterpret_cast<unsigned long long *>(A.C.dot + (int64_t)stg_q[j] * S +
                                                                      g0 + s),
-                              (unsigned long long)stg_v[j * kGroup + s]);
+                              (unsigned long long)stg_v[j * GP + s]);
             }
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -381,22 +384,44 @@ hipError_t launch_extract(const GridDev &g, const BatchBuffers &b, int s, float 
     return hipGetLastError();
 }
 
-hipError_t launch_drop_tiles_batch(const DropTileArgs &a, const BatchBuffers &b, int64_t ntiles,
-                                   hipStream_t stream)
+namespace {
+
+template <int NT, int GP>
+hipError_t drop_batch(const DropTileArgs &a, const BatchBuffers &b, hipStream_t stream)
 {
-    if (ntiles <= 0 || (!a.P.valid && !a.C.valid)) return hipSuccess;
     const TileBlock &v = a.P.valid ? a.P : a.C;
-    const dim3 grid((unsigned)(a.tiles ? a.nact : ntiles), (unsigned)((b.S + kGroup - 1) / kGroup));
+    const dim3 grid((unsigned)a.nact, (unsigned)((b.S + GP - 1) / GP));
     if (v.chq)
-        hipLaunchKernelGGL(k_drop_tile_batch<uint16_t>, grid, dim3(kThreads), 0, stream, a, b.S,
-                           (const double *)b.lambda);
+        hipLaunchKernelGGL((k_drop_tile_batch<NT, GP, uint16_t>), grid, dim3(NT), 0, stream, a,
+                           b.S, (const double *)b.lambda);
     else if (v.ch16)
-        hipLaunchKernelGGL(k_drop_tile_batch<__half>, grid, dim3(kThreads), 0, stream, a, b.S,
+        hipLaunchKernelGGL((k_drop_tile_batch<NT, GP, __half>), grid, dim3(NT), 0, stream, a, b.S,
                            (const double *)b.lambda);
     else
-        hipLaunchKernelGGL(k_drop_tile_batch<float>, grid, dim3(kThreads), 0, stream, a, b.S,
+        hipLaunchKernelGGL((k_drop_tile_batch<NT, GP, float>), grid, dim3(NT), 0, stream, a, b.S,
                            (const double *)b.lambda);
     return hipGetLastError();
+}
+
+}  // namespace
+
+bool batch_shape_ok(int threads, int group)
+{
+    return (threads == 128 || threads == 256) && (group == 4 || group == 8 || group == 16);
+}
+
+hipError_t launch_drop_tiles_batch(const DropTileArgs &a, const BatchBuffers &b, int64_t ntiles,
+                                   int threads, int group, hipStream_t stream)
+{
+    if (ntiles <= 0 || (!a.P.valid && !a.C.valid) || !a.tiles || a.nact <= 0) return hipSuccess;
+    if (threads == 128) {
+        if (group == 4) return drop_batch<128, 4>(a, b, stream);
+        if (group == 16) return drop_batch<128, 16>(a, b, stream);
+        return drop_batch<128, 8>(a, b, stream);
+    }
+    if (group == 4) return drop_batch<256, 4>(a, b, stream);
+    if (group == 16) return drop_batch<256, 16>(a, b, stream);
+    return drop_batch<256, 8>(a, b, stream);
 }
 
 }  // namespace tvs

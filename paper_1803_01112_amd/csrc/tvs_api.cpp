@@ -174,6 +174,8 @@ struct tvs_ctx {
     double big = 0.0, dot_max = 0.0;  // fixed-point ranges of the DROP kernels
     int threads = 256;              // threads per tile workgroup
     int split = 0;                  // 1: two launches per block
+    int bthreads = 256;             // batched DROP step: threads per workgroup
+    int bgroup = 8;                 // batched DROP step: settings per pass through LDS
     int64_t fill_wgs = 0;           // grid cap of the sweep's row formation (0: none)
 
     // cycle state
@@ -1756,7 +1758,7 @@ int batch_cycle(tvs_ctx *ctx, int nmax, hipStream_t st)
         A.err = ctx->flags + kFlagRange;
         A.tiles = ctx->act;
         A.nact = ctx->nact;
-        HIPCHK(tvs::launch_drop_tiles_batch(A, Bt.b, ctx->ntiles, st));
+        HIPCHK(tvs::launch_drop_tiles_batch(A, Bt.b, ctx->ntiles, ctx->bthreads, ctx->bgroup, st));
     }
     HIPCHK(tvs::launch_tick(Bt.b.cyc, st));
     return TVS_OK;
@@ -2000,6 +2002,151 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
         if (FILE *f = std::fopen(cache_path, "a")) {
             std::fprintf(f, "%s %d %d %.6f\n", key, out->tile_threads, out->sweep_kernel,
                          out->ms_per_block);
+            std::fclose(f);
+        }
+    }
+    return TVS_OK;
+}
+
+int tvs_autotune_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, const char *cache_path,
+                       tvs_batch_tune_result *out, void *stream)
+{
+    if (!ctx || !out) return TVS_EINVAL;
+    ctx->err.clear();
+    std::memset(out, 0, sizeof(*out));
+    if (S < 1 || S > 32) return fail(ctx, TVS_EINVAL, "batch size must lie in [1, 32]");
+    if (!p) return fail(ctx, TVS_EINVAL, "params is NULL");
+    for (int q = 0; q < S; q++) {
+        int rc = validate_params(ctx, p + q);
+        if (rc) return rc;
+    }
+    if (!ctx->loaded) return fail(ctx, TVS_ESTATE, "tvs_autotune_batch before tvs_load_histories");
+    HIPCHK(hipSetDevice(ctx->cfg.device));
+    hipStream_t st = pick(ctx, stream);
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, ctx->cfg.device));
+    char key[512];
+    std::snprintf(key, sizeof(key), "%s|%dx%dx%d|%.6gx%.6gx%.6g|H%lld|B%d|P%d|S%d", prop.gcnArchName,
+                  ctx->grid.nx, ctx->grid.ny, ctx->grid.nz, ctx->grid.vx, ctx->grid.vy,
+                  ctx->grid.vz, (long long)ctx->nh, ctx->cfg.block_size, ctx->cfg.path_mode, S);
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char line[1024];
+            while (std::fgets(line, sizeof(line), f)) {
+                char k[512];
+                int th = 0, gp = 0;
+                double ms = 0;
+                if (std::sscanf(line, "%511s %d %d %lf", k, &th, &gp, &ms) == 4 &&
+                    std::strcmp(k, key) == 0 && tvs::batch_shape_ok(th, gp)) {
+                    out->threads = th;
+                    out->group = gp;
+                    out->ms_per_block = ms;
+                    out->from_cache = 1;
+                }
+            }
+            std::fclose(f);
+        }
+        if (out->from_cache) {
+            ctx->bthreads = out->threads;
+            ctx->bgroup = out->group;
+            return TVS_OK;
+        }
+    }
+    const int64_t B = ctx->cfg.block_size;
+    const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
+    // the first blocks of the first chunk (formed here on the fly)
+    int64_t nb = std::min<int64_t>(ctx->nblocks, 48);
+    if (otf) nb = std::min<int64_t>(nb, ctx->chunk / B);
+    if (nb == 0) {
+        out->threads = ctx->bthreads;
+        out->group = ctx->bgroup;
+        return TVS_OK;
+    }
+    HIPCHK(hipStreamSynchronize(ctx->fill_stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    int rc = batch_init(ctx, p, S, st);
+    if (rc) return rc;
+    auto &Bt = ctx->batch;
+    if (otf) {
+        for (int q = 0; q < kChunkBuffers; q++) HIPCHK(hipStreamWaitEvent(st, ctx->ev_free[q], 0));
+        tvs::TileFill f = chunk_fill(ctx, 0, std::min(ctx->chunk, ctx->nh));
+        f.max_wgs = 0;
+        HIPCHK(tvs::launch_rows_fill_tiled(ctx->gd, hist_dev(ctx), ctx->mlp, f, st));
+        HIPCHK(hipEventRecord(ctx->ev_free[chunk_buffer(ctx, 0)], st));
+    }
+    const int ths[2] = {128, 256}, gps[3] = {4, 8, 16};
+    const int old_t = ctx->bthreads, old_g = ctx->bgroup;
+    double best = 1e300;
+    int nc = 0;
+    for (int ti = 0; ti < 2 && rc == TVS_OK; ti++) {
+        for (int gi = 0; gi < 3 && rc == TVS_OK; gi++) {
+            ctx->bthreads = ths[ti];
+            ctx->bgroup = gps[gi];
+            double tbest = 1e300;
+            for (int rep = 0; rep < 3 && rc == TVS_OK; rep++) {
+                ctx->tev_used = 0;
+                ctx->spans.clear();
+                hipError_t e = tvs::launch_zero_i64(Bt.dot, 3 * B * S, st);
+                long a = mark(ctx, st);
+                for (int64_t b = 0; b <= nb && e == hipSuccess; b++) {
+                    tvs::DropTileArgs A;
+                    if (b > 0) A.P = block_view(ctx, b - 1, Bt.dot, B * S);
+                    if (b < nb) A.C = block_view(ctx, b, Bt.dot, B * S);
+                    A.x = Bt.b.x;
+                    A.big = ctx->big;
+                    A.dot_max = ctx->dot_max;
+                    A.zero = Bt.dot + ((b + 1) % 3) * B * S;
+                    A.B = B;
+                    A.err = ctx->flags + kFlagRange;
+                    A.tiles = ctx->act;
+                    A.nact = ctx->nact;
+                    e = tvs::launch_drop_tiles_batch(A, Bt.b, ctx->ntiles, ctx->bthreads,
+                                                     ctx->bgroup, st);
+                }
+                long bm = mark(ctx, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                float ms = 0;
+                if (e == hipSuccess && a >= 0 && bm >= 0)
+                    e = hipEventElapsedTime(&ms, ctx->tev[(size_t)a], ctx->tev[(size_t)bm]);
+                if (e != hipSuccess) {
+                    rc = fail(ctx, TVS_EDEVICE, std::string("batch autotune: ") + hipGetErrorString(e));
+                    break;
+                }
+                if (rep > 0) tbest = std::min(tbest, (double)ms / (double)nb);   // rep 0 warms up
+            }
+            if (rc) break;
+            if (nc < 8) {
+                out->cand_threads[nc] = ths[ti];
+                out->cand_group[nc] = gps[gi];
+                out->cand_ms[nc] = tbest;
+                nc++;
+            }
+            if (tbest < best) {
+                best = tbest;
+                out->threads = ths[ti];
+                out->group = gps[gi];
+                out->ms_per_block = tbest;
+            }
+        }
+    }
+    ctx->tev_used = 0;
+    ctx->spans.clear();
+    ctx->timed = false;
+    out->n_candidates = nc;
+    // the timed steps moved the batch images: the next batch starts afresh
+    Bt.valid = false;
+    if (rc || best == 1e300) {
+        ctx->bthreads = old_t;
+        ctx->bgroup = old_g;
+        return rc ? rc : fail(ctx, TVS_EDEVICE, "batch autotune: no candidate ran");
+    }
+    ctx->bthreads = out->threads;
+    ctx->bgroup = out->group;
+    rc = check_flags(ctx, st);
+    if (rc) return rc;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s %d %d %.6f\n", key, out->threads, out->group, out->ms_per_block);
             std::fclose(f);
         }
     }

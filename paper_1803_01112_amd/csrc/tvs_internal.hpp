@@ -348,6 +348,9 @@ hipError_t launch_extract(const GridDev &g, const BatchBuffers &b, int s, float 
 // values, row-major by row; a.lambda is unused, the per-setting relaxations
 // come from b.lambda).
 hipError_t launch_drop_tiles_batch(const DropTileArgs &a, const BatchBuffers &b, int64_t ntiles,
-                                   hipStream_t stream);
+                                   int threads, int group, hipStream_t stream);
+// threads (128, 256) and settings per LDS pass (4, 8, 16) the batched step
+// is built for.
+bool batch_shape_ok(int threads, int group);
 
 }  // namespace tvs

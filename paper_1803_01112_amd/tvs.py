@@ -27,7 +27,8 @@ EXPORTED = ("tvs_config_default", "tvs_create", "tvs_destroy", "tvs_load_histori
             "tvs_get_batch_image", "tvs_server_config_default", "tvs_server_create",
             "tvs_server_footprint", "tvs_server_submit", "tvs_server_query", "tvs_server_wait",
             "tvs_server_get_counters", "tvs_server_destroy", "tvs_autotune", "tvs_initial_fbp",
-            "tvs_initial_fbp_noalloc", "tvs_hull_detect")
+            "tvs_initial_fbp_noalloc", "tvs_hull_detect",
+            "tvs_autotune_batch")
 
 
 class TvsError(RuntimeError):
@@ -81,6 +82,13 @@ class Stats(C.Structure):
                 ("k1_ms_total", C.c_double), ("k2_ms_total", C.c_double),
                 ("k_samples", C.c_int64), ("batch_ms_total", C.c_double), ("batch_cycles", C.c_int64),
                 ("batch_size", C.c_int32), ("pad", C.c_int32)]
+
+
+class BatchTuneResult(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("group", C.c_int32), ("ms_per_block", C.c_double),
+                ("from_cache", C.c_int32), ("n_candidates", C.c_int32),
+                ("cand_threads", C.c_int32 * 8), ("cand_group", C.c_int32 * 8),
+                ("cand_ms", C.c_double * 8)]
 
 
 class HullParams(C.Structure):
@@ -171,6 +179,9 @@ def load_library(path: str = LIB):
     L.tvs_last_error.restype = C.c_char_p
     L.tvs_autotune.argtypes = [C.c_void_p, C.c_double, C.c_char_p, P(TuneResult), C.c_void_p]
     L.tvs_autotune.restype = C.c_int
+    L.tvs_autotune_batch.argtypes = [C.c_void_p, P(Params), C.c_int32, C.c_char_p,
+                                     P(BatchTuneResult), C.c_void_p]
+    L.tvs_autotune_batch.restype = C.c_int
     L.tvs_server_config_default.argtypes = [P(ServerConfig)]
     L.tvs_server_config_default.restype = None
     L.tvs_server_create.argtypes = [P(ServerConfig), P(C.c_void_p)]
@@ -366,9 +377,8 @@ class Context:
         self._check(self._L.tvs_iterate(self._h, C.byref(p), int(K), _stream_handle(stream)),
                     "tvs_iterate")
 
-    def iterate_batch(self, K, settings, stream=None):
-        """K cycles of S settings together; settings: list of dicts with keys
-        lam, N, alpha and optionally variant, tv_eps, seed, gamma."""
+    @staticmethod
+    def _settings(settings):
         S = len(settings)
         arr = (Params * max(S, 1))()
         for q, st in enumerate(settings):
@@ -377,8 +387,27 @@ class Context:
             arr[q] = Params(float(st["lam"]), int(st["N"]), float(st["alpha"]),
                             int(bool(st.get("tv_check", False))), v, float(st.get("tv_eps", 0.0)),
                             int(st.get("seed", 0)) & (2**64 - 1), float(st.get("gamma", 0.5)))
+        return S, arr
+
+    def iterate_batch(self, K, settings, stream=None):
+        """K cycles of S settings together; settings: list of dicts with keys
+        lam, N, alpha and optionally variant, tv_eps, seed, gamma."""
+        S, arr = self._settings(settings)
         self._check(self._L.tvs_iterate_batch(self._h, arr, S, int(K), _stream_handle(stream)),
                     "tvs_iterate_batch")
+
+    def autotune_batch(self, settings, cache_path=None, stream=None):
+        """Times the batched step's shapes (threads x settings per LDS pass)
+        for these settings and keeps the fastest; returns a dict."""
+        S, arr = self._settings(settings)
+        r = BatchTuneResult()
+        cp = cache_path.encode() if cache_path else None
+        self._check(self._L.tvs_autotune_batch(self._h, arr, S, cp, C.byref(r),
+                                               _stream_handle(stream)), "tvs_autotune_batch")
+        return dict(threads=r.threads, group=r.group, ms_per_block=r.ms_per_block,
+                    from_cache=bool(r.from_cache),
+                    candidates=[dict(threads=r.cand_threads[q], group=r.cand_group[q],
+                                     ms=r.cand_ms[q]) for q in range(r.n_candidates)])
 
     def autotune(self, lam=1e-4, cache_path=None, stream=None):
         """Times the launch-shape candidates and keeps the fastest; returns a dict."""

@@ -97,3 +97,48 @@ def test_batch_rejects_bad_settings(slice64):
         with pytest.raises(tvs.TvsError) as e:
             ctx.get_batch_image(2)
         assert e.value.status == tvs.TVS_ERANGE
+
+
+SHAPES = [(128, 4), (128, 8), (128, 16), (256, 4), (256, 8), (256, 16)]
+
+
+@pytest.mark.parametrize("path_mode,S", [("otf", 6), ("f32", 20)])
+def test_batch_autotune_and_every_shape(slice64, tmp_path, path_mode, S):
+    """The batch tuner times every (threads, settings per LDS pass) shape and
+    keeps one it measured; a cached entry is reused; every shape (forced
+    through the cache, whose last matching line wins) gives the images of the
+    default shape, with S below, at and above a group's size."""
+    w, h, rows = slice64
+    x0 = w.initial_image()
+    rng = np.random.default_rng(S)
+    sets = [dict(lam=float(rng.choice([0.02, 0.05])), N=int(rng.choice([1, 3, 6])),
+                 alpha=float(rng.choice([0.5, 0.75, 0.95])), seed=200 + q) for q in range(S)]
+    cache = str(tmp_path / "batch_tune.txt")
+    with tvs.Context(w.grid, block_size=64, mlp_step_mm=2.0, path_mode=path_mode,
+                     chunk_histories=6400) as ctx:
+        ctx.load_histories(h)
+        ctx.set_image(x0)
+        ctx.iterate_batch(2, sets)
+        ref = [ctx.get_batch_image(q).astype(np.float64) for q in range(S)]
+        r = ctx.autotune_batch(sets, cache)
+        assert not r["from_cache"] and len(r["candidates"]) == len(SHAPES)
+        assert {(c["threads"], c["group"]) for c in r["candidates"]} == set(SHAPES)
+        assert all(c["ms"] > 0 for c in r["candidates"])
+        assert (r["threads"], r["group"]) in SHAPES
+        assert r["ms_per_block"] == min(c["ms"] for c in r["candidates"])
+        r2 = ctx.autotune_batch(sets, cache)
+        assert r2["from_cache"] and (r2["threads"], r2["group"]) == (r["threads"], r["group"])
+        key = open(cache).read().split()[0]
+        for th, gp in SHAPES:
+            with open(cache, "a") as f:
+                f.write(f"{key} {th} {gp} 0.0\n")
+            r3 = ctx.autotune_batch(sets, cache)
+            assert r3["from_cache"] and (r3["threads"], r3["group"]) == (th, gp)
+            ctx.set_image(x0)
+            ctx.iterate_batch(2, sets)
+            for q in range(S):
+                assert rel_err(ctx.get_batch_image(q), ref[q]) <= 1e-5, (th, gp, q)
+    st = sets[S - 1]
+    O = oracle.Superiorizer(w.grid, rows, x0, 64)
+    O.iterate(2, st["lam"], st["N"], st["alpha"], seed=st["seed"])
+    assert rel_err(ref[S - 1], O.x) <= TOL
