@@ -279,6 +279,8 @@ def run_batch(tvs, torch, args):
     ctx.iterate(1, **kw)
     dt1 = timed_cycles(torch, ctx, args.batch_steps, kw) / args.batch_steps
     ctx.set_image(x0)
+    tune = ctx.autotune_batch(sets)                # threads x settings per LDS pass
+    log(f"batch shape: {tune['threads']} threads, {tune['group']} settings per pass")
     ctx.iterate_batch(1, sets)                     # warm-up cycle (captures the graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -301,7 +303,11 @@ def run_batch(tvs, torch, args):
                 device_ms_per_cycle=st["batch_ms_total"] / max(st["batch_cycles"], 1),
                 latency_ms=percentiles(lat) if lat else None,
                 single_setting=dict(value=H / dt1, ms_per_cycle=1e3 * dt1, N=3, alpha=0.75),
-                speedup_vs_separate_runs=(S * dt1) / dt, path_mode=args.batch_path)
+                speedup_vs_separate_runs=(S * dt1) / dt, path_mode=args.batch_path,
+                shape=dict(threads=tune["threads"], settings_per_pass=tune["group"],
+                           ms_per_block=tune["ms_per_block"],
+                           candidates=[(c["threads"], c["group"], round(c["ms"], 5))
+                                       for c in tune["candidates"]]))
 
 
 def run_serving(tvs, args):

@@ -231,7 +231,8 @@ int tvs_get_image(tvs_ctx *ctx, float *out, int on_device, void *stream);
  * tvs_params and all starting from the image set by tvs_set_image, advanced
  * K cycles together.  Every cycle reads each row once and applies it to all
  * S images; the launches of one cycle are captured in a hipGraph and
- * replayed for every cycle.  Unchecked schedules only (TVS_NTVS with
+ * replayed for every cycle (on-the-fly rows are formed in that graph on a
+ * second stream, beside the TV steps and the DROP chain).  Unchecked schedules only (TVS_NTVS with
  * tv_check = 0, or TVS_DECOUPLED); 1 <= S <= 32; p points to S parameter
  * sets.  A call with the same S and parameters as the previous one
  * continues those reconstructions; otherwise they restart from the initial
@@ -437,7 +438,7 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
 
 /* Autotuning of the batched sweep's step (tvs_iterate_batch) for S settings
  * p[0..S-1]: threads per workgroup (128, 256) x settings applied per pass
- * through LDS (4, 8, 16), each timed on the first DROP blocks (on the fly,
+ * through LDS (2, 4, 8, 16; untuned: 256 x 4), each timed on the first DROP blocks (on the fly,
  * of the first chunk, formed for the purpose) with S images started from
  * the initial image; keeps the fastest for the context and appends it to
  * cache_path (reused for the same device, grid, history count, B, path mode

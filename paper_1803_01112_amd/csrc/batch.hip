@@ -156,7 +156,7 @@ unsigned elem_grid(int64_t n)
 }
 
 // ------------------------------------------------------------- DROP, S images
-// Settings per pass through LDS (GP: 4, 8 or 16) and threads per workgroup
+// Settings per pass through LDS (GP: 2, 4, 8 or 16) and threads per workgroup
 // (NT: 128 or 256) are template parameters, picked by the batch autotuner.
 
 // LDS index of (voxel word w, setting s of the group): the settings of a
@@ -407,7 +407,8 @@ hipError_t drop_batch(const DropTileArgs &a, const BatchBuffers &b, hipStream_t 
 
 bool batch_shape_ok(int threads, int group)
 {
-    return (threads == 128 || threads == 256) && (group == 4 || group == 8 || group == 16);
+    return (threads == 128 || threads == 256) &&
+           (group == 2 || group == 4 || group == 8 || group == 16);
 }
 
 hipError_t launch_drop_tiles_batch(const DropTileArgs &a, const BatchBuffers &b, int64_t ntiles,
@@ -415,10 +416,12 @@ hipError_t launch_drop_tiles_batch(const DropTileArgs &a, const BatchBuffers &b,
 {
     if (ntiles <= 0 || (!a.P.valid && !a.C.valid) || !a.tiles || a.nact <= 0) return hipSuccess;
     if (threads == 128) {
+        if (group == 2) return drop_batch<128, 2>(a, b, stream);
         if (group == 4) return drop_batch<128, 4>(a, b, stream);
         if (group == 16) return drop_batch<128, 16>(a, b, stream);
         return drop_batch<128, 8>(a, b, stream);
     }
+    if (group == 2) return drop_batch<256, 2>(a, b, stream);
     if (group == 4) return drop_batch<256, 4>(a, b, stream);
     if (group == 16) return drop_batch<256, 16>(a, b, stream);
     return drop_batch<256, 8>(a, b, stream);

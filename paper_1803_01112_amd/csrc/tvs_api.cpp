@@ -175,7 +175,7 @@ struct tvs_ctx {
     int threads = 256;              // threads per tile workgroup
     int split = 0;                  // 1: two launches per block
     int bthreads = 256;             // batched DROP step: threads per workgroup
-    int bgroup = 8;                 // batched DROP step: settings per pass through LDS
+    int bgroup = 4;                 // batched DROP step: settings per pass through LDS
     int64_t fill_wgs = 0;           // grid cap of the sweep's row formation (0: none)
 
     // cycle state
@@ -221,6 +221,11 @@ struct tvs_ctx {
         double ms_total = 0;
         int64_t cycles = 0;
     } batch;
+    // fork/join events of the captured batched cycle (the fill stream's row
+    // formation beside the batched chain); only ever recorded in capture
+    hipEvent_t bev_fork = nullptr;
+    hipEvent_t bev_filled[kChunkBuffers] = {};
+    hipEvent_t bev_free[kChunkBuffers] = {};
 };
 
 namespace {
@@ -935,7 +940,10 @@ void tvs_destroy(tvs_ctx *ctx)
     for (int q = 0; q < kChunkBuffers; q++) {
         if (ctx->ev_filled[q]) (void)hipEventDestroy(ctx->ev_filled[q]);
         if (ctx->ev_free[q]) (void)hipEventDestroy(ctx->ev_free[q]);
+        if (ctx->bev_filled[q]) (void)hipEventDestroy(ctx->bev_filled[q]);
+        if (ctx->bev_free[q]) (void)hipEventDestroy(ctx->bev_free[q]);
     }
+    if (ctx->bev_fork) (void)hipEventDestroy(ctx->bev_fork);
     if (ctx->fill_stream) (void)hipStreamDestroy(ctx->fill_stream);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -1041,10 +1049,16 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
     for (int q = 0; q < kChunkBuffers; q++) {
         if (hipEventCreateWithFlags(&ctx->ev_filled[q], hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&ctx->ev_free[q], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->bev_filled[q], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->bev_free[q], hipEventDisableTiming) != hipSuccess ||
             hipEventRecord(ctx->ev_free[q], ctx->stream) != hipSuccess) {
             tvs_destroy(ctx);
             return TVS_EDEVICE;
         }
+    }
+    if (hipEventCreateWithFlags(&ctx->bev_fork, hipEventDisableTiming) != hipSuccess) {
+        tvs_destroy(ctx);
+        return TVS_EDEVICE;
     }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemsetAsync(ctx->x, 0, sizeof(double) * nvox, ctx->stream);
@@ -1718,12 +1732,37 @@ int batch_init(tvs_ctx *ctx, const tvs_params *p, int S, hipStream_t st)
 
 // Enqueues the launches of one batched cycle (captured into a graph): the
 // TV steps of every setting, then the tile-wise DROP chain for all S
-// images; on-the-fly rows are formed chunk by chunk on the same stream
-// into alternating buffers.
+// images.  On the fly, the fill stream joins the capture and forms the
+// rows chunk by chunk into the ring of buffers beside the TV steps and the
+// chain, with the single-image sweep's filled/free ordering (events of the
+// batch's own, so the sweep's events keep their real records); the chain
+// waits for the last chunk, which joins the fill stream back.
 int batch_cycle(tvs_ctx *ctx, int nmax, hipStream_t st)
 {
     auto &Bt = ctx->batch;
     const int S = Bt.S;
+    const int64_t B = ctx->cfg.block_size, nb = ctx->nblocks;
+    const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
+    const int64_t step = otf ? ctx->chunk : ctx->nh;
+    const int64_t nchunks = nb > 0 ? (ctx->nh + step - 1) / step : 0;
+    const int64_t NB = ctx->nbuf;
+    hipStream_t fs = ctx->fill_stream;
+    auto fill = [&](int64_t c) -> int {
+        const int q = chunk_buffer(ctx, c);
+        if (c >= NB) HIPCHK(hipStreamWaitEvent(fs, ctx->bev_free[q], 0));
+        tvs::TileFill f = chunk_fill(ctx, c, std::min(step, ctx->nh - c * step));
+        HIPCHK(tvs::launch_rows_fill_tiled(ctx->gd, hist_dev(ctx), ctx->mlp, f, fs));
+        HIPCHK(hipEventRecord(ctx->bev_filled[q], fs));
+        return TVS_OK;
+    };
+    if (otf && nchunks > 0) {
+        HIPCHK(hipEventRecord(ctx->bev_fork, st));
+        HIPCHK(hipStreamWaitEvent(fs, ctx->bev_fork, 0));
+        for (int64_t c = 0; c < std::min<int64_t>(NB, nchunks); c++) {
+            int rc = fill(c);
+            if (rc) return rc;
+        }
+    }
     for (int n = 0; n < nmax; n++) {
         uint32_t active = 0;
         for (int q = 0; q < S; q++)
@@ -1731,22 +1770,17 @@ int batch_cycle(tvs_ctx *ctx, int nmax, hipStream_t st)
         HIPCHK(tvs::launch_tvb_grad(ctx->gd, Bt.b, active, st));
         HIPCHK(tvs::launch_tvb_step(Bt.b, active, n, nmax, st));
     }
-    const int64_t B = ctx->cfg.block_size, nb = ctx->nblocks;
     if (nb == 0) {
         HIPCHK(tvs::launch_tick(Bt.b.cyc, st));
         return TVS_OK;
     }
-    const bool otf = ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY;
-    const int64_t step = otf ? ctx->chunk : ctx->nh;
     HIPCHK(tvs::launch_zero_i64(Bt.dot, 3 * B * S, st));
     for (int64_t b = 0; b <= nb; b++) {
         const bool has_c = b < nb;
-        if (otf && has_c && (b * B) % step == 0) {
-            const int64_t c = (b * B) / step;
-            tvs::TileFill f = chunk_fill(ctx, c, std::min(step, ctx->nh - c * step));
-            f.max_wgs = 0;   // in line with the chain here: the whole device
-            HIPCHK(tvs::launch_rows_fill_tiled(ctx->gd, hist_dev(ctx), ctx->mlp, f, st));
-        }
+        const int64_t c = has_c ? (b * B) / step : -1;
+        const bool first_of_chunk = has_c && (b * B) % step == 0;
+        if (otf && first_of_chunk)
+            HIPCHK(hipStreamWaitEvent(st, ctx->bev_filled[chunk_buffer(ctx, c)], 0));
         tvs::DropTileArgs A;
         if (b > 0) A.P = block_view(ctx, b - 1, Bt.dot, B * S);
         if (has_c) A.C = block_view(ctx, b, Bt.dot, B * S);
@@ -1759,6 +1793,12 @@ int batch_cycle(tvs_ctx *ctx, int nmax, hipStream_t st)
         A.tiles = ctx->act;
         A.nact = ctx->nact;
         HIPCHK(tvs::launch_drop_tiles_batch(A, Bt.b, ctx->ntiles, ctx->bthreads, ctx->bgroup, st));
+        if (otf && first_of_chunk && c >= 1 && c - 1 + NB < nchunks) {
+            // the launch above was the last to read chunk c - 1's buffer
+            HIPCHK(hipEventRecord(ctx->bev_free[chunk_buffer(ctx, c - 1)], st));
+            int rc = fill(c - 1 + NB);
+            if (rc) return rc;
+        }
     }
     HIPCHK(tvs::launch_tick(Bt.b.cyc, st));
     return TVS_OK;
@@ -2074,12 +2114,12 @@ int tvs_autotune_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, const char 
         HIPCHK(tvs::launch_rows_fill_tiled(ctx->gd, hist_dev(ctx), ctx->mlp, f, st));
         HIPCHK(hipEventRecord(ctx->ev_free[chunk_buffer(ctx, 0)], st));
     }
-    const int ths[2] = {128, 256}, gps[3] = {4, 8, 16};
+    const int ths[2] = {128, 256}, gps[4] = {2, 4, 8, 16};
     const int old_t = ctx->bthreads, old_g = ctx->bgroup;
     double best = 1e300;
     int nc = 0;
     for (int ti = 0; ti < 2 && rc == TVS_OK; ti++) {
-        for (int gi = 0; gi < 3 && rc == TVS_OK; gi++) {
+        for (int gi = 0; gi < 4 && rc == TVS_OK; gi++) {
             ctx->bthreads = ths[ti];
             ctx->bgroup = gps[gi];
             double tbest = 1e300;

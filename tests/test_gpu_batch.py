@@ -99,7 +99,7 @@ def test_batch_rejects_bad_settings(slice64):
         assert e.value.status == tvs.TVS_ERANGE
 
 
-SHAPES = [(128, 4), (128, 8), (128, 16), (256, 4), (256, 8), (256, 16)]
+SHAPES = [(t, g) for t in (128, 256) for g in (2, 4, 8, 16)]
 
 
 @pytest.mark.parametrize("path_mode,S", [("otf", 6), ("f32", 20)])
