@@ -189,15 +189,16 @@ k_drop_tile_batch(DropTileArgs A, int S, const double *lambda)
         for (int64_t q = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * NT + t;
              q < A.B * S; q += (int64_t)gridDim.x * gridDim.y * NT)
             A.zero[q] = 0;
-    const int64_t T = A.tiles ? (int64_t)A.tiles[blockIdx.x] : (int64_t)blockIdx.x;
+    // workgroup x takes dispatch slot x: its lists' bounds at [x], its tile act[x]
+    const int64_t T = A.tiles[blockIdx.x];
     int64_t p0 = 0, p1 = 0, c0 = 0, c1 = 0;
     if (A.P.valid) {
-        p0 = A.P.toff[T];
-        p1 = A.P.toff[T + 1];
+        p0 = A.P.toff[blockIdx.x];
+        p1 = A.P.toff[blockIdx.x + 1];
     }
     if (A.C.valid) {
-        c0 = A.C.toff[T];
-        c1 = A.C.toff[T + 1];
+        c0 = A.C.toff[blockIdx.x];
+        c1 = A.C.toff[blockIdx.x + 1];
     }
     if (p0 == p1 && c0 == c1) return;
     double *xt = A.x + (T << kTileShift) * S;

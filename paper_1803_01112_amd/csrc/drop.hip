@@ -183,12 +183,14 @@ __device__ inline void clear_next(const DropTileArgs &A, int nt)
         A.zero[q] = 0;
 }
 
-__device__ inline void list_range(const TileBlock &t, int64_t T, int64_t &a, int64_t &b)
+// List bounds of dispatch slot i (lists are laid out in slot order, so the
+// bounds do not wait for the slot's tile to be looked up).
+__device__ inline void list_range(const TileBlock &t, int64_t i, int64_t &a, int64_t &b)
 {
     a = b = 0;
     if (t.valid) {
-        a = t.toff[T];
-        b = t.toff[T + 1];
+        a = t.toff[i];
+        b = t.toff[i + 1];
     }
 }
 
@@ -226,10 +228,10 @@ __global__ void __launch_bounds__(NT) k_drop_tile(DropTileArgs A)
 {
     __shared__ TileLds L;
     chain_priority();
-    const int64_t T = A.tiles ? (int64_t)A.tiles[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t T = A.tiles[blockIdx.x];
     int64_t p0, p1, c0, c1;
-    list_range(A.P, T, p0, p1);
-    list_range(A.C, T, c0, c1);
+    list_range(A.P, blockIdx.x, p0, p1);
+    list_range(A.C, blockIdx.x, c0, c1);
     clear_next(A, NT);
     if (p0 == p1 && c0 == c1) return;
     double *xt = A.x + (T << kTileShift);
@@ -248,9 +250,9 @@ __global__ void __launch_bounds__(NT) k_drop_tile_finish(DropTileArgs A)
 {
     __shared__ TileLds L;
     chain_priority();
-    const int64_t T = A.tiles ? (int64_t)A.tiles[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t T = A.tiles[blockIdx.x];
     int64_t p0, p1;
-    list_range(A.P, T, p0, p1);
+    list_range(A.P, blockIdx.x, p0, p1);
     if (p0 == p1) return;
     double *xt = A.x + (T << kTileShift);
     const Ent pe = load_ent<CH>(A.P, p0 + threadIdx.x, p1);
@@ -266,9 +268,9 @@ __global__ void __launch_bounds__(NT) k_drop_tile_dots(DropTileArgs A)
 {
     __shared__ TileLds L;
     chain_priority();
-    const int64_t T = A.tiles ? (int64_t)A.tiles[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t T = A.tiles[blockIdx.x];
     int64_t c0, c1;
-    list_range(A.C, T, c0, c1);
+    list_range(A.C, blockIdx.x, c0, c1);
     clear_next(A, NT);
     if (c0 == c1) return;
     const double *xt = A.x + (T << kTileShift);
@@ -279,17 +281,28 @@ __global__ void __launch_bounds__(NT) k_drop_tile_dots(DropTileArgs A)
 }
 
 // One lane per tile, walking the blocks (lanes of neighbouring tiles read
-// neighbouring list starts): the tile's entries over all blocks, saturated
+// neighbouring counts): the tile's list entries over all blocks, saturated
 // at 2^32 - 1.
-__global__ void __launch_bounds__(256) k_tile_active(const int64_t *bt_off, int64_t nblocks,
+__global__ void __launch_bounds__(256) k_tile_totals(const uint32_t *cnt, int64_t nblocks,
                                                      int64_t ntiles, uint32_t *total)
 {
     const int64_t T = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (T >= ntiles) return;
     uint64_t tot = 0;
-    for (int64_t b = 0; b < nblocks; b++)
-        tot += (uint64_t)(bt_off[b * ntiles + T + 1] - bt_off[b * ntiles + T]);
+    for (int64_t b = 0; b < nblocks; b++) tot += cnt[b * ntiles + T];
     total[T] = tot > 0xffffffffull ? 0xffffffffu : (uint32_t)tot;
+}
+
+// The (block, tile) counts gathered into (block, slot) order.
+__global__ void __launch_bounds__(256) k_slot_counts(const uint32_t *cnt, const int32_t *act,
+                                                     int64_t nact, int64_t nblocks, int64_t ntiles,
+                                                     uint32_t *out)
+{
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nblocks * nact;
+         q += (int64_t)gridDim.x * 256) {
+        const int64_t b = q / nact, i = q - b * nact;
+        out[q] = cnt[b * ntiles + act[i]];
+    }
 }
 
 __global__ void __launch_bounds__(256) k_zero_i64(long long *p, int64_t n)
@@ -312,7 +325,7 @@ template <int NT, typename CH>
 hipError_t drop_tiles(const DropTileArgs &a, int64_t ntiles, int split, hipStream_t stream,
                       const KTimer &t)
 {
-    const dim3 grid((unsigned)(a.tiles ? a.nact : ntiles)), block(NT);
+    const dim3 grid((unsigned)a.nact), block(NT);
     if (!split) {
         launch(k_drop_tile<NT, CH>, grid, block, stream, t.e[0], t.e[1], a);
         return hipGetLastError();
@@ -338,7 +351,7 @@ hipError_t drop_tiles_nt(const DropTileArgs &a, int64_t ntiles, int threads, int
 hipError_t launch_drop_tiles(const DropTileArgs &a, int64_t ntiles, int threads, int split,
                              hipStream_t stream, const KTimer *kt)
 {
-    if (ntiles <= 0 || (!a.P.valid && !a.C.valid)) return hipSuccess;
+    if (ntiles <= 0 || (!a.P.valid && !a.C.valid) || !a.tiles || a.nact <= 0) return hipSuccess;
     const KTimer none{};
     const KTimer &t = kt ? *kt : none;
     const TileBlock &v = a.P.valid ? a.P : a.C;
@@ -347,12 +360,23 @@ hipError_t launch_drop_tiles(const DropTileArgs &a, int64_t ntiles, int threads,
     return drop_tiles_nt<float>(a, ntiles, threads, split, stream, t);
 }
 
-hipError_t launch_tile_active(const int64_t *bt_off, int64_t nblocks, int64_t ntiles,
+hipError_t launch_tile_totals(const uint32_t *cnt, int64_t nblocks, int64_t ntiles,
                               uint32_t *total, hipStream_t stream)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_active, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, stream,
-                       bt_off, nblocks, ntiles, total);
+    hipLaunchKernelGGL(k_tile_totals, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, stream,
+                       cnt, nblocks, ntiles, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_counts(const uint32_t *cnt, const int32_t *act, int64_t nact,
+                              int64_t nblocks, int64_t ntiles, uint32_t *out, hipStream_t stream)
+{
+    const int64_t n = nblocks * nact;
+    if (n <= 0) return hipSuccess;
+    const int64_t wgs = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_slot_counts, dim3((unsigned)wgs), dim3(256), 0, stream, cnt, act, nact,
+                       nblocks, ntiles, out);
     return hipGetLastError();
 }
 

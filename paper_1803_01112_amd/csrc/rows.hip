@@ -606,20 +606,21 @@ k_rows_seg(GridDev g, HistDev H, MlpCfg m, int64_t n, int64_t B, int64_t ntiles,
 
 __global__ void __launch_bounds__(kThreads)
 k_seg_dest(int64_t n, int64_t B, int64_t ntiles, const int64_t *seg_off, const int64_t *bt_off,
-           uint64_t *segtab, uint32_t *err)
+           const int32_t *slot_of, int64_t nslots, uint64_t *segtab, uint32_t *err)
 {
     int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
-    const int64_t *bto = bt_off + (i / B) * ntiles;
+    const int64_t *bto = bt_off + (i / B) * nslots;
     for (int64_t s = seg_off[i]; s < seg_off[i + 1]; s++) {
         const uint64_t v = segtab[s];
         const int64_t T = (int64_t)(v >> 32);
-        if (T >= ntiles) {
+        const int32_t slot = T < ntiles ? slot_of[T] : -1;
+        if (slot < 0) {
             atomicOr(err, 1u);
             segtab[s] = 0;
             continue;
         }
-        segtab[s] = (uint64_t)(bto[T] + (int64_t)(v & 0xffffffffull));
+        segtab[s] = (uint64_t)(bto[slot] + (int64_t)(v & 0xffffffffull));
     }
 }
 
@@ -845,13 +846,13 @@ hipError_t launch_rows_seg(const GridDev &g, const HistDev &h, const MlpCfg &m, 
 }
 
 hipError_t launch_seg_dest(const GridDev &g, int64_t n, int64_t B, const int64_t *seg_off,
-                           const int64_t *bt_off, uint64_t *segtab, uint32_t *err,
-                           hipStream_t stream)
+                           const int64_t *bt_off, const int32_t *slot_of, int64_t nslots,
+                           uint64_t *segtab, uint32_t *err, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
     dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
     hipLaunchKernelGGL(k_seg_dest, grid, dim3(kThreads), 0, stream, n, B, num_tiles(g), seg_off,
-                       bt_off, segtab, err);
+                       bt_off, slot_of, nslots, segtab, err);
     return hipGetLastError();
 }
 

@@ -147,8 +147,9 @@ struct tvs_ctx {
     int32_t *order = nullptr;       // nh: each chunk's histories by decreasing row length
     uint64_t *segtab = nullptr;     // nseg: global entry index of each segment's first entry
     int64_t nseg = 0;
-    int64_t *bt_off = nullptr;      // nblocks * ntiles + 1 list starts
-    int32_t *act = nullptr;         // tiles that some block's lists cross
+    int64_t *bt_off = nullptr;      // nblocks * nact + 1 list starts, slots in order per block
+    int32_t *act = nullptr;         // tiles that some block's lists cross (slot -> tile)
+    int32_t *slot_of = nullptr;     // ntiles: tile -> slot, -1 for a tile no list crosses
     int64_t nact = 0;
     int64_t nblocks = 0;
     // entries: the store, or a ring of chunk buffers on the fly
@@ -275,7 +276,7 @@ void dfree(tvs_ctx *ctx, T **p, size_t count)
     }
 }
 
-int64_t bt_len(const tvs_ctx *ctx) { return ctx->nblocks * ctx->ntiles + 1; }
+int64_t bt_len(const tvs_ctx *ctx) { return ctx->nblocks * ctx->nact + 1; }
 
 // Ring buffer of chunk c of the current sweep (on the fly).
 int chunk_buffer(const tvs_ctx *ctx, int64_t c) { return (int)((ctx->cbase + c) % ctx->nbuf); }
@@ -294,6 +295,7 @@ void free_histories(tvs_ctx *ctx)
     dfree(ctx, &ctx->segtab, (size_t)ctx->nseg);
     dfree(ctx, &ctx->bt_off, (size_t)bt_len(ctx));
     dfree(ctx, &ctx->act, (size_t)std::max<int64_t>(ctx->nact, 1));
+    dfree(ctx, &ctx->slot_of, (size_t)std::max<int64_t>(ctx->ntiles, 1));
     ctx->nact = 0;
     for (int q = 0; q < kChunkBuffers; q++) {
         dfree(ctx, &ctx->meta[q], (size_t)ctx->cap);
@@ -462,7 +464,7 @@ TileBlock block_view(tvs_ctx *ctx, int64_t b, long long *dot_base, int64_t dot_s
     t.qunit = ctx->qunit;
     t.qshift = ctx->qshift;
     t.rowmask = ctx->rowmask;
-    t.toff = ctx->bt_off + b * ctx->ntiles;
+    t.toff = ctx->bt_off + b * ctx->nact;
     t.base = otf ? ctx->chunk_base[(size_t)c] : 0;
     t.wepl = ctx->hist + 12 * ctx->nh + b * B;
     t.n2 = ctx->norm2 + b * B;
@@ -609,19 +611,22 @@ int count_rows(tvs_ctx *ctx, int64_t first, int64_t n, int64_t *row_off_dev, hip
 }
 
 // The tiles that some block's lists cross (a tile outside the scanned
-// object has no entry in any block): the DROP steps launch one workgroup
-// per such tile only, in order of decreasing entries over the scan, so that
-// the longest lists are dispatched first and do not trail the step.  At
-// least one tile is kept, so that a step always has a workgroup to clear
-// the next dot-product buffer.
-int build_active_tiles(tvs_ctx *ctx, hipStream_t st)
+// object has no entry in any block), from the (block, tile) list lengths:
+// the DROP steps launch one workgroup per such tile only, in order of
+// decreasing entries over the scan, so that the longest lists are
+// dispatched first and do not trail the step.  Workgroup i of a step takes
+// slot i: tile act[i], whose lists are laid out in slot order (slot_of
+// inverts act; -1 for a tile no list crosses).  At least one tile is kept,
+// so that a step always has a workgroup to clear the next dot-product
+// buffer.
+int build_active_tiles(tvs_ctx *ctx, const uint32_t *btc, hipStream_t st)
 {
     const int64_t nt = ctx->ntiles;
     uint32_t *total = nullptr;
     int rc = dalloc(ctx, &total, (size_t)std::max<int64_t>(nt, 1));
     if (rc) return rc;
     std::vector<uint32_t> f((size_t)std::max<int64_t>(nt, 1), 0u);
-    hipError_t e = tvs::launch_tile_active(ctx->bt_off, ctx->nblocks, nt, total, st);
+    hipError_t e = tvs::launch_tile_totals(btc, ctx->nblocks, nt, total, st);
     if (e == hipSuccess && nt > 0)
         e = hipMemcpyAsync(f.data(), total, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -633,10 +638,16 @@ int build_active_tiles(tvs_ctx *ctx, hipStream_t st)
     std::stable_sort(a.begin(), a.end(),
                      [&](int32_t x, int32_t y) { return f[(size_t)x] > f[(size_t)y]; });
     if (a.empty()) a.push_back(0);
+    std::vector<int32_t> inv((size_t)std::max<int64_t>(nt, 1), -1);
+    for (size_t i = 0; i < a.size(); i++) inv[(size_t)a[i]] = (int32_t)i;
     rc = dalloc(ctx, &ctx->act, a.size());
+    if (!rc) rc = dalloc(ctx, &ctx->slot_of, inv.size());
     if (rc) return rc;
     ctx->nact = (int64_t)a.size();
     e = hipMemcpyAsync(ctx->act, a.data(), sizeof(int32_t) * a.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->slot_of, inv.data(), sizeof(int32_t) * inv.size(),
+                           hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(ctx, TVS_EDEVICE, std::string("active tiles: ") + hipGetErrorString(e));
     return TVS_OK;
@@ -650,7 +661,8 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
     const int64_t n = ctx->nh, B = ctx->cfg.block_size;
     const int64_t nbt = ((n + B - 1) / B) * ctx->ntiles;
     int32_t *cnt = nullptr, *cseg = nullptr;
-    uint32_t *btc = nullptr;
+    uint32_t *btc = nullptr, *sbc = nullptr;   // list lengths by (block, tile), by (block, slot)
+    int64_t nsbc = 0;
     int64_t *tmp = nullptr;
     // scan scratch, later also the gathered block starts
     const int64_t ntmp = std::max(tvs::scan_tmp_elems(std::max(n, nbt)) + 1, (n + B - 1) / B + 1);
@@ -658,6 +670,7 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
         dfree(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
         dfree(ctx, &cseg, (size_t)std::max<int64_t>(n, 1));
         dfree(ctx, &btc, (size_t)std::max<int64_t>(nbt, 1));
+        dfree(ctx, &sbc, (size_t)std::max<int64_t>(nsbc, 1));
         dfree(ctx, &tmp, (size_t)ntmp);
     };
     int rc = dalloc(ctx, &cnt, (size_t)std::max<int64_t>(n, 1));
@@ -753,7 +766,6 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
     ctx->dot_max = 67108864.0 / (double)std::max<int64_t>(mx, 1);  // 2^26 / max_row
 
     rc = dalloc(ctx, &ctx->segtab, (size_t)nseg);
-    if (!rc) rc = dalloc(ctx, &ctx->bt_off, (size_t)bt_len(ctx));
     if (!rc) rc = dalloc(ctx, &btc, (size_t)std::max<int64_t>(nbt, 1));
     if (rc) {
         cleanup();
@@ -765,16 +777,32 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
         e = tvs::launch_rows_seg(ctx->gd, hd, ctx->mlp, n, B, ctx->seg_off, btc, ctx->segtab,
                                  ctx->flags + kFlagLists, ctx->flags + kFlagChordMax, ctx->order,
                                  st);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(ctx, TVS_EDEVICE, std::string("tile lists: ") + hipGetErrorString(e));
+    }
+    // the dispatch slots, then the lists of every block laid out in slot
+    // order: a step's workgroup i finds its list bounds at [b * nact + i]
+    // without first looking up its tile
+    rc = build_active_tiles(ctx, btc, st);
+    nsbc = ctx->nblocks * ctx->nact;
+    if (!rc) rc = dalloc(ctx, &ctx->bt_off, (size_t)bt_len(ctx));
+    if (!rc) rc = dalloc(ctx, &sbc, (size_t)std::max<int64_t>(nsbc, 1));
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    e = tvs::launch_slot_counts(btc, ctx->act, ctx->nact, ctx->nblocks, ctx->ntiles, sbc, st);
     if (e == hipSuccess)
-        e = tvs::launch_scan(reinterpret_cast<const int32_t *>(btc), nbt, ctx->bt_off, tmp, st);
+        e = tvs::launch_scan(reinterpret_cast<const int32_t *>(sbc), nsbc, ctx->bt_off, tmp, st);
     if (e == hipSuccess)
-        e = tvs::launch_seg_dest(ctx->gd, n, B, ctx->seg_off, ctx->bt_off, ctx->segtab,
-                                 ctx->flags + kFlagLists, st);
+        e = tvs::launch_seg_dest(ctx->gd, n, B, ctx->seg_off, ctx->bt_off, ctx->slot_of,
+                                 ctx->nact, ctx->segtab, ctx->flags + kFlagLists, st);
     // every block's lists must add up to the block's entries (the block
     // starts are gathered into the freed count buffer, then copied)
     std::vector<int64_t> starts((size_t)ctx->nblocks + 1);
     if (e == hipSuccess && ctx->nblocks > 0)
-        e = tvs::launch_pick(ctx->bt_off, ctx->ntiles, ctx->nblocks + 1, tmp, st);
+        e = tvs::launch_pick(ctx->bt_off, ctx->nact, ctx->nblocks + 1, tmp, st);
     if (e == hipSuccess && ctx->nblocks > 0)
         e = hipMemcpyAsync(starts.data(), tmp, sizeof(int64_t) * (ctx->nblocks + 1),
                            hipMemcpyDeviceToHost, st);
@@ -795,7 +823,7 @@ int build_tile_lists(tvs_ctx *ctx, hipStream_t st)
                             " of " + std::to_string(ctx->nblocks) + ": " +
                             std::to_string(starts[(size_t)b]) + " != " + std::to_string(want));
     }
-    return build_active_tiles(ctx, st);
+    return TVS_OK;
 }
 
 // Allocates the entry buffers and, for a path store, forms every row now.

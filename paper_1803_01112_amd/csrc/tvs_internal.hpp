@@ -163,9 +163,10 @@ hipError_t launch_rows_seg(const GridDev &g, const HistDev &h, const MlpCfg &m, 
                            int64_t B, const int64_t *seg_off, uint32_t *btc, uint64_t *segtab,
                            uint32_t *err, uint32_t *chmax, const int32_t *order,
                            hipStream_t stream);
+// bt_off: the list starts of every (block, slot), slot_of: tile -> slot.
 hipError_t launch_seg_dest(const GridDev &g, int64_t n, int64_t B, const int64_t *seg_off,
-                           const int64_t *bt_off, uint64_t *segtab, uint32_t *err,
-                           hipStream_t stream);
+                           const int64_t *bt_off, const int32_t *slot_of, int64_t nslots,
+                           uint64_t *segtab, uint32_t *err, hipStream_t stream);
 // Forms the rows of f.first .. f.first + f.n - 1 into their tile lists.
 hipError_t launch_rows_fill_tiled(const GridDev &g, const HistDev &h, const MlpCfg &m,
                                   const TileFill &f, hipStream_t stream);
@@ -222,7 +223,7 @@ struct TileBlock {
     double qunit = 0.0;               // fixed-point store: mm per unit of the code
     uint32_t qshift = 31;             // fixed-point store: the code's bits 16.. sit in tag bits qshift..
     uint32_t rowmask = 0xffffffu;     // row field of a tag: (tag >> 8) & rowmask
-    const int64_t *toff = nullptr;    // ntiles + 1 list starts (global entry index)
+    const int64_t *toff = nullptr;    // nact + 1 list starts in slot order (global entry index)
     int64_t base = 0;
     const float *wepl = nullptr;      // per row of the block
     const float *n2 = nullptr;        // ||a_i||^2 per row of the block
@@ -267,7 +268,9 @@ hipError_t launch_drop_tiles(const DropTileArgs &a, int64_t ntiles, int threads,
 hipError_t launch_zero_i64(long long *p, int64_t n, hipStream_t stream);
 // total[T] = entries of tile T over the lists of every block (list starts
 // bt_off of nblocks x ntiles lists), saturated at 2^32 - 1.
-hipError_t launch_tile_active(const int64_t *bt_off, int64_t nblocks, int64_t ntiles,
+hipError_t launch_slot_counts(const uint32_t *cnt, const int32_t *act, int64_t nact,
+                              int64_t nblocks, int64_t ntiles, uint32_t *out, hipStream_t stream);
+hipError_t launch_tile_totals(const uint32_t *cnt, int64_t nblocks, int64_t ntiles,
                               uint32_t *total, hipStream_t stream);
 
 // ----------------------------------------------------------------- tv.hip
