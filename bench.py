@@ -490,6 +490,10 @@ def main():
     # on the second stream (events around every launch)
     nnz = st["nnz"]
     k1_ms = st["k1_ms_total"] / max(st["k_samples"], 1)
+    if st["k_samples"] == 0:
+        # no kernel-stamped launches (--time-sample 0): the chain's device
+        # time per step stands in for the launch duration
+        k1_ms = st["drop_ms_total"] / max(st["drop_launches"], 1) / (T + 1)
     rows_ms = st["rows_ms_total"] / max(st["rows_launches"], 1)
     per_cycle = {"k_drop_tile": k1_ms * (T + 1)}
     if args.path_mode == "otf":
