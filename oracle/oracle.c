@@ -23,7 +23,7 @@
  *     with the midpoint rule (the paper is silent on the walk);
  *   - P_T is one sweep of block-iterative DROP (Section III-D; Appendix A),
  *     with the block form U_t = diag(1/s_j), unit row weights;
- *   - phi = total variation, "sum of local variations over all voxels"
+ *   - phi = total variation, the local variations added over every voxel
  *     (Section IV), read as 2-D isotropic forward differences per slice;
  *   - the perturbation vector v = -grad(phi)/||grad(phi)|| (Appendix A);
  *   - the NTVS cycle with and without the TV-reduction check (Appendix C),

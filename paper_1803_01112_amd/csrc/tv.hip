@@ -1,6 +1,6 @@
 // tv.hip -- total variation, its subgradient and the normalised perturbation
-// step on gfx950 (arXiv 1803.01112: phi = TV, "the sum of local variations
-// over all voxels", Section IV; v = -grad phi / ||grad phi||, Appendix A).
+// step on gfx950 (arXiv 1803.01112: phi = TV, the local variations added over
+// every voxel, Section IV; v = -grad phi / ||grad phi||, Appendix A).
 //
 // TV is taken per slice (2-D isotropic forward differences, zero difference
 // past the last row/column): m_ij = sqrt(dx^2 + dy^2 + eps^2),

@@ -3,7 +3,7 @@ runner over the batched sweep.
 
 The measures follow the paper's analysis (arXiv 1803.01112, Section IV):
 
-* total variation of the image: the sum of local variations over all voxels,
+* total variation of the image: the local variations added over every voxel,
   read (as everywhere in this package) as 2-D isotropic forward differences
   within each slice, a difference past the last row or column being zero;
 * mean and standard deviation of the RSP in a circular region of interest

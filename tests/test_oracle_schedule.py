@@ -148,7 +148,7 @@ def test_decoupled_schedule_beta():
 # ---------------------------------------------------------------------------
 # The retry branch of the checked step and the length of the unchecked step,
 # pinned against images stepped explicitly here.  TV is recomputed with numpy
-# (per-slice forward differences, Section IV's "sum of local variations");
+# (per-slice forward differences, Section IV's definition of TV);
 # the direction v = -grad/||grad|| takes the oracle's subgradient, which
 # tests/test_oracle_tv.py pins against finite differences.
 # ---------------------------------------------------------------------------

@@ -1,6 +1,6 @@
 """Pins of the oracle's total variation and its subgradient.
 
-phi = TV, "the sum of local variations over all voxels" (arXiv 1803.01112,
+phi = TV, the local variations added over every voxel (arXiv 1803.01112,
 Section IV); v = -grad phi/||grad phi|| (Appendix A).  Reading: per slice,
 isotropic forward differences, zero difference past the last row/column,
 local variation m = sqrt(dx^2 + dy^2 + eps^2), phi = sum (m - eps).
