@@ -340,25 +340,40 @@ def run_serving(tvs, args):
         return s.submit(w.grid, hh, lam=r["lam"], N=r["N"], alpha=r["alpha"], K=r["K"],
                         path_mode=args.serve_path, x0=x0, seed=7)
 
-    with tvs.Server(max_active=1) as s:
-        t0 = time.perf_counter()
-        for r in reqs:
-            s.wait(sub(s, r))
-        t_alone = time.perf_counter() - t0
+    if args.serve_capacity > 0:
+        # a capacity measured before (history-cycles/s of requests run one
+        # at a time): long mixes skip the serial pass
+        t_alone = work / args.serve_capacity
+        log(f"serving: capacity given, {args.serve_capacity:.4g} history-cycles/s")
+    else:
+        with tvs.Server(max_active=1) as s:
+            t0 = time.perf_counter()
+            for q, r in enumerate(reqs):
+                s.wait(sub(s, r))
+                if (q + 1) % 20 == 0:
+                    log(f"serving: {q + 1} of {len(reqs)} requests run one at a time")
+            t_alone = time.perf_counter() - t0
+        log(f"serving: {len(reqs)} requests one at a time in {t_alone:.1f} s")
     cap_rate = len(reqs) / t_alone
-    log(f"serving: {len(reqs)} requests one at a time in {t_alone:.1f} s")
     out = dict(requests=len(reqs), histories=f"log-uniform in [{args.serve_hmin}, {hmax}]",
-               history_cycles=work, serial_s=t_alone, serial_value=work / t_alone,
+               history_cycles=work, serial_s=None if args.serve_capacity > 0 else t_alone,
+               serial_value=work / t_alone, capacity_given=args.serve_capacity > 0,
                slots=args.serve_slots, path_mode=args.serve_path, loads={})
     for rho in [float(v) for v in args.serve_loads.split(",")]:
         gaps = rng.exponential(1.0 / (rho * cap_rate), len(reqs))
         with tvs.Server(max_active=args.serve_slots) as s:
             t0 = time.perf_counter()
             ids = []
-            for r, gap in zip(reqs, gaps):
+            for q, (r, gap) in enumerate(zip(reqs, gaps)):
                 time.sleep(gap)
                 ids.append(sub(s, r))
-            res = [s.wait(i) for i in ids]
+                if (q + 1) % 20 == 0:
+                    log(f"serving at load {rho}: {q + 1} of {len(reqs)} submitted")
+            res = []
+            for q, i in enumerate(ids):
+                res.append(s.wait(i))
+                if (q + 1) % 20 == 0:
+                    log(f"serving at load {rho}: {q + 1} of {len(reqs)} done")
             dt = time.perf_counter() - t0
             c = s.counters()
         lat = np.array([i["done_ms"] - i["submit_ms"] for _, i in res])
@@ -439,6 +454,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--serve-path", default="q16")
+    ap.add_argument("--serve-capacity", type=float, default=0.0,
+                    help="serial capacity in history-cycles/s (skips the serial pass)")
     ap.add_argument("--fbp", action="store_true",
                     help="also time the initial iterate (FBP + median) of all histories")
     ap.add_argument("--precision-hist", type=int, default=3_750_000)
