@@ -394,8 +394,12 @@ void tvs_server_config_default(tvs_server_config *cfg);
  * simulated server without a budget; TVS_EDEVICE if the device is unusable. */
 int tvs_server_create(const tvs_server_config *cfg, tvs_server **out);
 /* Device bytes reserved for a request (history streams, row lengths, row
- * buffers of one chunk or the whole store, image buffers); an upper
- * estimate that also bounds the request's own context. */
+ * buffers of one chunk or the whole store, image buffers).  The row entries
+ * of a store are estimated from the histories' straight entry-exit lines,
+ * the most likely path taken within 10 mm plus half the line's length times
+ * the entry and exit slopes of them (a host pass over the arrays); the
+ * estimate also bounds the request's own context, so a request whose rows
+ * exceed it fails alone with TVS_ENOMEM. */
 uint64_t tvs_server_footprint(const tvs_server *sv, const tvs_request *r);
 /* Queues a request; *id receives its handle.  TVS_EINVAL for a bad grid or
  * sizes, TVS_ENOMEM when its footprint alone exceeds the budget. */

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -43,31 +44,112 @@ struct Req {
     std::string err;
 };
 
+// Bounds on a request's row entries and row segments (a row's run of
+// entries inside one 16 x 16 tile) from its histories' straight entry-exit
+// lines.  The most likely path is taken to stay within a margin of that
+// line: kMargin mm plus half the line's length times the entry and exit
+// slopes (the path bends from the entry ray towards the exit ray); a row
+// then crosses at most (extent along an axis + 2 margins) / voxel size + 2
+// planes of each axis, and tile boundaries 16 times fewer in x and y; each
+// history's bound is also held below the grid-wide ones (row_cap, seg_cap).
+// A host pass over the borrowed arrays, on several threads for large
+// requests; without histories the grid-wide bounds are used.
+constexpr double kMargin = 10.0;
+
+struct LineSums {
+    double rows = 0.0, segs = 0.0;
+};
+
+LineSums line_bounds(const tvs_request &r, double row_cap, double seg_cap)
+{
+    LineSums tot;
+    const int64_t n = std::max<int64_t>(r.n, 0);
+    const tvs_histories &h = r.h;
+    if (!h.ex || !h.ey || !h.ez || !h.qx || !h.qy || !h.qz || !h.eth || !h.eps || !h.qth ||
+        !h.qps) {
+        tot.rows = row_cap * (double)n;
+        tot.segs = seg_cap * (double)n;
+        return tot;
+    }
+    const tvs_grid &g = r.grid;
+    const double ext[3] = {g.nx * g.vx, g.ny * g.vy, g.nz * g.vz};
+    auto part = [&](int64_t i0, int64_t i1, LineSums *out) {
+        LineSums t;
+        for (int64_t i = i0; i < i1; i++) {
+            const double d[3] = {std::fabs((double)h.qx[i] - h.ex[i]),
+                                 std::fabs((double)h.qy[i] - h.ey[i]),
+                                 std::fabs((double)h.qz[i] - h.ez[i])};
+            const double len = std::hypot(d[0], d[1]);
+            const double mt = kMargin + 0.5 * len * (std::fabs((double)h.eth[i]) +
+                                                     std::fabs((double)h.qth[i]));
+            const double mv = kMargin + 0.5 * len * (std::fabs((double)h.eps[i]) +
+                                                     std::fabs((double)h.qps[i]));
+            const double m[3] = {mt, mt, mv};
+            double e[3];
+            for (int a = 0; a < 3; a++) {
+                e[a] = std::min(d[a] + 2.0 * m[a], ext[a]);
+                if (!(e[a] >= 0.0)) e[a] = ext[a];   // NaN input: the grid's extent
+            }
+            const double rows = e[0] / g.vx + e[1] / g.vy + e[2] / g.vz + 6.0;
+            const double segs = e[0] / (16.0 * g.vx) + e[1] / (16.0 * g.vy) + e[2] / g.vz + 6.0;
+            t.rows += std::min(rows, row_cap);
+            t.segs += std::min(segs, seg_cap);
+        }
+        *out = t;
+    };
+    const int64_t per = 1 << 20;
+    const int nt = (int)std::min<int64_t>(16, (n + per - 1) / per);
+    if (nt <= 1) {
+        part(0, n, &tot);
+        return tot;
+    }
+    std::vector<LineSums> sums((size_t)nt);
+    std::vector<std::thread> th;
+    for (int q = 0; q < nt; q++)
+        th.emplace_back(part, n * q / nt, n * (q + 1) / nt, &sums[(size_t)q]);
+    for (auto &t : th) t.join();
+    for (const auto &t : sums) {
+        tot.rows += t.rows;
+        tot.segs += t.segs;
+    }
+    return tot;
+}
+
 uint64_t footprint(const tvs_request &r, int64_t chunk)
 {
-    // conservative device bytes of one context (see tvs_server_footprint)
+    // device bytes of one context (see tvs_server_footprint)
     // image words in the device's tiled layout (16 x 16 tiles, padding included)
     const uint64_t nvox = (uint64_t)(((r.grid.nx + 15) / 16) * 16) *
                           (uint64_t)(((r.grid.ny + 15) / 16) * 16) * (uint64_t)r.grid.nz;
     const uint64_t ntiles = nvox / 256;
     const double vmin = std::min(r.grid.vx, r.grid.vy);
     const double span = (r.grid.nx * r.grid.vx + r.grid.ny * r.grid.vy) / vmin;
-    const uint64_t row_est = (uint64_t)(0.8 * span) + (uint64_t)r.grid.nz + 8;
-    const uint64_t seg_est = row_est / 4 + 2;
+    const double row_cap = (double)((uint64_t)(0.8 * span) + (uint64_t)r.grid.nz + 8);
+    const double seg_cap = row_cap / 4 + 2;
     const uint64_t n = (uint64_t)std::max<int64_t>(r.n, 0);
+    const LineSums ls = line_bounds(r, row_cap, seg_cap);
     const uint64_t B = (uint64_t)(r.block_size > 0 ? r.block_size : 3200);
     const uint64_t nblocks = (n + B - 1) / B;
-    uint64_t rows_held;
-    if (r.path_mode == TVS_PATH_ON_THE_FLY) rows_held = 3 * std::min<uint64_t>(n, (uint64_t)chunk);  // ring of 3
-    else rows_held = n;
-    // entries: 32-bit tag + chord (float32, or float16 for the f16 store)
+    // entries: 32-bit tag + chord (float32, or 16 bits for the f16 / q16 stores)
     const uint64_t entry =
         (r.path_mode == TVS_PATH_STORE_F16 || r.path_mode == TVS_PATH_STORE_Q16) ? 6 : 8;
-    const uint64_t per_hist = 52 /* streams */ + 8 + 4 + 8 /* row_off, norm2, seg_off */ +
-                              8 /* load-time counts */ + 8 * seg_est /* segment places */;
-    const uint64_t lists = 12 * (nblocks * ntiles + 1) /* list starts + load-time counts */;
-    return per_hist * n + lists + rows_held * row_est * entry + 40 * nvox + 24 * B +
-           (64ull << 20);
+    double entries;
+    if (r.path_mode == TVS_PATH_ON_THE_FLY) {
+        // a ring of three chunks of the longest rows the request can have
+        const uint64_t held = 3 * std::min<uint64_t>(n, (uint64_t)chunk);
+        entries = (double)held * row_cap;
+    } else {
+        entries = ls.rows;
+    }
+    const double per_hist = 52 /* streams */ + 8 + 4 + 8 + 4 /* row_off, norm2, seg_off, order */ +
+                            8 /* load-time counts */;
+    // list starts and the load-time list lengths by (block, tile) and by
+    // (block, dispatch slot), live together at the peak
+    const double lists = 16.0 * (double)(nblocks * ntiles + 1);
+    const double bytes = per_hist * (double)n + 8.0 * ls.segs /* segment places */ + lists +
+                         entries * (double)entry + 40.0 * (double)nvox + 24.0 * (double)B +
+                         (double)(64ull << 20);
+    return (uint64_t)bytes;
 }
 
 }  // namespace
