@@ -136,6 +136,13 @@ def run_form(tvs, torch, w, dev_hist, x0, args, mode, K, W, n_lat, check=False, 
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t0
     ctx.set_image(x0)
+    tune = None
+    if args.tune:
+        # the library's launch-shape tuner (on the fly also the share of row
+        # chunks formed at full occupancy); it restores the image
+        tune = ctx.autotune(args.lam)
+        log(f"{mode}: tuned {tune['tile_threads']} threads, sweep kernel {tune['sweep_kernel']}, "
+            f"full-occupancy row chunks {tune['fill_wide_pct']} %")
     kw = dict(lam=args.lam, N=args.N, alpha=args.alpha, tv_check=check, seed=args.seed)
     if W > 0:
         ctx.iterate(W, **kw)
@@ -164,6 +171,9 @@ def run_form(tvs, torch, w, dev_hist, x0, args, mode, K, W, n_lat, check=False, 
                       what="algorithmic bytes of one sweep over the DROP chain's device time")
     if mode == "otf":
         out["hbm"]["on_the_fly_stream_bytes"] = 52.0 * H
+    if tune is not None:
+        out["tuned"] = dict(tile_threads=tune["tile_threads"], sweep_kernel=tune["sweep_kernel"],
+                            fill_wide_pct=tune["fill_wide_pct"] if mode == "otf" else None)
     if lat:
         out["latency_ms"] = percentiles(lat)
     if steps is not None:
@@ -445,6 +455,8 @@ def main():
     ap.add_argument("--check-steps", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the library's launch-shape tuner before each timed form")
     ap.add_argument("--batch-path", default="f32")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--batch-latency", type=int, default=10)

@@ -98,9 +98,12 @@ typedef struct {
                                 k-th DROP block (per-launch durations in tvs_stats); 0: off */
     int32_t fill_wgs_per_cu; /* on-the-fly rows: cap on the workgroups per compute unit of
                                 the row formation that runs beside the DROP chain; 0 or < 0:
-                                no cap (its register budget already leaves every SIMD room
-                                for the DROP step's waves) */
-    int32_t pad;
+                                no cap */
+    int32_t fill_wide_pct;   /* on-the-fly rows: percentage of the chunks formed at the row
+                                kernel's full occupancy (three waves per SIMD, which leaves a
+                                SIMD no room for DROP waves); the others are held at two
+                                waves per SIMD, with room for four DROP waves beside them;
+                                spread evenly over the sweep; < 0: the library's choice (0) */
 } tvs_config;
 
 /* Fills *cfg with the defaults above (B = 3200, on-the-fly rows, log term on). */
@@ -419,11 +422,15 @@ void tvs_server_destroy(tvs_server *sv);
  * Autotuning of the launch shape.  Times every candidate shape (threads per
  * image-tile workgroup 64 / 128 / 256, one or two launches per DROP block)
  * on the first blocks of the loaded histories, from the current image,
- * which is restored afterwards, and keeps the fastest for the context.  The
- * block size B is a parameter of the method and is never changed.  With
- * cache_path (a text file, created if missing) a shape measured before for
- * the same device, grid, history count, B and path mode is reused without
- * timing, and new measurements are appended.
+ * which is restored afterwards, and keeps the fastest for the context.  On
+ * the fly a second stage then times whole sweeps (row formation beside the
+ * chain) for the share of chunks formed at the row kernel's full occupancy
+ * (tvs_config.fill_wide_pct: 0, 20, 40, 60, 80, 100) and keeps the fastest.
+ * The block size B is a parameter of the method and is never changed (a
+ * larger B is always faster per sweep, and changes the reconstruction).
+ * With cache_path (a text file, created if missing) a shape measured before
+ * for the same device, grid, history count, B and path mode is reused
+ * without timing, and new measurements are appended.
  * ------------------------------------------------------------------------ */
 typedef struct {
     int32_t tile_threads;    /* chosen shape */
@@ -434,6 +441,10 @@ typedef struct {
     int32_t cand_threads[8];
     int32_t cand_sweep[8];
     double cand_ms[8];       /* per block, per candidate */
+    int32_t fill_wide_pct;   /* on the fly: chosen share of full-occupancy chunks, % */
+    int32_t n_fill;          /* on the fly: shares timed (0 otherwise) */
+    int32_t cand_pct[8];
+    double cand_sweep_ms[8]; /* per sweep, per share */
 } tvs_tune_result;
 
 /* TVS_ESTATE before tvs_load_histories; TVS_EINVAL for lambda <= 0. */

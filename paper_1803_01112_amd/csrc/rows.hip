@@ -624,10 +624,15 @@ k_seg_dest(int64_t n, int64_t B, int64_t ntiles, const int64_t *seg_off, const i
     }
 }
 
-template <typename CH>
+// kRoom: the kernel takes at least 171 VGPRs (176 allocated: the empty asm
+// below claims v170), so that a SIMD holds two of its waves and four 40-VGPR
+// DROP waves beside them; otherwise it fits three waves per SIMD, and a DROP
+// step finds no room on a SIMD that holds three.
+template <typename CH, bool kRoom>
 __global__ void __launch_bounds__(kThreads, kRowWaves)
 k_rows_fill_tiled(GridDev g, HistDev H, MlpCfg m, TileFill f, CH *chord)
 {
+    if constexpr (kRoom) asm volatile("" ::: "v170");
     // grid-stride: the grid may be held below the device's capacity so that
     // the DROP launches running beside it always find free slots
     for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < f.n;
@@ -864,14 +869,17 @@ hipError_t launch_rows_fill_tiled(const GridDev &g, const HistDev &h, const MlpC
     if (f.max_wgs > 0 && wgs > f.max_wgs) wgs = f.max_wgs;
     dim3 grid((unsigned)wgs);
     if (f.chq)
-        hipLaunchKernelGGL(k_rows_fill_tiled<uint16_t>, grid, dim3(kThreads), 0, stream, g, h, m,
-                           f, f.chq);
+        hipLaunchKernelGGL((k_rows_fill_tiled<uint16_t, false>), grid, dim3(kThreads), 0, stream,
+                           g, h, m, f, f.chq);
     else if (f.ch16)
-        hipLaunchKernelGGL(k_rows_fill_tiled<__half>, grid, dim3(kThreads), 0, stream, g, h, m, f,
-                           f.ch16);
+        hipLaunchKernelGGL((k_rows_fill_tiled<__half, false>), grid, dim3(kThreads), 0, stream, g,
+                           h, m, f, f.ch16);
+    else if (f.room)
+        hipLaunchKernelGGL((k_rows_fill_tiled<float, true>), grid, dim3(kThreads), 0, stream, g, h,
+                           m, f, f.ch32);
     else
-        hipLaunchKernelGGL(k_rows_fill_tiled<float>, grid, dim3(kThreads), 0, stream, g, h, m, f,
-                           f.ch32);
+        hipLaunchKernelGGL((k_rows_fill_tiled<float, false>), grid, dim3(kThreads), 0, stream, g,
+                           h, m, f, f.ch32);
     return hipGetLastError();
 }
 

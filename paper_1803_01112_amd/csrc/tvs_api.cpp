@@ -178,6 +178,7 @@ struct tvs_ctx {
     int bthreads = 256;             // batched DROP step: threads per workgroup
     int bgroup = 4;                 // batched DROP step: settings per pass through LDS
     int64_t fill_wgs = 0;           // grid cap of the sweep's row formation (0: none)
+    int fill_wide_pct = 0;          // chunks formed at the row kernel's full occupancy, %
 
     // cycle state
     int64_t k = 0, ell = 0;
@@ -492,6 +493,11 @@ tvs::TileFill chunk_fill(tvs_ctx *ctx, int64_t c, int64_t n)
     f.err = ctx->flags + kFlagLists;
     f.max_wgs = ctx->fill_wgs;
     f.order = ctx->order;
+    // beside the DROP chain: chunk c at full occupancy when the running count
+    // of such chunks steps up at c (fill_wide_pct of them, spread evenly),
+    // else held at two waves per SIMD
+    const int64_t pct = ctx->fill_wide_pct;
+    f.room = ((c + 1) * pct / 100 > c * pct / 100) ? 0 : 1;
     return f;
 }
 
@@ -924,7 +930,7 @@ void tvs_config_default(tvs_config *cfg)
     cfg->tile_threads = 0;
     cfg->time_sample = 0;
     cfg->fill_wgs_per_cu = 0;
-    cfg->pad = 0;
+    cfg->fill_wide_pct = -1;
 }
 
 const char *tvs_strerror(int status)
@@ -1030,6 +1036,10 @@ int tvs_create(const tvs_grid *grid, const tvs_config *cfg_in, tvs_ctx **out)
             cus = 0;
         const int per_cu = cfg.fill_wgs_per_cu;
         ctx->fill_wgs = (per_cu > 0 && cus > 0) ? (int64_t)per_cu * cus : 0;
+        // the library's choice: about 40 % of the chunks at full occupancy
+        // (within a few % of the best share at 200x200x16 and 256x256x32;
+        // tvs_autotune times the shares on the loaded histories)
+        ctx->fill_wide_pct = cfg.fill_wide_pct < 0 ? 40 : std::min(cfg.fill_wide_pct, 100);
         // Tile workgroup size: 128 lanes on the fly (they leave the row
         // formation beside the DROP chain more room) and for grids of more
         // tiles than twice the 256-lane workgroups the device holds at once
@@ -1979,14 +1989,16 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
             char line[1024];
             while (std::fgets(line, sizeof(line), f)) {
                 char k[512];
-                int th = 0, sw = 0;
+                int th = 0, sw = 0, pct = -1;
                 double ms = 0;
-                if (std::sscanf(line, "%511s %d %d %lf", k, &th, &sw, &ms) == 4 &&
-                    std::strcmp(k, key) == 0 && (th == 64 || th == 128 || th == 256) &&
+                const int got = std::sscanf(line, "%511s %d %d %lf %d", k, &th, &sw, &ms, &pct);
+                if (got >= 4 && std::strcmp(k, key) == 0 && (th == 64 || th == 128 || th == 256) &&
                     (sw == 1 || sw == 2)) {
                     out->tile_threads = th;
                     out->sweep_kernel = sw;
                     out->ms_per_block = ms;
+                    out->fill_wide_pct = (got == 5 && pct >= 0 && pct <= 100) ? pct
+                                                                               : ctx->fill_wide_pct;
                     out->from_cache = 1;
                 }
             }
@@ -1995,11 +2007,13 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
         if (out->from_cache) {
             ctx->threads = out->tile_threads;
             ctx->split = out->sweep_kernel == 2 ? 1 : 0;
+            ctx->fill_wide_pct = out->fill_wide_pct;
             return TVS_OK;
         }
     }
     const int64_t B = ctx->cfg.block_size;
     const int64_t nb = std::min<int64_t>(ctx->nblocks, 48);
+    out->fill_wide_pct = ctx->fill_wide_pct;
     if (nb == 0) {
         out->tile_threads = ctx->threads;
         out->sweep_kernel = ctx->split ? 2 : 1;
@@ -2054,22 +2068,64 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
             }
         }
     }
-    dfree(ctx, &saved, (size_t)ctx->nvox);
-    ctx->tev_used = 0;
-    ctx->spans.clear();
-    ctx->timed = false;
     out->n_candidates = nc;
     if (rc || best == 1e300) {
+        dfree(ctx, &saved, (size_t)ctx->nvox);
+        ctx->tev_used = 0;
+        ctx->spans.clear();
+        ctx->timed = false;
         ctx->threads = old_threads;
         ctx->split = old_split;
         return rc ? rc : fail(ctx, TVS_EDEVICE, "autotune: no candidate ran");
     }
     ctx->threads = out->tile_threads;
     ctx->split = out->sweep_kernel == 2 ? 1 : 0;
+    // on the fly: whole sweeps (the row formation beside the chain) for the
+    // share of chunks formed at the row kernel's full occupancy; with one
+    // chunk the share does not matter
+    const int64_t nchunks = (ctx->nh + ctx->chunk - 1) / ctx->chunk;
+    if (ctx->cfg.path_mode == TVS_PATH_ON_THE_FLY && nchunks > 1) {
+        const int pcts[6] = {0, 20, 40, 60, 80, 100};
+        const int old_pct = ctx->fill_wide_pct;
+        double pbest = 1e300;
+        for (int pi = 0; pi < 6 && rc == TVS_OK; pi++) {
+            ctx->fill_wide_pct = pcts[pi];
+            ctx->tev_used = 0;
+            ctx->spans.clear();
+            long a = mark(ctx, st);
+            rc = run_sweep(ctx, lambda, st);
+            long b = mark(ctx, st);
+            if (rc) break;
+            hipError_t e = hipMemcpyAsync(ctx->x, saved, sizeof(double) * ctx->nvox,
+                                          hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->fill_stream);
+            float ms = 0;
+            if (e == hipSuccess && a >= 0 && b >= 0)
+                e = hipEventElapsedTime(&ms, ctx->tev[(size_t)a], ctx->tev[(size_t)b]);
+            if (e != hipSuccess) {
+                rc = fail(ctx, TVS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+                break;
+            }
+            out->cand_pct[out->n_fill] = pcts[pi];
+            out->cand_sweep_ms[out->n_fill] = ms;
+            out->n_fill++;
+            if (ms < pbest) {
+                pbest = ms;
+                out->fill_wide_pct = pcts[pi];
+            }
+        }
+        ctx->fill_wide_pct = rc ? old_pct : out->fill_wide_pct;
+    }
+    dfree(ctx, &saved, (size_t)ctx->nvox);
+    ctx->tev_used = 0;
+    ctx->spans.clear();
+    ctx->timed = false;
+    if (rc) return rc;
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %.6f\n", key, out->tile_threads, out->sweep_kernel,
-                         out->ms_per_block);
+            std::fprintf(f, "%s %d %d %.6f %d\n", key, out->tile_threads, out->sweep_kernel,
+                         out->ms_per_block, out->fill_wide_pct);
             std::fclose(f);
         }
     }

@@ -145,6 +145,8 @@ struct TileFill {
     int64_t max_wgs = 0;            // > 0: at most this many workgroups (grid-stride)
     const int32_t *order = nullptr; // non-null: lane q forms history order[first + q] (the
                                     // histories of a chunk by decreasing row length)
+    int32_t room = 0;               // 1 (float chords only): the kernel held at two waves per
+                                    // SIMD, leaving room for DROP waves beside it
 };
 
 // ----------------------------------------------------------------- rows.hip

@@ -49,7 +49,7 @@ class Config(C.Structure):
                 ("chunk_histories", C.c_int64), ("hbm_budget_bytes", C.c_uint64),
                 ("device", C.c_int32), ("max_tries", C.c_int32), ("sweep_kernel", C.c_int32),
                 ("tile_threads", C.c_int32), ("time_sample", C.c_int32),
-                ("fill_wgs_per_cu", C.c_int32), ("pad", C.c_int32)]
+                ("fill_wgs_per_cu", C.c_int32), ("fill_wide_pct", C.c_int32)]
 
 
 _FP = C.POINTER(C.c_float)
@@ -106,7 +106,9 @@ class TuneResult(C.Structure):
     _fields_ = [("tile_threads", C.c_int32), ("sweep_kernel", C.c_int32),
                 ("ms_per_block", C.c_double), ("from_cache", C.c_int32),
                 ("n_candidates", C.c_int32), ("cand_threads", C.c_int32 * 8),
-                ("cand_sweep", C.c_int32 * 8), ("cand_ms", C.c_double * 8)]
+                ("cand_sweep", C.c_int32 * 8), ("cand_ms", C.c_double * 8),
+                ("fill_wide_pct", C.c_int32), ("n_fill", C.c_int32), ("cand_pct", C.c_int32 * 8),
+                ("cand_sweep_ms", C.c_double * 8)]
 
 
 class ServerConfig(C.Structure):
@@ -293,7 +295,7 @@ class Context:
     def __init__(self, grid, *, block_size=3200, path_mode="otf", mlp_step_mm=0.0,
                  mlp_log_term=True, mlp_const_power=False, chunk_histories=0,
                  hbm_budget_bytes=0, device=0, max_tries=0, sweep_kernel=0, tile_threads=0,
-                 time_sample=0, fill_wgs_per_cu=0):
+                 time_sample=0, fill_wgs_per_cu=0, fill_wide_pct=-1):
         self._L = load_library()
         self.grid = grid
         self.nvox = int(grid.nx) * int(grid.ny) * int(grid.nz)
@@ -311,6 +313,7 @@ class Context:
         cfg.tile_threads = int(tile_threads)
         cfg.time_sample = int(time_sample)
         cfg.fill_wgs_per_cu = int(fill_wgs_per_cu)
+        cfg.fill_wide_pct = int(fill_wide_pct)
         self.cfg = cfg
         h = C.c_void_p()
         g = grid_struct(grid)
@@ -419,7 +422,10 @@ class Context:
         return dict(tile_threads=r.tile_threads, sweep_kernel=r.sweep_kernel,
                     ms_per_block=r.ms_per_block, from_cache=bool(r.from_cache),
                     candidates=[dict(threads=r.cand_threads[q], sweep=r.cand_sweep[q],
-                                     ms=r.cand_ms[q]) for q in range(n)])
+                                     ms=r.cand_ms[q]) for q in range(n)],
+                    fill_wide_pct=r.fill_wide_pct,
+                    fill_candidates=[dict(pct=r.cand_pct[q], ms=r.cand_sweep_ms[q])
+                                     for q in range(r.n_fill)])
 
     def get_batch_image(self, s, out=None, stream=None):
         if out is None:
