@@ -421,7 +421,7 @@ void tvs_server_destroy(tvs_server *sv);
 /* ------------------------------------------------------------------------
  * Autotuning of the launch shape.  Times every candidate shape (threads per
  * image-tile workgroup 64 / 128 / 256, one or two launches per DROP block)
- * on the first blocks of the loaded histories, from the current image,
+ * on the first 1,024 blocks of the loaded histories, from the current image,
  * which is restored afterwards, and keeps the fastest for the context.  On
  * the fly a second stage then times whole sweeps (row formation beside the
  * chain) for the share of chunks formed at the row kernel's full occupancy

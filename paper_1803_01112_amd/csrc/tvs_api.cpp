@@ -2012,7 +2012,10 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
         }
     }
     const int64_t B = ctx->cfg.block_size;
-    const int64_t nb = std::min<int64_t>(ctx->nblocks, 48);
+    // enough blocks that the candidates' differences stand above the spread
+    // of a step's duration (48 blocks picked 64-lane tiles for the 256x256x32
+    // fixed-point store, 20 % slower per whole sweep than 128)
+    const int64_t nb = std::min<int64_t>(ctx->nblocks, 1024);
     out->fill_wide_pct = ctx->fill_wide_pct;
     if (nb == 0) {
         out->tile_threads = ctx->threads;
