@@ -186,9 +186,11 @@ def run_form(tvs, torch, w, dev_hist, x0, args, mode, K, W, n_lat, check=False, 
 
 def cpu_baseline(w, args, cores):
     """The oracle (plain float64 CPU code) on a bounded prefix of the same
-    scan, one cycle as the library runs it on the fly: rows formed (MLP +
-    walk; OpenMP over histories on all host threads, and on one thread for a
-    tenth of the prefix), then N TV steps and one DROP sweep (one thread)."""
+    scan (1M histories by default), one cycle as the library runs it on the
+    fly: rows formed (MLP + walk; OpenMP over histories on all host threads,
+    and on one thread for a tenth of the prefix), then N TV steps and one
+    DROP sweep (one thread).  The sweep alone and a cycle with the TV check
+    are timed beside it, so the phases are reported separately."""
     import oracle
     n = args.cpu_sample
     h = w.histories(count=n)
@@ -207,12 +209,23 @@ def cpu_baseline(w, args, cores):
     t0 = time.perf_counter()
     S.iterate(1, args.lam, args.N, args.alpha, seed=args.seed)
     t_cycle = time.perf_counter() - t0
+    S0 = oracle.Superiorizer(w.grid, rows, x0, args.block)
+    t0 = time.perf_counter()
+    S0.iterate(1, args.lam, 0, args.alpha, seed=args.seed)
+    t_sweep = time.perf_counter() - t0
+    Sc = oracle.Superiorizer(w.grid, rows, x0, args.block)
+    t0 = time.perf_counter()
+    Sc.iterate(1, args.lam, args.N, args.alpha, tv_check=1, seed=args.seed)
+    t_checked = time.perf_counter() - t0
     el = t_rows + t_cycle
     return dict(value=n / el, unit="histories/s", cores=cores, kind="oracle",
                 single_thread_value=n / (t_rows1 + t_cycle),
                 phases_s_per_cycle={"rows_mlp_walk_all_cores": t_rows,
                                     "rows_mlp_walk_one_thread": t_rows1,
-                                    "tv_steps_and_drop_sweep_one_thread": t_cycle},
+                                    "tv_steps_and_drop_sweep_one_thread": t_cycle,
+                                    "drop_sweep_one_thread": t_sweep,
+                                    "tv_steps_one_thread": max(t_cycle - t_sweep, 0.0),
+                                    "tv_steps_checked_one_thread": max(t_checked - t_sweep, 0.0)},
                 sample=f"first {n} histories of the {w.name} scan ({w.n_hist}); one cycle: rows "
                        f"(MLP + walk) on {cores} threads, then N={args.N} TV steps and one DROP "
                        f"sweep on one thread ({el:.1f} s); the one-thread row time is measured "
@@ -453,7 +466,7 @@ def main():
     ap.add_argument("--legs", default="check,precision,batch,serve",
                     help="further legs: check, precision, batch, serve")
     ap.add_argument("--check-steps", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=200_000)
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="skip the library's launch-shape tuner before each timed form")
