@@ -161,6 +161,33 @@ def test_resume_equals_single_call(slice64):
     assert rel_err(out[0][0], out[1][0].astype(np.float64)) <= 1e-5
 
 
+def test_row_occupancy_share_changes_no_result(slice64):
+    """On the fly the row chunks are formed by the row kernel at two
+    occupancies (two or three waves per SIMD) in a share set by
+    fill_wide_pct; only the scheduling differs, so every share gives the
+    same image bit for bit (the DROP sums are exact integers), also in a
+    batch, and the image matches the oracle."""
+    w, h, rows = slice64
+    x0 = w.initial_image()
+    imgs = {}
+    for pct in (0, 40, 100):
+        with tvs.Context(w.grid, block_size=64, mlp_step_mm=2.0, path_mode="otf",
+                         chunk_histories=6400, fill_wide_pct=pct) as ctx:
+            ctx.load_histories(h)
+            ctx.set_image(x0)
+            ctx.iterate(2, 0.05, 3, 0.75, seed=4)
+            imgs[pct] = ctx.get_image()
+            ctx.set_image(x0)
+            ctx.iterate_batch(2, [dict(lam=0.05, N=3, alpha=0.75, seed=4)])
+            imgs[(pct, "batch")] = ctx.get_batch_image(0)
+    for pct in (40, 100):
+        np.testing.assert_array_equal(imgs[pct], imgs[0])
+        np.testing.assert_array_equal(imgs[(pct, "batch")], imgs[(0, "batch")])
+    S = oracle.Superiorizer(w.grid, rows, x0, 64)
+    S.iterate(2, 0.05, 3, 0.75, seed=4)
+    assert rel_err(imgs[0], S.x) <= TOL
+
+
 def test_path_modes_agree(slice64):
     w, h, rows = slice64
     x0 = w.initial_image()
