@@ -25,9 +25,9 @@ constexpr double kE0 = 13.6;     // MeV, Highland constant
 constexpr double kX0 = 360.8;    // mm, radiation length of water
 constexpr int kThreads = 256;
 __device__ const double kZero3[3] = {0.0, 0.0, 0.0};
-// Row kernels: a budget of 2 wavefronts per SIMD (the two vertices a lane
-// evaluates side by side need ~180 VGPRs); beside the sweep's row formation
-// this leaves room on every SIMD for the DROP step's waves.
+// Row kernels: at least 2 wavefronts per SIMD (the two vertices a lane
+// evaluates side by side need many VGPRs).  The tile-list kernel takes few
+// enough to fit 3; its kRoom instance holds 2, leaving room for DROP waves.
 constexpr int kRowWaves = 2;
 // List entries staged per lane before they are written (LDS: 8 bytes each,
 // 32 KB per 256-lane workgroup with float32 chords).
