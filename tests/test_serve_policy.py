@@ -92,3 +92,26 @@ def test_shutdown_cancels_only_queued():
     ia = s.query(a)
     s.close()
     assert ia["state"] in (1, 2)
+
+
+@pytest.mark.parametrize("name,n", [("slice64", 20_000), ("vol64", 50_000), ("vol200", 30_000),
+                                    ("vol256", 20_000)])
+def test_store_estimate_bounds_the_rows(name, n):
+    """The admission estimate of a path store comes from the histories'
+    straight entry-exit lines with a margin for the most likely path's bend;
+    it must hold every row entry the oracle forms for those histories (the
+    float32 and 6-byte stores differ by 2 bytes per estimated entry), and
+    stay well below the grid-wide bound it replaced."""
+    import oracle
+    w = synth.workload(name, n_hist=n)
+    h = w.histories()
+    nnz = len(oracle.build_rows(w.grid, h, min(w.grid.vx, w.grid.vy))["idx"])
+    with tvs.Server(simulate=True, max_active=1, hbm_budget_bytes=1 << 50,
+                    sim_ns_per_history_cycle=1.0) as s:
+        f32 = s.footprint(w.grid, h, path_mode="f32")
+        q16 = s.footprint(w.grid, h, path_mode="q16")
+    est = (f32 - q16) / 2.0
+    assert nnz <= est <= 2.5 * nnz, (nnz, est)
+    span = (w.grid.nx * w.grid.vx + w.grid.ny * w.grid.vy) / min(w.grid.vx, w.grid.vy)
+    grid_wide = n * (int(0.8 * span) + w.grid.nz + 8)
+    assert est < grid_wide
