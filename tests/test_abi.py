@@ -89,6 +89,26 @@ def test_null_context_calls(lib):
     assert lib.tvs_get_stats(None, None) == tvs.TVS_EINVAL
     assert lib.tvs_iterate(None, None, 1, None) == tvs.TVS_EINVAL
     assert lib.tvs_load_histories(None, 0, None, 0, None) == tvs.TVS_EINVAL
+    assert lib.tvs_iterate_batch(None, None, 1, 1, None) == tvs.TVS_EINVAL
+    assert lib.tvs_get_batch_image(None, 0, None, 0, None) == tvs.TVS_EINVAL
+    tr = tvs.TuneResult()
+    assert lib.tvs_autotune(None, 1e-4, None, C.byref(tr), None) == tvs.TVS_EINVAL
+    br = tvs.BatchTuneResult()
+    assert lib.tvs_autotune_batch(None, None, 1, None, C.byref(br), None) == tvs.TVS_EINVAL
+    hp = tvs.HullParams()
+    assert lib.tvs_hull_detect(None, C.byref(hp), None, 0, None) == tvs.TVS_EINVAL
+    prm = tvs.FbpParams(90, 2, 0.0, 1, 0)
+    assert lib.tvs_initial_fbp_noalloc(None, C.byref(prm), None, 0, None) == tvs.TVS_EINVAL
+
+
+def test_config_carries_the_row_occupancy_share(lib):
+    """The share of on-the-fly row chunks formed at full occupancy is a
+    config field: the default asks for the library's choice (< 0)."""
+    cfg = tvs.default_config()
+    assert cfg.fill_wide_pct < 0
+    assert C.sizeof(tvs.Config) == C.sizeof(cfg)
+    r = tvs.TuneResult()
+    assert r.n_fill == 0 and len(r.cand_pct) == 8
 
 
 def test_output_buffers_checked_before_the_call():
