@@ -482,7 +482,8 @@ def main():
     ap.add_argument("--serve-capacity", type=float, default=0.0,
                     help="serial capacity in history-cycles/s (skips the serial pass)")
     ap.add_argument("--fbp", action="store_true",
-                    help="also time the initial iterate (FBP + median) of all histories")
+                    help="also time the initial iterate (FBP + median) and hull detection of "
+                         "all histories")
     ap.add_argument("--precision-hist", type=int, default=3_750_000)
     ap.add_argument("--precision-cycles", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -595,9 +596,18 @@ def main():
             t0 = time.perf_counter()
             ctx.initial_fbp(w.n_angles, median_radius=2)
             tms.append(time.perf_counter() - t0)
+        # hull detection (space modelling on the same histories, every one
+        # of which crosses the object), returned to the host
+        hms = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hull = ctx.hull_detect(wepl_in_mm=1.0, min_in=1)
+            hms.append(time.perf_counter() - t0)
         ctx.close()
         fbp = dict(ms=1e3 * min(tms), unit="ms per initial iterate", histories=H,
-                   n_angles=w.n_angles, median_radius=2)
+                   n_angles=w.n_angles, median_radius=2,
+                   hull_ms=1e3 * min(hms), hull_voxels=int(hull.sum()))
         log(f"fbp: {fbp}")
         del fbp_h
     del dev
