@@ -177,7 +177,9 @@ struct Emit {
     uint32_t qshift = 31;        // kTiled, fixed-point chords: tag bit of the code's bit 16
     double maxc = 0.0;           // kSeg: longest entry of the row
     uint32_t *in_cnt = nullptr;  // kHull: this line counts (space modelling) into in_cnt,
-    uint32_t *out_cnt = nullptr; //        carves (space carving) into out_cnt
+    uint32_t *out_cnt = nullptr; //        carves (space carving) into out_cnt,
+    uint32_t in_sat = 0;         //        each count only up to the value past which no
+    uint32_t out_sat = 0;        //        further line changes the voxel's decision
     uint32_t *btc = nullptr;     // kSeg: list lengths of this row's block
     uint64_t *segtab = nullptr;  // kSeg: (tile, place) of this row's segments
     const int64_t *segdst = nullptr;  // kTiled: first entry of this row's segments
@@ -218,8 +220,15 @@ struct Emit {
     {
         if (cur < 0) return;
         if constexpr (MODE == kHull) {
-            if (in_cnt) atomicAdd(in_cnt + cur, 1u);
-            if (out_cnt) atomicAdd(out_cnt + cur, 1u);
+            // a count read below its true value (another line's add not yet
+            // seen) only costs an add; one at or past the saturation value
+            // has reached it for good (counts only grow)
+            if (in_cnt && __hip_atomic_load(in_cnt + cur, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) < in_sat)
+                atomicAdd(in_cnt + cur, 1u);
+            if (out_cnt && __hip_atomic_load(out_cnt + cur, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) < out_sat)
+                atomicAdd(out_cnt + cur, 1u);
             cur = -1;
             cur_len = 0.0;
             n++;
@@ -701,10 +710,11 @@ k_validate(HistDev H, int64_t n, double step, uint32_t *bad, uint32_t *jmax)
 // point, walked like a row segment; a line whose WEPL reaches wepl_in counts
 // its voxels (space modelling), one whose WEPL is below wepl_out carves them
 // (space carving).  One lane per history; the counters are in the tiled
-// layout.
+// layout and saturate at in_sat / out_sat (min_in and max_out + 1): past
+// them no further line changes a decision, and most adds are skipped.
 __global__ void __launch_bounds__(kThreads)
 k_hull_counts(GridDev g, HistDev H, int64_t n, double wepl_in, double wepl_out, uint32_t *in_cnt,
-              uint32_t *out_cnt)
+              uint32_t *out_cnt, uint32_t in_sat, uint32_t out_sat)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
@@ -719,6 +729,8 @@ k_hull_counts(GridDev g, HistDev H, int64_t n, double wepl_in, double wepl_out, 
     Emit<kHull, float> e;
     e.in_cnt = in ? in_cnt : nullptr;
     e.out_cnt = out ? out_cnt : nullptr;
+    e.in_sat = in_sat;
+    e.out_sat = out_sat;
     walk_segment<kHull, float>(g, p0, p1, g0, g1, e);
     e.flush();
 }
@@ -906,11 +918,12 @@ hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *b
 
 hipError_t launch_hull_counts(const GridDev &g, const HistDev &h, int64_t n, double wepl_in,
                               double wepl_out, uint32_t *in_cnt, uint32_t *out_cnt,
-                              hipStream_t stream)
+                              uint32_t in_sat, uint32_t out_sat, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_hull_counts, dim3((unsigned)((n + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, stream, g, h, n, wepl_in, wepl_out, in_cnt, out_cnt);
+                       dim3(kThreads), 0, stream, g, h, n, wepl_in, wepl_out, in_cnt, out_cnt,
+                       in_sat, out_sat);
     return hipGetLastError();
 }
 

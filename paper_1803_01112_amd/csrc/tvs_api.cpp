@@ -1441,7 +1441,8 @@ int tvs_hull_detect(tvs_ctx *ctx, const tvs_hull_params *p, uint8_t *hull, int o
     hipError_t e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * 2 * ctx->nvox, st);
     if (e == hipSuccess)
         e = tvs::launch_hull_counts(ctx->gd, hist_dev(ctx), ctx->nh, p->wepl_in_mm, p->wepl_out_mm,
-                                    cnt, cnt + ctx->nvox, st);
+                                    cnt, cnt + ctx->nvox, (uint32_t)p->min_in,
+                                    (uint32_t)p->max_out + 1u, st);
     if (e == hipSuccess)
         e = tvs::launch_hull_decide(ctx->gd, cnt, cnt + ctx->nvox, (uint32_t)p->min_in,
                                     (uint32_t)p->max_out, hd, p->mask_image ? ctx->x : nullptr, st);

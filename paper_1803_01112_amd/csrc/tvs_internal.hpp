@@ -187,11 +187,12 @@ hipError_t launch_validate(const HistDev &h, int64_t n, double step, uint32_t *b
                            uint32_t *jmax, hipStream_t stream);
 // Hull detection (straight entry-exit lines): in_cnt / out_cnt (tiled
 // layout, cleared by the caller) count the lines of WEPL >= wepl_in /
-// < wepl_out through every voxel; decide writes hull (x-fastest uint8) and,
-// with mask, zeroes the image outside the hull.
+// < wepl_out through every voxel, each up to in_sat / out_sat (past which no
+// decision changes); decide writes hull (x-fastest uint8) and, with mask,
+// zeroes the image outside the hull.
 hipError_t launch_hull_counts(const GridDev &g, const HistDev &h, int64_t n, double wepl_in,
                               double wepl_out, uint32_t *in_cnt, uint32_t *out_cnt,
-                              hipStream_t stream);
+                              uint32_t in_sat, uint32_t out_sat, hipStream_t stream);
 hipError_t launch_hull_decide(const GridDev &g, const uint32_t *in_cnt, const uint32_t *out_cnt,
                               uint32_t min_in, uint32_t max_out, uint8_t *hull, double *mask,
                               hipStream_t stream);
