@@ -28,7 +28,12 @@
  *   - the perturbation vector v = -grad(phi)/||grad(phi)|| (Appendix A);
  *   - the NTVS cycle with and without the TV-reduction check (Appendix C),
  *     the OTVS cycle (Appendix B) and the decoupled schedule proposed in
- *     Section VI (beta = alpha^n gamma^k).
+ *     Section VI (beta = alpha^n gamma^k);
+ *   - the front end the paper cites: an initial iterate by parallel-beam
+ *     filtered backprojection of the binned straight entry-exit lines with
+ *     the in-slice median of radius 2 (Section V-A), and hull detection by
+ *     space modelling and space carving on those lines (the preprocessing
+ *     of Section III-D).
  *
  * Parity pins live in tests/ (closed forms, invariants, brute force).
  */
