@@ -1969,6 +1969,46 @@ int tvs_get_batch_image(tvs_ctx *ctx, int32_t s, float *out, int on_device, void
     return TVS_OK;
 }
 
+extern "C++" {
+
+// Launch-shape cache of the tuners: one line per measurement, "key values",
+// the key a whitespace-free description of the device, grid, history count,
+// B and path mode (plus the tuner's own tag); the last matching line wins.
+static std::string tune_key(const tvs_ctx *ctx, const hipDeviceProp_t &prop, const char *tag)
+{
+    char key[512];
+    std::snprintf(key, sizeof(key), "%s|%dx%dx%d|%.6gx%.6gx%.6g|H%lld|B%d|P%d%s", prop.gcnArchName,
+                  ctx->grid.nx, ctx->grid.ny, ctx->grid.nz, ctx->grid.vx, ctx->grid.vy,
+                  ctx->grid.vz, (long long)ctx->nh, ctx->cfg.block_size, ctx->cfg.path_mode, tag);
+    return key;
+}
+
+// Calls fn(values) for every line of the cache file whose key is `key`.
+template <typename F>
+static void cache_scan(const char *path, const std::string &key, F fn)
+{
+    FILE *f = path ? std::fopen(path, "r") : nullptr;
+    if (!f) return;
+    char line[1024];
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[512];
+        int used = 0;
+        if (std::sscanf(line, "%511s%n", k, &used) == 1 && key == k) fn(line + used);
+    }
+    std::fclose(f);
+}
+
+static void cache_append(const char *path, const std::string &key, const std::string &values)
+{
+    if (!path) return;
+    if (FILE *f = std::fopen(path, "a")) {
+        std::fprintf(f, "%s %s\n", key.c_str(), values.c_str());
+        std::fclose(f);
+    }
+}
+
+}  // extern "C++"
+
 int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_result *out,
                  void *stream)
 {
@@ -1981,30 +2021,21 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
     hipStream_t st = pick(ctx, stream);
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, ctx->cfg.device));
-    char key[512];
-    std::snprintf(key, sizeof(key), "%s|%dx%dx%d|%.6gx%.6gx%.6g|H%lld|B%d|P%d", prop.gcnArchName,
-                  ctx->grid.nx, ctx->grid.ny, ctx->grid.nz, ctx->grid.vx, ctx->grid.vy,
-                  ctx->grid.vz, (long long)ctx->nh, ctx->cfg.block_size, ctx->cfg.path_mode);
+    const std::string key = tune_key(ctx, prop, "");
     if (cache_path) {
-        if (FILE *f = std::fopen(cache_path, "r")) {
-            char line[1024];
-            while (std::fgets(line, sizeof(line), f)) {
-                char k[512];
-                int th = 0, sw = 0, pct = -1;
-                double ms = 0;
-                const int got = std::sscanf(line, "%511s %d %d %lf %d", k, &th, &sw, &ms, &pct);
-                if (got >= 4 && std::strcmp(k, key) == 0 && (th == 64 || th == 128 || th == 256) &&
-                    (sw == 1 || sw == 2)) {
-                    out->tile_threads = th;
-                    out->sweep_kernel = sw;
-                    out->ms_per_block = ms;
-                    out->fill_wide_pct = (got == 5 && pct >= 0 && pct <= 100) ? pct
-                                                                               : ctx->fill_wide_pct;
-                    out->from_cache = 1;
-                }
+        cache_scan(cache_path, key, [&](const char *v) {
+            int th = 0, sw = 0, pct = -1;
+            double ms = 0;
+            const int got = std::sscanf(v, "%d %d %lf %d", &th, &sw, &ms, &pct);
+            if (got >= 3 && (th == 64 || th == 128 || th == 256) && (sw == 1 || sw == 2)) {
+                out->tile_threads = th;
+                out->sweep_kernel = sw;
+                out->ms_per_block = ms;
+                out->fill_wide_pct = (got == 4 && pct >= 0 && pct <= 100) ? pct
+                                                                           : ctx->fill_wide_pct;
+                out->from_cache = 1;
             }
-            std::fclose(f);
-        }
+        });
         if (out->from_cache) {
             ctx->threads = out->tile_threads;
             ctx->split = out->sweep_kernel == 2 ? 1 : 0;
@@ -2126,13 +2157,10 @@ int tvs_autotune(tvs_ctx *ctx, double lambda, const char *cache_path, tvs_tune_r
     ctx->spans.clear();
     ctx->timed = false;
     if (rc) return rc;
-    if (cache_path) {
-        if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %.6f %d\n", key, out->tile_threads, out->sweep_kernel,
-                         out->ms_per_block, out->fill_wide_pct);
-            std::fclose(f);
-        }
-    }
+    char vals[128];
+    std::snprintf(vals, sizeof(vals), "%d %d %.6f %d", out->tile_threads, out->sweep_kernel,
+                  out->ms_per_block, out->fill_wide_pct);
+    cache_append(cache_path, key, vals);
     return TVS_OK;
 }
 
@@ -2153,27 +2181,18 @@ int tvs_autotune_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, const char 
     hipStream_t st = pick(ctx, stream);
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, ctx->cfg.device));
-    char key[512];
-    std::snprintf(key, sizeof(key), "%s|%dx%dx%d|%.6gx%.6gx%.6g|H%lld|B%d|P%d|S%d", prop.gcnArchName,
-                  ctx->grid.nx, ctx->grid.ny, ctx->grid.nz, ctx->grid.vx, ctx->grid.vy,
-                  ctx->grid.vz, (long long)ctx->nh, ctx->cfg.block_size, ctx->cfg.path_mode, S);
+    const std::string key = tune_key(ctx, prop, ("|S" + std::to_string(S)).c_str());
     if (cache_path) {
-        if (FILE *f = std::fopen(cache_path, "r")) {
-            char line[1024];
-            while (std::fgets(line, sizeof(line), f)) {
-                char k[512];
-                int th = 0, gp = 0;
-                double ms = 0;
-                if (std::sscanf(line, "%511s %d %d %lf", k, &th, &gp, &ms) == 4 &&
-                    std::strcmp(k, key) == 0 && tvs::batch_shape_ok(th, gp)) {
-                    out->threads = th;
-                    out->group = gp;
-                    out->ms_per_block = ms;
-                    out->from_cache = 1;
-                }
+        cache_scan(cache_path, key, [&](const char *v) {
+            int th = 0, gp = 0;
+            double ms = 0;
+            if (std::sscanf(v, "%d %d %lf", &th, &gp, &ms) == 3 && tvs::batch_shape_ok(th, gp)) {
+                out->threads = th;
+                out->group = gp;
+                out->ms_per_block = ms;
+                out->from_cache = 1;
             }
-            std::fclose(f);
-        }
+        });
         if (out->from_cache) {
             ctx->bthreads = out->threads;
             ctx->bgroup = out->group;
@@ -2272,12 +2291,9 @@ int tvs_autotune_batch(tvs_ctx *ctx, const tvs_params *p, int32_t S, const char 
     ctx->bgroup = out->group;
     rc = check_flags(ctx, st);
     if (rc) return rc;
-    if (cache_path) {
-        if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %.6f\n", key, out->threads, out->group, out->ms_per_block);
-            std::fclose(f);
-        }
-    }
+    char vals[96];
+    std::snprintf(vals, sizeof(vals), "%d %d %.6f", out->threads, out->group, out->ms_per_block);
+    cache_append(cache_path, key, vals);
     return TVS_OK;
 }
 
